@@ -1,0 +1,28 @@
+"""Plain FP64 CPU oracle for the randomized LU decomposition (Shabat et al.,
+arXiv 1310.7202, Section 4, Algorithm 4.1).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import anything from this package.
+The product path (the HIP library and its Python binding) never calls it and
+shares no code with it: no kernels, no helpers, no constants.
+
+Every function is written to be read against the paper: no blocking, no
+fusion, no reordering beyond what the algorithm states.  Floating point is
+IEEE binary64 throughout (NumPy / LAPACK via NumPy and SciPy).
+
+Pinned by (see ``tests/test_oracle_*.py``):
+  * ``rlu.randomized_lu``      -- exact rank-k reconstruction, Eckart-Young
+    lower bound, Theorem 4.1 upper bound, the projection identity of the
+    proof of Theorem 4.1, oversampling invariance under partial pivoting,
+    LAPACK getrf special cases, SciPy/NumPy least squares, full-rank
+    reconstruction, and exact-rational Schur-complement brute force.
+  * ``rlu.lu_partial_pivot``   -- LAPACK getrf (SciPy) and the closed-form
+    block elimination, in exact rational arithmetic on tiny inputs.
+  * ``rlu.lu_col_pivot``       -- LAPACK getrf of the transpose (pivots) and
+    the closed-form Schur complement.
+  * ``bounds.xi``              -- Table 4.1 of the paper, 9 of 9 rows.
+  * ``philox.philox4x32_10``   -- Random123 known-answer vectors.
+  * ``philox.gaussian_matrix`` -- Box-Muller closed form on fixed uniforms and
+    moment / Kolmogorov-Smirnov checks.
+Parity unpinned: nothing in this package (every function has a pin above).
+"""

@@ -1,0 +1,269 @@
+"""FP64 CPU oracle of Algorithm 4.1 (randomized LU) of Shabat et al.,
+arXiv 1310.7202, Section 4.
+
+TEST INFRASTRUCTURE ONLY: see the package docstring for who may call this.
+
+Conventions (the paper uses permutation matrices, Section 3.1, Eq. 3.1; this
+oracle uses 0-based index vectors with the same meaning):
+  * ``p`` (length m):  (P A)(i, :) = A(p[i], :)
+  * ``q`` (length n):  (A Q)(:, j) = A(:, q[j])
+  * ``ipiv[j]`` / ``qpiv[j]``: LAPACK-style swap sequence -- at step j the
+    row (column) at position j was exchanged with the one at position
+    ipiv[j] (qpiv[j]).
+
+Readings of the paper taken here (each is listed in the design doc as well):
+  * Step 3 uses LU with partial pivoting (the Remark after Algorithm 4.1
+    allows it in place of RRLU), factoring all l columns of Y; Step 4 then
+    keeps the first k columns of L_y.
+  * Ties in a pivot search go to the lowest current position (LAPACK i?amax).
+  * A zero pivot (whole active column zero) is recorded in ``info`` as the
+    1-based step, and that step's scaling and update are skipped, as in
+    LAPACK getf2; the factorization continues.
+  * Step 5's pseudo-inverse is applied as a least-squares solve through a
+    Householder QR of L_y.  The paper's Remark forms (L_y^T L_y)^{-1} L_y^T;
+    the two agree in exact arithmetic and the QR route is the more accurate
+    reference.
+  * Step 6 is row-by-row elimination with column pivoting; L_b is unit lower
+    triangular and U_b carries the pivots.  If a pivot is zero, column j of
+    L_b below the diagonal is left zero.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+
+def sketch(A: np.ndarray, G: np.ndarray) -> np.ndarray:
+    """Step 2 of Algorithm 4.1: Y = A G (a plain matrix product)."""
+    return A @ G
+
+
+def lu_partial_pivot(Y: np.ndarray):
+    """Step 3 of Algorithm 4.1 with partial pivoting (Remark after Alg. 4.1).
+
+    Unblocked right-looking Gaussian elimination on the m x w matrix Y
+    (m >= w): at step j the pivot is the entry of largest magnitude in the
+    active part of column j (lowest position on ties); the two full rows are
+    exchanged; the multipliers are the active column divided by the pivot;
+    the trailing block receives the rank-one update.
+
+    Returns (LU, ipiv, p, info, diag) where LU packs the unit-lower factor
+    below the diagonal and U on and above it (positions, i.e. rows of P Y),
+    and ``diag`` holds per-step pivot diagnostics used to gate pivot
+    comparisons: |pivot|, the relative gap to the runner-up, and max |Y|.
+    """
+    LU = np.array(Y, dtype=np.float64, copy=True)
+    m, w = LU.shape
+    if w > m:
+        raise ValueError("lu_partial_pivot expects a tall matrix (m >= w)")
+    ipiv = np.zeros(w, dtype=np.int64)
+    p = np.arange(m, dtype=np.int64)
+    info = 0
+    piv_abs = np.zeros(w)
+    gap = np.zeros(w)
+    ymax = float(np.max(np.abs(LU))) if LU.size else 0.0
+    for j in range(w):
+        col = np.abs(LU[j:, j])
+        r = j + int(np.argmax(col))
+        piv_abs[j] = col[r - j]
+        if col.size > 1:
+            second = np.partition(col, col.size - 2)[col.size - 2]
+            gap[j] = (piv_abs[j] - second) / piv_abs[j] if piv_abs[j] > 0 else 0.0
+        else:
+            gap[j] = 1.0
+        ipiv[j] = r
+        if r != j:
+            LU[[j, r], :] = LU[[r, j], :]
+            p[[j, r]] = p[[r, j]]
+        pivot = LU[j, j]
+        if pivot != 0.0:
+            LU[j + 1:, j] = LU[j + 1:, j] / pivot
+            LU[j + 1:, j + 1:] -= np.outer(LU[j + 1:, j], LU[j, j + 1:])
+        elif info == 0:
+            info = j + 1
+    return LU, ipiv, p, info, {"piv_abs": piv_abs, "gap": gap, "max_abs": ymax}
+
+
+def unit_lower(LU: np.ndarray, k: int) -> np.ndarray:
+    """Step 4 of Algorithm 4.1: L_y <- L_y(:, 1:k), the unit-lower part of
+    the first k columns of the packed factor."""
+    m = LU.shape[0]
+    L = np.tril(LU[:, :k], -1)
+    L[np.arange(k), np.arange(k)] = 1.0
+    return L[:m, :k]
+
+
+def pinv_apply(Ly: np.ndarray, PA: np.ndarray) -> np.ndarray:
+    """Step 5 of Algorithm 4.1: B = L_y^dagger (P A).
+
+    L_y has full column rank (unit diagonal), so its pseudo-inverse is the
+    least-squares solution operator; it is applied through the reduced
+    Householder QR  L_y = Q R:  B = R^{-1} Q^T (P A).
+    """
+    Q, R = np.linalg.qr(Ly, mode="reduced")
+    return scipy.linalg.solve_triangular(R, Q.T @ PA, lower=False)
+
+
+def lu_col_pivot(B: np.ndarray):
+    """Step 6 of Algorithm 4.1: LU of the k x n matrix B with column
+    pivoting, B Q = L_b U_b (k <= n).
+
+    Row-by-row elimination: at step j the pivot is the entry of largest
+    magnitude in the active part of row j (lowest position on ties); the two
+    full columns are exchanged; the entries of column j below the pivot are
+    divided by it to give column j of L_b, and the trailing rows receive the
+    rank-one update.  U_b is the upper-trapezoidal part of the result.
+
+    Returns (Lb, Ub, qpiv, q, info, diag).
+    """
+    W = np.array(B, dtype=np.float64, copy=True)
+    k, n = W.shape
+    if k > n:
+        raise ValueError("lu_col_pivot expects a wide matrix (k <= n)")
+    Lb = np.eye(k)
+    qpiv = np.zeros(k, dtype=np.int64)
+    q = np.arange(n, dtype=np.int64)
+    info = 0
+    piv_abs = np.zeros(k)
+    gap = np.zeros(k)
+    bmax = float(np.max(np.abs(W))) if W.size else 0.0
+    for j in range(k):
+        row = np.abs(W[j, j:])
+        c = j + int(np.argmax(row))
+        piv_abs[j] = row[c - j]
+        if row.size > 1:
+            second = np.partition(row, row.size - 2)[row.size - 2]
+            gap[j] = (piv_abs[j] - second) / piv_abs[j] if piv_abs[j] > 0 else 0.0
+        else:
+            gap[j] = 1.0
+        qpiv[j] = c
+        if c != j:
+            W[:, [j, c]] = W[:, [c, j]]
+            q[[j, c]] = q[[c, j]]
+        pivot = W[j, j]
+        if pivot != 0.0:
+            Lb[j + 1:, j] = W[j + 1:, j] / pivot
+            W[j + 1:, j:] -= np.outer(Lb[j + 1:, j], W[j, j:])
+        elif info == 0:
+            info = j + 1
+    Ub = np.triu(W)
+    return Lb, Ub, qpiv, q, info, {"piv_abs": piv_abs, "gap": gap, "max_abs": bmax}
+
+
+def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray) -> dict:
+    """Algorithm 4.1 of the paper, Steps 2-8, for a given Gaussian G (Step 1).
+
+    Inputs: A (m x n), k (target rank), l (number of sketch columns,
+    k <= l <= min(m, n)), G (n x l).  Returns a dict with the outputs
+    L (m x k unit lower trapezoidal), U (k x n upper trapezoidal), p, q and
+    the intermediates (Y, packed LU of Y, ipiv, L_y, B, L_b, qpiv, info words
+    and pivot diagnostics).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    G = np.asarray(G, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= k <= l <= min(m, n)):
+        raise ValueError("need 1 <= k <= l <= min(m, n)")
+    if G.shape != (n, l):
+        raise ValueError("G must be n x l")
+    Y = sketch(A, G)                                   # Step 2
+    LUy, ipiv, p, info_y, diag_y = lu_partial_pivot(Y)  # Step 3
+    Ly = unit_lower(LUy, k)                            # Step 4
+    B = pinv_apply(Ly, A[p, :])                        # Step 5
+    Lb, Ub, qpiv, q, info_b, diag_b = lu_col_pivot(B)  # Step 6
+    L = Ly @ Lb                                        # Step 7
+    U = Ub                                             # Step 8
+    return {
+        "L": L, "U": U, "p": p, "q": q,
+        "Y": Y, "LUy": LUy, "ipiv": ipiv, "Ly": Ly, "B": B,
+        "Lb": Lb, "Ub": Ub, "qpiv": qpiv,
+        "info": (info_y, info_b),
+        "diag_y": diag_y, "diag_b": diag_b,
+    }
+
+
+def permuted(A: np.ndarray, p: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """P A Q with the index-vector conventions of this module."""
+    return np.asarray(A)[np.ix_(p, q)]
+
+
+def spectral_norm(X: np.ndarray) -> float:
+    """Largest singular value (Section 3 notation), by a full SVD."""
+    if X.size == 0:
+        return 0.0
+    return float(np.linalg.svd(X, compute_uv=False)[0])
+
+
+def residual(A: np.ndarray, out: dict, exact: bool = True, iters: int = 60,
+             seed: int = 0) -> float:
+    """||L U - P A Q||_2 (the quantity bounded by Theorem 4.1).
+
+    ``exact`` uses a full SVD; otherwise a fixed number of power iterations
+    on the operator x -> (L U - P A Q)^T (L U - P A Q) x, never forming the
+    difference for large inputs (an estimate from below).
+    """
+    L, U, p, q = out["L"], out["U"], out["p"], out["q"]
+    if exact:
+        return spectral_norm(L @ U - permuted(A, p, q))
+    rng = np.random.default_rng(seed)
+    n = U.shape[1]
+    x = rng.standard_normal(n)
+    x /= np.linalg.norm(x)
+    qinv = np.empty_like(q)
+    qinv[q] = np.arange(q.size)
+    pinv = np.empty_like(p)
+    pinv[p] = np.arange(p.size)
+    est = 0.0
+    for _ in range(iters):
+        # y = (L U - P A Q) x
+        y = L @ (U @ x) - (A @ x[qinv])[p]
+        # z = (L U - P A Q)^T y
+        z = U.T @ (L.T @ y) - (A.T @ y[pinv])[q]
+        nz = np.linalg.norm(z)
+        if nz == 0.0:
+            return 0.0
+        est = np.sqrt(nz)
+        x = z / nz
+    return float(est)
+
+
+def relative_residual(A: np.ndarray, out: dict, exact: bool = True) -> float:
+    """Relative error of Section 5.1: ||L U - P A Q||_2 / ||A||_2."""
+    den = spectral_norm(A) if exact else _power_norm(A)
+    return residual(A, out, exact=exact) / den
+
+
+def _power_norm(A: np.ndarray, iters: int = 60, seed: int = 1) -> float:
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal(A.shape[1])
+    x /= np.linalg.norm(x)
+    est = 0.0
+    for _ in range(iters):
+        z = A.T @ (A @ x)
+        nz = np.linalg.norm(z)
+        if nz == 0.0:
+            return 0.0
+        est = np.sqrt(nz)
+        x = z / nz
+    return float(est)
+
+
+def pivot_gate(diag: dict, u: float = 2.0 ** -53, gap_min: float = 1e-8,
+               mag_factor: float = 1e3) -> int:
+    """Number of leading pivot steps whose choice is numerically decided:
+    every step up to it has a relative gap to the runner-up >= gap_min and a
+    pivot magnitude >= mag_factor * u * max|input|.  Pivot sequences of two
+    correct implementations must agree on this prefix."""
+    thr = mag_factor * u * diag["max_abs"]
+    n = 0
+    for g, a in zip(diag["gap"], diag["piv_abs"]):
+        if g < gap_min or a < thr:
+            break
+        n += 1
+    return n
+
+
+def kappa(X: np.ndarray) -> float:
+    """2-norm condition number (diagnostic for the Gram route of Step 5)."""
+    s = np.linalg.svd(X, compute_uv=False)
+    return float(s[0] / s[-1]) if s[-1] > 0 else float("inf")
