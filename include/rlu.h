@@ -1,0 +1,161 @@
+/*
+ * rlu.h -- C ABI of the MI355X randomized LU library (librlu.so).
+ *
+ * Computes the randomized LU decomposition of Shabat, Shmueli, Aizenbud and
+ * Averbuch (arXiv 1310.7202), Section 4, Algorithm 4.1: for an m x n matrix A,
+ * a target rank k and a sketch width l (k <= l <= min(m, n)),
+ *
+ *   Step 1  G      <- n x l i.i.d. N(0, 1)
+ *   Step 2  Y      <- A G
+ *   Step 3  P Y    =  L_y U_y        (LU with partial pivoting; the Remark
+ *                                     after Algorithm 4.1 allows it in place
+ *                                     of a rank-revealing LU)
+ *   Step 4  L_y    <- L_y(:, 1:k)
+ *   Step 5  B      <- L_y^+ P A      (pseudo-inverse through the Gram matrix
+ *                                     L_y^T L_y, as in the Remark after
+ *                                     Algorithm 4.1)
+ *   Step 6  B Q    =  L_b U_b        (LU with column pivoting)
+ *   Step 7  L      <- L_y L_b
+ *   Step 8  U      <- U_b
+ *
+ * with ||P A Q - L U||_2 controlled by sigma_{k+1}(A) (Theorem 4.1).
+ *
+ * Conventions
+ *   - Matrices are column-major with an explicit leading dimension; indices
+ *     are 0-based.
+ *   - Every matrix, permutation and info pointer in rlu_buffers_t is a DEVICE
+ *     pointer on the handle's device.  The caller owns all of them.
+ *   - Permutations are index vectors: (P A)(i, :) = A(p[i], :) and
+ *     (A Q)(:, j) = A(:, q[j]).
+ *   - L (m x k) is unit lower trapezoidal with the unit diagonal stored;
+ *     U (k x n) is upper trapezoidal with zeros stored below the diagonal.
+ *   - All work is enqueued on the caller's stream; rlu_factor returns once the
+ *     work is enqueued.  No value is read back to the host on the way.
+ *
+ * Errors
+ *   - Argument errors return a negative status synchronously, before any
+ *     device work is enqueued.
+ *   - Data-dependent conditions never stop the path: a zero pivot (rank of
+ *     the sketch or of B below k) is reported in the device word info[0] (for
+ *     Step 3) or info[1] (for Step 6) as the 1-based step where it occurred,
+ *     0 meaning none.  The factors stay defined (see the zero-pivot rules in
+ *     the documentation of rlu_factor).
+ *   - A device-side failure of the cross-workgroup pivot exchange (it never
+ *     completes within its time limit) sets info[2] to 1; the outputs are
+ *     then undefined.  rlu_check_info maps the three words to a status.
+ *   - No exception crosses this interface.
+ *
+ * Threading: a handle may be used by one host thread at a time.
+ */
+#ifndef RLU_H
+#define RLU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RLU_OK = 0,
+  RLU_PENDING = 1,
+  RLU_WARN_ZERO_PIVOT = 2,
+  RLU_ERR_INVALID_ARG = -1,
+  RLU_ERR_OUT_OF_MEMORY = -2,
+  RLU_ERR_DEVICE = -3,
+  RLU_ERR_TOO_LARGE = -4,
+  RLU_ERR_QUEUE_FULL = -5,
+  RLU_ERR_NONFINITE = -6,
+  RLU_ERR_UNKNOWN_TICKET = -7,
+  RLU_ERR_UNSUPPORTED = -8
+} rlu_status_t;
+
+/* Storage type of A, G, L and U. */
+typedef enum { RLU_F64 = 0, RLU_F32 = 1 } rlu_dtype_t;
+
+/* Arithmetic of the two large products (Steps 2 and 5).  The pivoted LUs
+ * (Steps 3 and 6), the Gram matrix and its inverse are FP64 in every mode. */
+typedef enum {
+  RLU_PREC_FP64 = 0,       /* requires RLU_F64 storage                      */
+  RLU_PREC_FP32 = 1,       /* requires RLU_F32 storage                      */
+  RLU_PREC_MIXED_BF16 = 2, /* RLU_F32 storage; bf16 MFMA, fp32 accumulation */
+  RLU_PREC_MIXED_FP16 = 3  /* RLU_F32 storage; fp16 MFMA, fp32 accumulation */
+} rlu_precision_t;
+
+enum {
+  RLU_FLAG_CHECK_FINITE = 1u, /* reserved */
+  RLU_FLAG_DIAGNOSTICS = 2u   /* fill the optional diagnostic outputs      */
+};
+
+/* Problem description (Algorithm 4.1, Input): A is m x n, k the target rank,
+ * l the number of sketch columns.  Requires 1 <= k <= l <= min(m, n). */
+typedef struct {
+  int64_t m, n, k, l;
+  rlu_dtype_t dtype;
+  rlu_precision_t precision;
+  uint64_t seed;      /* Step 1: G from Philox4x32-10 + Box-Muller, see below */
+  const void* G;      /* optional caller G (n x l, storage dtype, device);    */
+  int64_t ldg;        /*   NULL => generated from seed                        */
+  uint32_t flags;
+} rlu_problem_t;
+
+/* Step 1 generator: key = (seed mod 2^32, seed div 2^32); element (i, j) of G
+ * has column-major index e = i + j*n and uses counter (e/2 mod 2^32,
+ * e/2 div 2^32, 0, 0); the four output words give u1 = ((x1:x0 >> 11) + 1)
+ * 2^-53 and u2 = (x3:x2 >> 11) 2^-53, and the Box-Muller pair
+ * sqrt(-2 ln u1) (cos, sin)(2 pi u2) goes to the even and odd e. */
+
+/* Inputs and outputs (Algorithm 4.1, Output), all device pointers. */
+typedef struct {
+  const void* A; int64_t lda;  /* in  m x n, lda >= m; never modified           */
+  void* L; int64_t ldl;        /* out m x k, ldl >= m: unit lower trapezoidal   */
+  void* U; int64_t ldu;        /* out k x n, ldu >= k: upper trapezoidal        */
+  int64_t* p;                  /* out length m: row permutation P               */
+  int64_t* q;                  /* out length n: column permutation Q            */
+  int32_t* info;               /* out 3 words: zero-pivot step of Step 3, of
+                                  Step 6 (1-based, 0 = none), exchange failure */
+  /* Optional diagnostics, filled only with RLU_FLAG_DIAGNOSTICS (each may be
+   * NULL).  Y and B use the storage dtype of the FP64/FP32 path (FP64 for the
+   * FP64 and mixed modes, FP32 for the FP32 mode). */
+  void* Y; int64_t ldy;        /* out m x l: the sketch A G (before Step 3)     */
+  void* B; int64_t ldb;        /* out k x n: B = L_y^+ P A (before Step 6)      */
+  int32_t* ipiv;               /* out length l: Step 3 swap sequence (LAPACK)   */
+  int32_t* qpiv;               /* out length k: Step 6 swap sequence            */
+} rlu_buffers_t;
+
+typedef struct rlu_handle_s* rlu_handle_t;
+typedef void* rlu_stream_t; /* a hipStream_t; NULL = the null stream */
+
+/* Create a handle bound to HIP device `device` (the handle caches device
+ * workspace and a second stream used to overlap independent steps). */
+rlu_status_t rlu_create(rlu_handle_t* h, int device);
+rlu_status_t rlu_destroy(rlu_handle_t h);
+
+/* Device workspace rlu_factor needs for this problem, in bytes (the handle
+ * allocates and caches it; the figure is what it will hold). */
+rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
+
+/* Algorithm 4.1, Steps 1-8, enqueued on `stream`.
+ *
+ * Zero pivots: in Step 3 the LAPACK getf2 convention holds (no scaling, no
+ * update, info[0] = first such step); in Step 6, column j of L_b below the
+ * diagonal is zero and row j of U_b is zero (info[1] = first such step).
+ * Ties in a pivot search go to the lowest current position. */
+rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
+                        const rlu_buffers_t* io, rlu_stream_t stream);
+
+/* Map the three info words (already copied to the host) to a status:
+ * RLU_ERR_DEVICE if the exchange failed, RLU_WARN_ZERO_PIVOT if a zero pivot
+ * occurred, RLU_OK otherwise. */
+rlu_status_t rlu_check_info(const int32_t info_host[3]);
+
+const char* rlu_status_string(rlu_status_t st);
+
+/* Library version string. */
+const char* rlu_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLU_H */

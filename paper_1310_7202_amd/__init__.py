@@ -1,0 +1,228 @@
+"""MI355X-native randomized LU decomposition (Shabat et al., arXiv 1310.7202,
+Section 4, Algorithm 4.1).
+
+Thin Python binding over the C ABI of ``librlu.so`` (declared in
+``include/rlu.h``): argument marshalling only.  Every step of the
+factorization runs in the library's HIP kernels; torch provides device
+memory and streams.  If the library has not been built, every call raises
+(there is no other compute path).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+__all__ = ["RluError", "Handle", "factor", "lib", "status_string", "LIB_PATH",
+           "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
+           "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librlu.so")
+
+F64, F32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_FP16 = 0, 1, 2, 3
+FLAG_CHECK_FINITE, FLAG_DIAGNOSTICS = 1, 2
+
+STATUS = {
+    0: "RLU_OK", 1: "RLU_PENDING", 2: "RLU_WARN_ZERO_PIVOT", -1: "RLU_ERR_INVALID_ARG",
+    -2: "RLU_ERR_OUT_OF_MEMORY", -3: "RLU_ERR_DEVICE", -4: "RLU_ERR_TOO_LARGE",
+    -5: "RLU_ERR_QUEUE_FULL", -6: "RLU_ERR_NONFINITE", -7: "RLU_ERR_UNKNOWN_TICKET",
+    -8: "RLU_ERR_UNSUPPORTED",
+}
+
+# every function include/rlu.h declares
+EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
+                    "rlu_check_info", "rlu_status_string", "rlu_version"]
+
+
+class RluError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS.get(status, status)} ({status_string(status)})")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("l", ctypes.c_int64), ("dtype", ctypes.c_int), ("precision", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("G", ctypes.c_void_p), ("ldg", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
+class Buffers(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("info", ctypes.c_void_p),
+                ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("ipiv", ctypes.c_void_p), ("qpiv", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librlu.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1310_7202_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.rlu_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]
+        L.rlu_destroy.argtypes = [ctypes.c_void_p]
+        L.rlu_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
+        L.rlu_factor.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                 ctypes.POINTER(Buffers), ctypes.c_void_p]
+        L.rlu_check_info.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        L.rlu_status_string.argtypes = [ctypes.c_int]
+        L.rlu_status_string.restype = ctypes.c_char_p
+        L.rlu_version.restype = ctypes.c_char_p
+        for name in ("rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
+                     "rlu_check_info"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def status_string(st: int) -> str:
+    try:
+        return lib().rlu_status_string(st).decode()
+    except RuntimeError:
+        return STATUS.get(st, "unknown")
+
+
+def _check(st: int, where: str):
+    if st < 0:
+        raise RluError(st, where)
+    return st
+
+
+class Handle:
+    """A library handle bound to one device (caches device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().rlu_create(ctypes.byref(self._h), device), "rlu_create")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().rlu_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ptr(self):
+        return self._h
+
+
+_handles: dict = {}
+
+
+def default_handle(device: int = 0) -> Handle:
+    h = _handles.get(device)
+    if h is None:
+        h = _handles[device] = Handle(device)
+    return h
+
+
+def workspace_size(m, n, k, l, dtype=F64, precision=PREC_FP64, with_g=False) -> int:
+    pb = Problem(m, n, k, l, dtype, precision, 0, None, 0, 0)
+    if with_g:
+        pb.G = 1
+        pb.ldg = n
+    out = ctypes.c_size_t()
+    _check(lib().rlu_workspace_size(ctypes.byref(pb), ctypes.byref(out)), "rlu_workspace_size")
+    return out.value
+
+
+@dataclass
+class Factors:
+    L: "object"
+    U: "object"
+    p: "object"
+    q: "object"
+    info: "object"
+    Y: "object" = None
+    B: "object" = None
+    ipiv: "object" = None
+    qpiv: "object" = None
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
+           diagnostics: bool = False, handle: Handle | None = None, stream=None,
+           out: Factors | None = None) -> Factors:
+    """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
+    float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
+    tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
+    p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
+    current torch stream by default) and not synchronized."""
+    import torch
+
+    if A.dim() != 2 or not A.is_cuda:
+        raise ValueError("A must be a 2-D device tensor")
+    m, n = A.shape
+    if A.stride(0) != 1:
+        raise ValueError("A must be column-major (stride(0) == 1)")
+    lda = max(A.stride(1), m) if n > 1 else m
+    if A.dtype == torch.float64:
+        dtype = F64
+        prec = PREC_FP64 if precision is None else precision
+    elif A.dtype == torch.float32:
+        dtype = F32
+        prec = PREC_FP32 if precision is None else precision
+    else:
+        raise ValueError("A must be float64 or float32")
+    dev = A.device
+    h = handle or default_handle(dev.index or 0)
+    if out is None:
+        L = torch.empty((k, m), dtype=A.dtype, device=dev).t()
+        U = torch.empty((n, k), dtype=A.dtype, device=dev).t()
+        p = torch.empty(m, dtype=torch.int64, device=dev)
+        q = torch.empty(n, dtype=torch.int64, device=dev)
+        info = torch.empty(3, dtype=torch.int32, device=dev)
+        out = Factors(L, U, p, q, info)
+        if diagnostics:
+            ytype = torch.float32 if prec == PREC_FP32 else torch.float64
+            out.Y = torch.empty((l, m), dtype=ytype, device=dev).t()
+            out.B = torch.empty((n, k), dtype=ytype, device=dev).t()
+            out.ipiv = torch.empty(l, dtype=torch.int32, device=dev)
+            out.qpiv = torch.empty(k, dtype=torch.int32, device=dev)
+    pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, FLAG_DIAGNOSTICS if diagnostics else 0)
+    if G is not None:
+        if G.shape != (n, l) or G.stride(0) != 1 or G.dtype != A.dtype:
+            raise ValueError("G must be an n x l column-major tensor of A's dtype")
+        pb.G = G.data_ptr()
+        pb.ldg = max(G.stride(1), n) if l > 1 else n
+    io = Buffers(A.data_ptr(), lda,
+                 out.L.data_ptr(), max(out.L.stride(1), m) if k > 1 else m,
+                 out.U.data_ptr(), max(out.U.stride(1), k) if n > 1 else k,
+                 out.p.data_ptr(), out.q.data_ptr(), out.info.data_ptr(),
+                 out.Y.data_ptr() if out.Y is not None else None,
+                 (max(out.Y.stride(1), m) if l > 1 else m) if out.Y is not None else 0,
+                 out.B.data_ptr() if out.B is not None else None,
+                 (max(out.B.stride(1), k) if n > 1 else k) if out.B is not None else 0,
+                 out.ipiv.data_ptr() if out.ipiv is not None else None,
+                 out.qpiv.data_ptr() if out.qpiv is not None else None)
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),
+                          ctypes.c_void_p(s.cuda_stream))
+    _check(st, "rlu_factor")
+    return out
+
+
+def check_info(info) -> int:
+    """Status for the three info words (host ints or a tensor)."""
+    vals = [int(x) for x in (info.tolist() if hasattr(info, "tolist") else info)]
+    arr = (ctypes.c_int32 * 3)(*vals)
+    return lib().rlu_check_info(arr)

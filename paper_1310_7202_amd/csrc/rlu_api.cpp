@@ -1,0 +1,375 @@
+// C ABI of librlu: argument validation, workspace planning and the launch
+// sequence of Algorithm 4.1 (Shabat et al., Section 4) on the caller's stream.
+//
+// Launch sequence of rlu_factor (FP64 path):
+//   Step 1  gaussian            G (n x l) from the seed, unless given
+//   Step 2  gemm                Y = A G
+//   Step 3  panel_lu(Y)         packed LU of Y in place, rows never moved
+//   Step 5  gemm (split-K)      S = Lv^T Lv        (Gram matrix)
+//           spd_inverse         S <- S^{-1}        on a second stream, while
+//           gemm                C = Lv^T A         runs on the caller's stream
+//           gemm                B = S^{-1} C
+//   Step 6  panel_lu(B^T)       packed LU of B^T in the storage of B
+//   Step 8  build_u             U = U_b  (k x n, positions)
+//   Step 7  build_lb, gemm      L = P (Lv L_b)     (rows scattered to positions)
+// Lv is the unit-lower factor of Step 3 in original row order; P enters
+// only through the row positions, never through a gather of A (Step 5:
+// L_y^T P A = Lv^T A).
+#include "../../include/rlu.h"
+#include "rlu_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+struct rlu_handle_s {
+  int device = 0;
+  int cus = 256;
+  hipStream_t side = nullptr;    // second stream for the Gram inverse
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace {
+
+using namespace rlu;
+
+constexpr long long kTimeoutTicks = 200LL * 1000 * 1000;  // 2 s of the 100 MHz clock
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t G = 0, Y = 0, part = 0, S = 0, C = 0, Bst = 0, Lb = 0;
+  size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
+  size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0, flags = 0, xch = 0;
+  size_t total = 0;
+  int ksplit_gram = 1, ksplit_y = 1;
+  PanelPlan py{}, pb{};
+};
+
+// Split K of a GEMM when its output alone cannot fill the device.
+int suggest_ksplit(int64_t M, int64_t N, int64_t K, int cus) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int ks = 1;
+  while (tiles * ks * 2 <= (int64_t)cus * 2 && K / (ks * 2) >= 512 && ks < 32) ks *= 2;
+  return ks;
+}
+
+bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
+  const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
+  size_t off = 0;
+  auto take = [&](size_t& slot, size_t bytes) {
+    slot = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+  };
+  const size_t d = sizeof(double);
+  take(L.G, pb.G ? 0 : (size_t)n * l * d);
+  take(L.Y, (size_t)m * l * d);
+  L.ksplit_gram = suggest_ksplit(k, k, m, cus);
+  L.ksplit_y = 1;
+  take(L.part, gemm_partial_elems(k, k, L.ksplit_gram) * d);
+  take(L.S, (size_t)k * k * d);
+  take(L.C, (size_t)k * n * d);
+  take(L.Bst, (size_t)k * n * d);
+  take(L.Lb, (size_t)k * k * d);
+  take(L.pos_y, (size_t)m * 4);
+  take(L.rstep_y, (size_t)m * 4);
+  take(L.piv_y, (size_t)l * 4);
+  take(L.ipiv_y, (size_t)l * 4);
+  take(L.pos_b, (size_t)n * 4);
+  take(L.rstep_b, (size_t)n * 4);
+  take(L.piv_b, (size_t)k * 4);
+  take(L.ipiv_b, (size_t)k * 4);
+  take(L.flags, 64);
+  L.py = panel_plan((int)m, (int)l, cus, 1);
+  L.pb = panel_plan((int)n, (int)k, cus, 1);
+  if (!L.py.ok || !L.pb.ok) return false;
+  take(L.xch, std::max(L.py.xch_bytes, L.pb.xch_bytes));
+  L.total = off;
+  return true;
+}
+
+rlu_status_t validate(const rlu_problem_t* pb) {
+  if (!pb) return RLU_ERR_INVALID_ARG;
+  if (pb->m < 1 || pb->n < 1 || pb->k < 1 || pb->l < pb->k) return RLU_ERR_INVALID_ARG;
+  if (pb->l > std::min(pb->m, pb->n)) return RLU_ERR_INVALID_ARG;
+  if (pb->m >= (1LL << 31) || pb->n >= (1LL << 31)) return RLU_ERR_TOO_LARGE;
+  if (pb->dtype != RLU_F64 && pb->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
+  switch (pb->precision) {
+    case RLU_PREC_FP64:
+      if (pb->dtype != RLU_F64) return RLU_ERR_INVALID_ARG;
+      break;
+    case RLU_PREC_FP32:
+    case RLU_PREC_MIXED_BF16:
+    case RLU_PREC_MIXED_FP16:
+      if (pb->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
+      return RLU_ERR_UNSUPPORTED;
+    default:
+      return RLU_ERR_INVALID_ARG;
+  }
+  if (pb->G && pb->ldg < pb->n) return RLU_ERR_INVALID_ARG;
+  if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS))
+    return RLU_ERR_INVALID_ARG;
+  if (!spd_inverse_supported(pb->k)) return RLU_ERR_UNSUPPORTED;
+  return RLU_OK;
+}
+
+rlu_status_t validate_io(const rlu_problem_t* pb, const rlu_buffers_t* io) {
+  if (!io) return RLU_ERR_INVALID_ARG;
+  if (!io->A || !io->L || !io->U || !io->p || !io->q || !io->info) return RLU_ERR_INVALID_ARG;
+  if (io->lda < pb->m || io->ldl < pb->m || io->ldu < pb->k) return RLU_ERR_INVALID_ARG;
+  if (pb->flags & RLU_FLAG_DIAGNOSTICS) {
+    if (io->Y && io->ldy < pb->m) return RLU_ERR_INVALID_ARG;
+    if (io->B && io->ldb < pb->k) return RLU_ERR_INVALID_ARG;
+  }
+  return RLU_OK;
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) {                            \
+      if (getenv("RLU_LOG"))                           \
+        fprintf(stderr, "librlu: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
+      return RLU_ERR_DEVICE;                           \
+    }                                                  \
+  } while (0)
+
+rlu_status_t ensure_ws(rlu_handle_s* h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return RLU_OK;
+  if (h->ws) {
+    if (hipFree(h->ws) != hipSuccess) return RLU_ERR_DEVICE;
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  if (hipMalloc(&h->ws, bytes) != hipSuccess) {
+    h->ws = nullptr;
+    return RLU_ERR_OUT_OF_MEMORY;
+  }
+  h->ws_bytes = bytes;
+  return RLU_OK;
+}
+
+template <typename P>
+P* at(void* base, size_t off) { return (P*)((char*)base + off); }
+
+rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buffers_t& io,
+                         hipStream_t s, const Layout& Ly) {
+  const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
+  void* ws = h->ws;
+  double* Y = at<double>(ws, Ly.Y);
+  double* S = at<double>(ws, Ly.S);
+  double* C = at<double>(ws, Ly.C);
+  double* Bst = at<double>(ws, Ly.Bst);
+  double* Lb = at<double>(ws, Ly.Lb);
+  int* pos_y = at<int>(ws, Ly.pos_y);
+  int* rstep_y = at<int>(ws, Ly.rstep_y);
+  int* piv_y = at<int>(ws, Ly.piv_y);
+  int* ipiv_y = at<int>(ws, Ly.ipiv_y);
+  int* pos_b = at<int>(ws, Ly.pos_b);
+  int* rstep_b = at<int>(ws, Ly.rstep_b);
+  int* piv_b = at<int>(ws, Ly.piv_b);
+  int* ipiv_b = at<int>(ws, Ly.ipiv_b);
+  int* flags = at<int>(ws, Ly.flags);  // [0] info_y, [1] info_b, [2] exchange failure
+  void* xch = at<void>(ws, Ly.xch);
+  const bool diag = (pb.flags & RLU_FLAG_DIAGNOSTICS) != 0;
+
+  HIP_TRY(launch_fill_u32((uint32_t*)flags, 16, 0u, s));
+
+  // Step 1
+  const double* G = (const double*)pb.G;
+  int64_t ldg = pb.ldg;
+  if (!G) {
+    double* Gw = at<double>(ws, Ly.G);
+    HIP_TRY(launch_gaussian<double>(Gw, n, n, l, pb.seed, s));
+    G = Gw;
+    ldg = n;
+  }
+  // Step 2: Y = A G
+  {
+    GemmDesc d{};
+    d.M = m; d.N = l; d.K = n;
+    d.A = io.A; d.lda = io.lda; d.opa = OpA::Plain;
+    d.B = G; d.ldb = ldg; d.opb = OpB::Plain;
+    d.C = Y; d.ldc = m;
+    d.ksplit = 1;
+    HIP_TRY(launch_gemm<double>(d, s));
+  }
+  if (diag && io.Y) HIP_TRY(launch_copy2d<double>(Y, m, (double*)io.Y, io.ldy, m, l, s));
+  // Step 3 (+ Step 4: only the first k columns of the unit-lower factor are used)
+  {
+    PanelDesc d{};
+    d.X = Y; d.rs = 1; d.cs = m; d.nrows = (int)m; d.ncols = (int)l;
+    d.pos = pos_y; d.rstep = rstep_y; d.piv_row = piv_y; d.ipiv = ipiv_y;
+    d.info = flags + 0; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    HIP_TRY(launch_panel_lu(d, Ly.py, s));
+  }
+  if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
+  // Step 5: S = Lv^T Lv, S <- S^{-1} (side stream) while C = Lv^T A
+  {
+    GemmDesc d{};
+    d.M = k; d.N = k; d.K = m;
+    d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
+    d.B = Y; d.ldb = m; d.opb = OpB::Lv; d.bstep = rstep_y;
+    d.C = S; d.ldc = k;
+    d.ksplit = Ly.ksplit_gram; d.partial = at<void>(ws, Ly.part);
+    HIP_TRY(launch_gemm<double>(d, s));
+  }
+  HIP_TRY(hipEventRecord(h->ev_fork, s));
+  HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
+  HIP_TRY(launch_spd_inverse(S, k, h->side));
+  HIP_TRY(hipEventRecord(h->ev_join, h->side));
+  {
+    GemmDesc d{};
+    d.M = k; d.N = n; d.K = m;
+    d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
+    d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
+    d.C = C; d.ldc = k;
+    d.ksplit = 1;
+    HIP_TRY(launch_gemm<double>(d, s));
+  }
+  HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
+  {
+    GemmDesc d{};
+    d.M = k; d.N = n; d.K = k;
+    d.A = S; d.lda = k; d.opa = OpA::Plain;
+    d.B = C; d.ldb = k; d.opb = OpB::Plain;
+    d.C = Bst; d.ldc = k;
+    d.ksplit = 1;
+    HIP_TRY(launch_gemm<double>(d, s));
+  }
+  if (diag && io.B) HIP_TRY(launch_copy2d<double>(Bst, k, (double*)io.B, io.ldb, k, n, s));
+  // Step 6 through the LU of B^T
+  {
+    PanelDesc d{};
+    d.X = Bst; d.rs = k; d.cs = 1; d.nrows = (int)n; d.ncols = (int)k;
+    d.pos = pos_b; d.rstep = rstep_b; d.piv_row = piv_b; d.ipiv = ipiv_b;
+    d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    HIP_TRY(launch_panel_lu(d, Ly.pb, s));
+  }
+  if (diag && io.qpiv) HIP_TRY(launch_copy_i32(ipiv_b, io.qpiv, k, s));
+  HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
+  HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
+  // Step 8: U = U_b
+  HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
+  // Step 7: L = L_y L_b, rows written at their positions
+  HIP_TRY(launch_build_lb<double>(Bst, k, k, piv_b, Lb, s));
+  {
+    GemmDesc d{};
+    d.M = m; d.N = k; d.K = k;
+    d.A = Y; d.lda = m; d.opa = OpA::Lv; d.astep = rstep_y;
+    d.B = Lb; d.ldb = k; d.opb = OpB::Plain;
+    d.C = io.L; d.ldc = io.ldl;
+    d.rowmap = pos_y;
+    d.ksplit = 1;
+    HIP_TRY(launch_gemm<double>(d, s));
+  }
+  HIP_TRY(launch_info_merge(flags + 0, flags + 1, flags + 2, io.info, s));
+  return RLU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rlu_status_t rlu_create(rlu_handle_t* out, int device) {
+  if (!out) return RLU_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return RLU_ERR_INVALID_ARG;
+  rlu_handle_s* h = new (std::nothrow) rlu_handle_s();
+  if (!h) return RLU_ERR_OUT_OF_MEMORY;
+  h->device = device;
+  int prev = 0;
+  hipGetDevice(&prev);
+  if (hipSetDevice(device) != hipSuccess) { delete h; return RLU_ERR_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cus = prop.multiProcessorCount;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+    hipSetDevice(prev);
+    delete h;
+    return RLU_ERR_DEVICE;
+  }
+  hipSetDevice(prev);
+  *out = h;
+  return RLU_OK;
+}
+
+rlu_status_t rlu_destroy(rlu_handle_t h) {
+  if (!h) return RLU_ERR_INVALID_ARG;
+  int prev = 0;
+  hipGetDevice(&prev);
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  if (h->ws) hipFree(h->ws);
+  if (h->ev_fork) hipEventDestroy(h->ev_fork);
+  if (h->ev_join) hipEventDestroy(h->ev_join);
+  if (h->side) hipStreamDestroy(h->side);
+  hipSetDevice(prev);
+  delete h;
+  return RLU_OK;
+}
+
+rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes) {
+  if (!bytes) return RLU_ERR_INVALID_ARG;
+  const rlu_status_t st = validate(pb);
+  if (st != RLU_OK) return st;
+  Layout L;
+  if (!plan_layout(*pb, 256, L)) return RLU_ERR_UNSUPPORTED;
+  *bytes = L.total;
+  return RLU_OK;
+}
+
+rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffers_t* io,
+                        rlu_stream_t stream) {
+  if (!h) return RLU_ERR_INVALID_ARG;
+  rlu_status_t st = validate(pb);
+  if (st != RLU_OK) return st;
+  st = validate_io(pb, io);
+  if (st != RLU_OK) return st;
+  Layout L;
+  if (!plan_layout(*pb, h->cus, L)) return RLU_ERR_UNSUPPORTED;
+  int prev = 0;
+  hipGetDevice(&prev);
+  if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RLU_ERR_DEVICE;
+  st = ensure_ws(h, L.total);
+  if (st == RLU_OK) st = factor_fp64(h, *pb, *io, (hipStream_t)stream, L);
+  if (prev != h->device) hipSetDevice(prev);
+  return st;
+}
+
+rlu_status_t rlu_check_info(const int32_t info_host[3]) {
+  if (!info_host) return RLU_ERR_INVALID_ARG;
+  if (info_host[2] != 0) return RLU_ERR_DEVICE;
+  if (info_host[0] != 0 || info_host[1] != 0) return RLU_WARN_ZERO_PIVOT;
+  return RLU_OK;
+}
+
+const char* rlu_status_string(rlu_status_t st) {
+  switch (st) {
+    case RLU_OK: return "ok";
+    case RLU_PENDING: return "pending";
+    case RLU_WARN_ZERO_PIVOT: return "zero pivot (rank below k)";
+    case RLU_ERR_INVALID_ARG: return "invalid argument";
+    case RLU_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case RLU_ERR_DEVICE: return "device error";
+    case RLU_ERR_TOO_LARGE: return "problem too large";
+    case RLU_ERR_QUEUE_FULL: return "queue full";
+    case RLU_ERR_NONFINITE: return "non-finite input";
+    case RLU_ERR_UNKNOWN_TICKET: return "unknown ticket";
+    case RLU_ERR_UNSUPPORTED: return "unsupported configuration";
+  }
+  return "unknown status";
+}
+
+const char* rlu_version(void) { return "rlu-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,80 @@
+// Host-side launchers of the librlu HIP kernels (internal interface between
+// the kernel translation units and the C ABI in rlu_api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rlu {
+
+// ----- Step 1: Gaussian test matrix (rng.hip) ------------------------------
+template <typename T>
+hipError_t launch_gaussian(T* G, int64_t ldg, int64_t n, int64_t l, uint64_t seed,
+                           hipStream_t s);
+
+// ----- MFMA GEMM (gemm.hip) -----------------------------------------------
+// C(M x N) = op(A)(M x K) * op(B)(K x N), all column-major with leading
+// dimensions.  Operand forms:
+enum class OpA {
+  Plain,      // A(i, kk) = A[i + kk*lda]                      (M contiguous)
+  LvT,        // A(i, kk) = Lv(kk, i), Lv stored as Y[kk + i*lda]
+  Lv          // A(i, kk) = Lv(i, kk), Lv stored as Y[i + kk*lda]
+};
+enum class OpB {
+  Plain,      // B(kk, j) = B[kk + j*ldb]                      (K contiguous)
+  Lv          // B(kk, j) = Lv(kk, j), Lv stored as Y[kk + j*ldb]
+};
+struct GemmDesc {
+  int64_t M, N, K;
+  const void* A; int64_t lda; OpA opa; const int* astep;  // Lv row steps
+  const void* B; int64_t ldb; OpB opb; const int* bstep;
+  void* C; int64_t ldc;
+  const int* rowmap;   // optional: output row i goes to C row rowmap[i]
+  int ksplit;          // >1: partial sums to `partial`, then a fixed-order sum
+  void* partial;       // ksplit * M * N elements of workspace
+};
+template <typename T>
+hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
+size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit);
+
+// ----- Pivoted LU of a tall matrix, rows spread over workgroups (panel_lu.hip)
+struct PanelDesc {
+  void* X; int64_t rs, cs;   // element (row r, col c) at X[r*rs + c*cs]
+  int nrows, ncols;          // factors all ncols columns, ncols <= nrows
+  int* pos;                  // out [nrows]: final position of each row
+  int* rstep;                // out [nrows]: step that chose the row (ncols if none)
+  int* piv_row;              // out [ncols]: row chosen at each step
+  int* ipiv;                 // out [ncols]: LAPACK-style swap target (position)
+  int* info;                 // out: first zero-pivot step (1-based), 0 if none
+  int* fail;                 // out: set to 1 if the exchange timed out
+  void* xch;                 // exchange area, panel_xch_bytes()
+  long long timeout_ticks;   // bound on every wait (100 MHz ticks)
+};
+struct PanelPlan { int rows_per_wg; int nwg; size_t lds_bytes; size_t xch_bytes; bool ok; };
+PanelPlan panel_plan(int nrows, int ncols, int device_cus, int max_wg_per_cu_hint);
+hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s);
+
+// ----- Inverse of the k x k Gram matrix (spd_inverse.hip) ------------------
+hipError_t launch_spd_inverse(double* S, int64_t k, hipStream_t s);  // in place
+bool spd_inverse_supported(int64_t k);
+
+// ----- Permutations and factor assembly (finish.hip) ------------------------
+hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
+// L_b (k x k, unit lower) from the pivoted LU of B^T stored in B (k x n)
+template <typename T>
+hipError_t launch_build_lb(const T* Bst, int64_t ldb, int64_t k, const int* piv_row,
+                           T* Lb, hipStream_t s);
+// U (k x n) from the pivoted LU of B^T
+template <typename T>
+hipError_t launch_build_u(const T* Bst, int64_t ldb, int64_t k, int64_t n,
+                          const int* piv_row, const int* rstep, const int64_t* q,
+                          T* U, int64_t ldu, hipStream_t s);
+template <typename T>
+hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,
+                         int64_t cols, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s);
+hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
+                             int32_t* info_out, hipStream_t s);
+hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);
+
+}  // namespace rlu

@@ -1,0 +1,54 @@
+"""Shared helpers for the GPU parity tests: host <-> device column-major
+tensors and the comparison rules between the HIP path and the oracle."""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def ensure_built():
+    """Build librlu.so only if it is not there yet."""
+    import paper_1310_7202_amd as rlu
+    if not os.path.exists(rlu.LIB_PATH):
+        from paper_1310_7202_amd import build
+        build.build()
+
+
+def to_dev_colmajor(X: np.ndarray, dtype=None, device="cuda"):
+    import torch
+    X = np.asarray(X)
+    t = torch.from_numpy(np.ascontiguousarray(X.T))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device).t()
+
+
+def to_host(t) -> np.ndarray:
+    return t.detach().cpu().numpy()
+
+
+def unpermute_rows(L: np.ndarray, p: np.ndarray) -> np.ndarray:
+    """P^T L: row i of L belongs to original row p[i]."""
+    out = np.empty_like(L)
+    out[p] = L
+    return out
+
+
+def unpermute_cols(U: np.ndarray, q: np.ndarray) -> np.ndarray:
+    """U Q^T: column j of U belongs to original column q[j]."""
+    out = np.empty_like(U)
+    out[:, q] = U
+    return out
+
+
+def rel_maxdiff(a: np.ndarray, b: np.ndarray) -> float:
+    den = np.abs(b).max()
+    if den == 0:
+        return float(np.abs(a - b).max())
+    return float(np.abs(a - b).max() / den)

@@ -1,0 +1,97 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+include/rlu.h declares, and validates arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from tests.helpers import ROOT, ensure_built
+
+
+@pytest.fixture(scope="module")
+def rlu():
+    ensure_built()
+    import paper_1310_7202_amd as m
+    return m
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "rlu.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlu_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_what_the_binding_lists(rlu):
+    assert _declared_functions() == sorted(rlu.EXPORTED_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(rlu):
+    lib = ctypes.CDLL(rlu.LIB_PATH)
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(rlu):
+    for st in rlu.STATUS:
+        s = rlu.status_string(st)
+        assert isinstance(s, str) and s and s != "unknown status"
+    assert rlu.lib().rlu_version().decode().startswith("rlu-mi355x")
+
+
+def test_check_info_mapping(rlu):
+    assert rlu.check_info([0, 0, 0]) == 0
+    assert rlu.check_info([3, 0, 0]) == 2
+    assert rlu.check_info([0, 1, 0]) == 2
+    assert rlu.check_info([0, 0, 1]) == -3
+
+
+def _ws(rlu, m, n, k, l, dtype=0, prec=0, G=None, ldg=0, flags=0):
+    pb = rlu.Problem(m, n, k, l, dtype, prec, 0, G, ldg, flags)
+    out = ctypes.c_size_t()
+    st = rlu.lib().rlu_workspace_size(ctypes.byref(pb), ctypes.byref(out))
+    return st, out.value
+
+
+@pytest.mark.parametrize("m,n,k,l", [
+    (0, 10, 1, 1), (10, 0, 1, 1), (10, 10, 0, 1), (10, 10, 3, 2),
+    (10, 5, 3, 6), (5, 10, 3, 6), (10, 10, -1, 2),
+])
+def test_invalid_shapes_rejected(rlu, m, n, k, l):
+    st, _ = _ws(rlu, m, n, k, l)
+    assert st == -1
+
+
+def test_invalid_dtype_precision_rejected(rlu):
+    assert _ws(rlu, 100, 100, 5, 8, dtype=0, prec=1)[0] == -1   # FP32 arithmetic on FP64 storage
+    assert _ws(rlu, 100, 100, 5, 8, dtype=7, prec=0)[0] == -1
+    assert _ws(rlu, 100, 100, 5, 8, dtype=0, prec=9)[0] == -1
+    assert _ws(rlu, 100, 100, 5, 8, G=1, ldg=50)[0] == -1       # ldg < n
+    assert _ws(rlu, 100, 100, 5, 8, flags=1 << 7)[0] == -1
+
+
+def test_workspace_size_grows_with_problem(rlu):
+    st1, a = _ws(rlu, 512, 512, 10, 15)
+    st2, b = _ws(rlu, 8192, 8192, 200, 210)
+    assert st1 == 0 and st2 == 0 and 0 < a < b
+    # G passed by the caller: no G workspace
+    st3, c = _ws(rlu, 8192, 8192, 200, 210, G=1, ldg=8192)
+    assert st3 == 0 and c < b
+    # the dominant terms: Y (m l), C and B (2 k n) in FP64
+    assert b >= 8 * (8192 * 210 + 2 * 200 * 8192)
+
+
+def test_factor_rejects_null_handle_and_buffers(rlu):
+    lib = rlu.lib()
+    pb = rlu.Problem(100, 100, 5, 8, 0, 0, 0, None, 0, 0)
+    io = rlu.Buffers()
+    assert lib.rlu_factor(None, ctypes.byref(pb), ctypes.byref(io), None) == -1
+    # a fake non-null handle is never dereferenced before validation fails
+    assert lib.rlu_factor(ctypes.c_void_p(1), ctypes.byref(pb), None, None) == -1
+    assert lib.rlu_factor(ctypes.c_void_p(1), ctypes.byref(pb), ctypes.byref(io), None) == -1
+
+
+def test_create_rejects_bad_device(rlu):
+    h = ctypes.c_void_p()
+    assert rlu.lib().rlu_create(ctypes.byref(h), -1) < 0
+    assert rlu.lib().rlu_create(None, 0) == -1

@@ -1,0 +1,189 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Rules (FP64 path):
+  * the sketch Y matches to 1e-13 relative (one GEMM, FP64 both sides);
+  * pivot sequences match on every step whose choice is numerically decided
+    (oracle.rlu.pivot_gate: relative gap >= 1e-8, magnitude >= 1e3 u max|.|);
+  * with the first k pivots of Step 3 decided, B and the unpermuted factors
+    P^T L and U Q^T match to 1e-10 relative (the tolerance the FP64 path is
+    held to), and when every pivot is decided, L, U, p and q match directly;
+  * structure is exact: unit diagonal and zeros above it in L, zeros below
+    the diagonal of U, p and q permutations, info words equal.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from tests.helpers import (ensure_built, rel_maxdiff, to_dev_colmajor, to_host, unpermute_cols,
+                           unpermute_rows)
+from oracle import philox, rlu as orl
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rlu():
+    ensure_built()
+    import paper_1310_7202_amd as m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return m
+
+
+def run_and_compare(rlu, A, k, l, G, label=""):
+    print(f"[parity] {label} m={A.shape[0]} n={A.shape[1]} k={k} l={l}", flush=True)
+    out = rlu.factor(to_dev_colmajor(A), k, l, G=to_dev_colmajor(G), diagnostics=True)
+    torch.cuda.synchronize()
+    o = orl.randomized_lu(A, k, l, G)
+    info = to_host(out.info)
+    assert info[2] == 0, "pivot exchange failed"
+    assert (int(info[0]), int(info[1])) == o["info"]
+    m, n = A.shape
+    L, U, p, q = to_host(out.L), to_host(out.U), to_host(out.p), to_host(out.q)
+    # exact structure
+    np.testing.assert_array_equal(np.sort(p), np.arange(m))
+    np.testing.assert_array_equal(np.sort(q), np.arange(n))
+    assert np.all(np.diag(L[:k]) == 1.0)
+    assert np.all(np.triu(L[:k], 1) == 0.0)
+    assert np.all(np.tril(U, -1) == 0.0)
+    # Step 2
+    assert rel_maxdiff(to_host(out.Y), o["Y"]) < 1e-13
+    # Step 3 pivots on the decided prefix
+    gy = orl.pivot_gate(o["diag_y"])
+    np.testing.assert_array_equal(to_host(out.ipiv)[:gy], o["ipiv"][:gy])
+    if gy < k:
+        pytest.skip(f"Step 3 pivot {gy} is not numerically decided; factors not comparable")
+    # Step 5
+    assert rel_maxdiff(to_host(out.B), o["B"]) < TOL
+    # Step 6 pivots on the decided prefix
+    gb = orl.pivot_gate(o["diag_b"])
+    np.testing.assert_array_equal(to_host(out.qpiv)[:gb], o["qpiv"][:gb])
+    if gb == k:
+        np.testing.assert_array_equal(q, o["q"])
+        assert rel_maxdiff(unpermute_rows(L, p), unpermute_rows(o["L"], o["p"])) < TOL
+        assert rel_maxdiff(U, o["U"]) < TOL
+    if gy == l and gb == k:
+        np.testing.assert_array_equal(p, o["p"])
+        assert rel_maxdiff(L, o["L"]) < TOL
+    return out, o
+
+
+def test_small_config(rlu):
+    A, k, l = workloads.config_small(101)
+    G = workloads.gaussian((A.shape[1], l), 7203)
+    run_and_compare(rlu, A, k, l, G, "512^2 rank-10")
+
+
+@pytest.mark.parametrize("m,n,k,l,rate", [
+    (3000, 2500, 50, 60, 20.0),     # several workgroups per panel, ragged tails
+    (700, 1300, 33, 41, 8.0),       # m < n, ragged GEMM tiles
+    (1300, 700, 40, 40, 8.0),       # k = l
+    (200, 64, 64, 64, 30.0),        # l = min(m, n): full-rank reconstruction
+    (97, 131, 5, 9, 3.0),           # sizes below one tile
+])
+def test_spectral_shapes(rlu, m, n, k, l, rate):
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), rate), 1000 + m)
+    G = workloads.gaussian((n, l), 2000 + n)
+    out, o = run_and_compare(rlu, A, k, l, G, f"spectral rate={rate}")
+    if k == l == min(m, n):
+        L, U, p, q = to_host(out.L), to_host(out.U), to_host(out.p), to_host(out.q)
+        np.testing.assert_allclose(L @ U, A[np.ix_(p, q)], atol=1e-11 * np.abs(A).max())
+
+
+def test_one_by_one(rlu):
+    A = np.array([[3.0]])
+    G = np.array([[0.5]])
+    out, o = run_and_compare(rlu, A, 1, 1, G, "1x1")
+    assert to_host(out.U)[0, 0] == pytest.approx(3.0, rel=1e-15)
+
+
+def test_single_column_rank_one(rlu):
+    A = np.zeros((40, 30))
+    A[:, 4] = np.linspace(-1.0, 2.0, 40)
+    G = workloads.gaussian((30, 3), 5)
+    out, o = run_and_compare(rlu, A, 1, 3, G, "rank one")
+
+
+def test_zero_matrix_sets_info(rlu):
+    A = np.zeros((64, 48))
+    G = workloads.gaussian((48, 6), 3)
+    out = rlu.factor(to_dev_colmajor(A), 4, 6, G=to_dev_colmajor(G), diagnostics=True)
+    torch.cuda.synchronize()
+    info = to_host(out.info)
+    assert tuple(info) == (1, 1, 0)
+    assert rlu.check_info(info) == 2  # RLU_WARN_ZERO_PIVOT
+    L, U = to_host(out.L), to_host(out.U)
+    assert np.all(U == 0.0)
+    assert np.all(np.diag(L[:4]) == 1.0)
+
+
+def test_rank_deficient_second_pivot_zero(rlu):
+    A = np.zeros((30, 20))
+    A[3, 5] = 2.0
+    G = workloads.gaussian((20, 3), 4)
+    out = rlu.factor(to_dev_colmajor(A), 2, 3, G=to_dev_colmajor(G), diagnostics=True)
+    torch.cuda.synchronize()
+    o = orl.randomized_lu(A, 2, 3, G)
+    info = to_host(out.info)
+    assert (int(info[0]), int(info[1])) == o["info"] == (2, 2)
+    L, U, p, q = to_host(out.L), to_host(out.U), to_host(out.p), to_host(out.q)
+    np.testing.assert_allclose(L @ U, A[np.ix_(p, q)], atol=1e-14)
+
+
+def test_device_gaussian_matches_host_generator(rlu):
+    n, l, seed = 300, 7, 0x1234_5678_9ABC
+    A = np.eye(n)
+    out = rlu.factor(to_dev_colmajor(A), 3, l, seed=seed, diagnostics=True)
+    torch.cuda.synchronize()
+    Yd = to_host(out.Y)            # A = I: Y is G itself (exact products)
+    Gh = philox.gaussian_matrix(n, l, seed)
+    diff = np.abs(Yd - Gh)
+    # libm differences only: a few ulp of each entry
+    assert np.all(diff <= 8 * np.spacing(np.abs(Gh)) + 1e-300)
+    assert diff.max() < 1e-14
+
+
+def test_generated_sketch_end_to_end(rlu):
+    A = workloads.spectral_matrix(900, 800, workloads.exp_decay(800, 10.0), 77)
+    k, l, seed = 30, 36, 99
+    out = rlu.factor(to_dev_colmajor(A), k, l, seed=seed, diagnostics=True)
+    torch.cuda.synchronize()
+    G = philox.gaussian_matrix(800, l, seed)
+    o = orl.randomized_lu(A, k, l, G)
+    L, U, p, q = to_host(out.L), to_host(out.U), to_host(out.p), to_host(out.q)
+    assert rel_maxdiff(unpermute_rows(L, p), unpermute_rows(o["L"], o["p"])) < TOL
+    assert rel_maxdiff(unpermute_cols(U, q), unpermute_cols(o["U"], o["q"])) < TOL
+
+
+def test_repeat_calls_are_bitwise_identical_and_resize(rlu):
+    A = workloads.spectral_matrix(1500, 1200, workloads.exp_decay(1200, 15.0), 5)
+    G = workloads.gaussian((1200, 40), 6)
+    dA, dG = to_dev_colmajor(A), to_dev_colmajor(G)
+    a = rlu.factor(dA, 32, 40, G=dG)
+    small = rlu.factor(to_dev_colmajor(A[:300, :200]), 8, 10, G=to_dev_colmajor(G[:200, :10]))
+    b = rlu.factor(dA, 32, 40, G=dG)
+    torch.cuda.synchronize()
+    for x, y in ((a.L, b.L), (a.U, b.U), (a.p, b.p), (a.q, b.q)):
+        assert torch.equal(x, y)
+    o = orl.randomized_lu(A[:300, :200], 8, 10, G[:200, :10])
+    assert rel_maxdiff(unpermute_rows(to_host(small.L), to_host(small.p)),
+                       unpermute_rows(o["L"], o["p"])) < TOL
+
+
+def test_leading_dimensions(rlu):
+    m, n, k, l = 300, 250, 12, 16
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), 5.0), 8)
+    G = workloads.gaussian((n, l), 9)
+    big = torch.zeros((n, m + 37), dtype=torch.float64, device="cuda")
+    big[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    dA = big.t()[:m]       # m x n view with lda = m + 37
+    assert dA.stride() == (1, m + 37)
+    out = rlu.factor(dA, k, l, G=to_dev_colmajor(G))
+    torch.cuda.synchronize()
+    o = orl.randomized_lu(A, k, l, G)
+    assert rel_maxdiff(unpermute_rows(to_host(out.L), to_host(out.p)),
+                       unpermute_rows(o["L"], o["p"])) < TOL
