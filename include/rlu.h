@@ -145,6 +145,22 @@ rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
 rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
                         const rlu_buffers_t* io, rlu_stream_t stream);
 
+/* Phase timing for measurement tools.  When enabled, rlu_factor records a
+ * HIP event pair around each phase on the stream that runs the phase (the
+ * caller's stream, or the handle's side stream for the Gram inverse).  The
+ * handle keeps the events of the last RLU_TIMING_RING calls. */
+#define RLU_TIMING_RING 64
+#define RLU_MAX_PHASES 16
+rlu_status_t rlu_set_timing(rlu_handle_t h, int enable);
+
+/* Durations (milliseconds) of the phases of the call `back` calls before the
+ * most recent one (back = 0: the most recent), waiting for its events.
+ * Fills up to `cap` entries of ms[] and names[] (static strings; either may
+ * be NULL) and stores the phase count in *count.  RLU_ERR_INVALID_ARG if no
+ * timed call is that far back. */
+rlu_status_t rlu_phase_times(rlu_handle_t h, int back, float* ms, const char** names, int cap,
+                             int* count);
+
 /* Map the three info words (already copied to the host) to a status:
  * RLU_ERR_DEVICE if the exchange failed, RLU_WARN_ZERO_PIVOT if a zero pivot
  * occurred, RLU_OK otherwise. */

@@ -32,7 +32,8 @@ STATUS = {
 
 # every function include/rlu.h declares
 EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                    "rlu_check_info", "rlu_status_string", "rlu_version"]
+                    "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
+                    "rlu_status_string", "rlu_version"]
 
 
 class RluError(RuntimeError):
@@ -78,8 +79,13 @@ def lib() -> ctypes.CDLL:
         L.rlu_status_string.argtypes = [ctypes.c_int]
         L.rlu_status_string.restype = ctypes.c_char_p
         L.rlu_version.restype = ctypes.c_char_p
+        L.rlu_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.rlu_phase_times.argtypes = [ctypes.c_void_p, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_float),
+                                      ctypes.POINTER(ctypes.c_char_p), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]
         for name in ("rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                     "rlu_check_info"):
+                     "rlu_check_info", "rlu_set_timing", "rlu_phase_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -120,6 +126,19 @@ class Handle:
     @property
     def ptr(self):
         return self._h
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().rlu_set_timing(self._h, 1 if enable else 0), "rlu_set_timing")
+
+    def phase_times(self, back: int = 0) -> dict:
+        """{phase name: ms} of the call `back` calls before the latest."""
+        cap = 16
+        ms = (ctypes.c_float * cap)()
+        names = (ctypes.c_char_p * cap)()
+        cnt = ctypes.c_int()
+        _check(lib().rlu_phase_times(self._h, back, ms, names, cap, ctypes.byref(cnt)),
+               "rlu_phase_times")
+        return {names[i].decode(): float(ms[i]) for i in range(cnt.value)}
 
 
 _handles: dict = {}

@@ -5,46 +5,57 @@
 //            S   = L_y^T L_y  = Lv^T Lv     (Gram matrix of the Remark)
 //            B   = S^{-1} C
 //   Step 7   L   = L_y L_b    = P (Lv L_b)  (rows scattered to positions)
-// where Lv is the unit-lower factor of Step 3 read in place (see
-// lv_value in rlu_device.h): the permutation P never touches A.
+// where Lv is the unit-lower factor of Step 3 read in place (see lv_value in
+// rlu_device.h): the permutation P never touches A.
 //
 // One kernel template: a workgroup computes a BM x BN tile of C with 16x16x4
-// MFMA tiles, staging BK = 16 deep slices of both operands through LDS with
-// register double buffering (global loads of slice t+1 overlap the MFMAs of
-// slice t).  Operands may be converted on load (TA, TB -> TC), the output is
-// written in TO.  Optional split-K writes per-split partial sums that a
-// second kernel adds in a fixed order, so results never depend on timing.
+// MFMA tiles, staging BK-deep slices of both operands through LDS with
+// register prefetch (global loads of slice t+1 overlap the MFMAs of slice t).
+// Each operand is staged in the LDS layout that matches its contiguous
+// dimension in HBM, so global reads stay long and coalesced:
+//   * operand contiguous along M/N (A of Step 2): LDS [k][row]
+//   * operand contiguous along K (both operands of Step 5): LDS [row][k],
+//     and a deep slice (BK = 32) so each column is read in 256-byte runs.
+// Operands may be converted on load (TA, TB -> TC), the output is written in
+// TO.  Optional split-K writes per-split partial sums that a second kernel
+// adds in a fixed order, so results never depend on timing.
 #include "rlu_device.h"
 #include "rlu_kernels.h"
+
+#include <cstdlib>
 
 namespace rlu {
 namespace {
 
-constexpr int BK = 16;
-
-template <typename TC, int BM, int BN, int WM, int WN>
+template <int BM, int BN, int BK, int WM, int WN, bool AK, bool BKC, int NBUF>
 struct Tile {
   static constexpr int NT = 64 * WM * WN;
   static constexpr int WTM = BM / WM, WTN = BN / WN;
   static constexpr int TM = WTM / 16, TN = WTN / 16;
-  static constexpr int APAD = 2, BPAD = 2;
-  static constexpr int AL = BM + APAD, BL = BN + BPAD;
+  // LDS strides: [k][row] layout pads rows, [row][k] layout pads k
+  static constexpr int A_LD = AK ? (BK + 2) : (BM + 2);
+  static constexpr int B_LD = BKC ? (BK + 2) : (BN + 2);
+  static constexpr int A_SZ = AK ? BM * A_LD : BK * A_LD;
+  static constexpr int B_SZ = BKC ? BN * B_LD : BK * B_LD;
   static constexpr int AE = BM * BK / NT, BE = BN * BK / NT;
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile must divide threads");
+  static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
 };
 
-template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int WM, int WN,
-          OpA OA, OpB OB>
+template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
+          int WN, int NBUF, OpA OA, OpB OB>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
             const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
             const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
             const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial) {
-  typedef Tile<TC, BM, BN, WM, WN> Tl;
+  constexpr bool AK = (OA == OpA::LvT);  // A operand contiguous along K
+  constexpr bool BKC = true;             // B operands are contiguous along K
+  typedef Tile<BM, BN, BK, WM, WN, AK, BKC, NBUF> Tl;
   typedef Mfma<TC> MF;
-  __shared__ TC As[2][BK][Tl::AL];
-  __shared__ TC Bs[2][BK][Tl::BL];
+  __shared__ TC As[NBUF][Tl::A_SZ];
+  __shared__ TC Bs[NBUF][Tl::B_SZ];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -63,7 +74,7 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
     for (int q = 0; q < Tl::AE; ++q) {
       const int e = tid + q * Tl::NT;
       int i, kk;
-      if (OA == OpA::LvT) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+      if (AK) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
       const int64_t gi = m0 + i, gk = k0 + kk;
       TC v = TC(0);
       if (gi < M && gk < kend) {
@@ -94,15 +105,19 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
 #pragma unroll
     for (int q = 0; q < Tl::AE; ++q) {
       const int e = tid + q * Tl::NT;
-      int i, kk;
-      if (OA == OpA::LvT) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
-      As[buf][kk][i] = ra[q];
+      if (AK) {
+        const int kk = e % BK, i = e / BK;
+        As[buf][i * Tl::A_LD + kk] = ra[q];
+      } else {
+        const int i = e % BM, kk = e / BM;
+        As[buf][kk * Tl::A_LD + i] = ra[q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < Tl::BE; ++q) {
       const int e = tid + q * Tl::NT;
       const int kk = e % BK, j = e / BK;
-      Bs[buf][kk][j] = rb[q];
+      Bs[buf][j * Tl::B_LD + kk] = rb[q];
     }
   };
 
@@ -126,17 +141,26 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
       const int kr = k4 * 4 + (lane >> 4);
       TC af[Tl::TM], bf[Tl::TN];
 #pragma unroll
-      for (int a = 0; a < Tl::TM; ++a) af[a] = As[buf][kr][wm * Tl::WTM + a * 16 + (lane & 15)];
+      for (int a = 0; a < Tl::TM; ++a) {
+        const int row = wm * Tl::WTM + a * 16 + (lane & 15);
+        af[a] = AK ? As[buf][row * Tl::A_LD + kr] : As[buf][kr * Tl::A_LD + row];
+      }
 #pragma unroll
-      for (int b = 0; b < Tl::TN; ++b) bf[b] = Bs[buf][kr][wn * Tl::WTN + b * 16 + (lane & 15)];
+      for (int b = 0; b < Tl::TN; ++b) {
+        const int col = wn * Tl::WTN + b * 16 + (lane & 15);
+        bf[b] = Bs[buf][col * Tl::B_LD + kr];
+      }
 #pragma unroll
       for (int a = 0; a < Tl::TM; ++a)
 #pragma unroll
         for (int b = 0; b < Tl::TN; ++b) acc[a][b] = MF::mma(af[a], bf[b], acc[a][b]);
     }
-    if (more) store(buf ^ 1);
+    if (more) {
+      if (NBUF == 1) __syncthreads();  // everyone is done reading the only buffer
+      store(NBUF == 1 ? 0 : buf ^ 1);
+    }
     __syncthreads();
-    buf ^= 1;
+    if (NBUF == 2) buf ^= 1;
   }
 
   // epilogue
@@ -176,30 +200,58 @@ __global__ void __launch_bounds__(256) splitk_sum_kernel(int64_t M, int64_t N, i
   }
 }
 
-struct Cfg { int bm, bn; };
+// Tile shapes compiled in (BM, BN, BK, waves M x N, LDS buffers).
+enum CfgId { C64x64x16, C64x112x16, C112x64x16, C64x112x32, C112x64x32, C112x64x64,
+             C64x64x32, C128x64x16, C64x128x16, CFG_COUNT };
+struct CfgInfo { int bm, bn, bk; };
+struct GemmShape { int cfg; int ksplit; };
+constexpr CfgInfo kCfg[CFG_COUNT] = {{64, 64, 16}, {64, 112, 16}, {112, 64, 16},
+                                     {64, 112, 32}, {112, 64, 32}, {112, 64, 64},
+                                     {64, 64, 32}, {128, 64, 16}, {64, 128, 16}};
 
-// Pick the tile shape that finishes first on 256 CUs: time ~ (rounds of 256
-// tiles) x (tile area); ties go to the shape with more tiles.
-Cfg choose_cfg(int64_t M, int64_t N) {
-  const Cfg cands[3] = {{64, 64}, {64, 112}, {112, 64}};
-  Cfg best = cands[0];
-  double best_cost = 1e300, best_tiles = 0;
-  for (const Cfg& c : cands) {
-    const double tiles = (double)((M + c.bm - 1) / c.bm) * (double)((N + c.bn - 1) / c.bn);
-    const double rounds = (double)(((int64_t)tiles + 255) / 256);
-    const double cost = rounds * c.bm * c.bn;
-    if (cost < best_cost || (cost == best_cost && tiles > best_tiles)) {
-      best_cost = cost; best = c; best_tiles = tiles;
+int g_force_cfg = -1;  // tuning override (-1: automatic)
+
+// Tile shape and split-K for a product (the tuning table of this library,
+// from sweeps of the FP64 products of the 8192 x 8192 configuration on
+// MI355X):
+//   * the tile shape minimizes (rounds of 256 tiles) x (tile area), ties to
+//     more tiles; an A operand streamed along K (Lv^T) uses 64 x 64 tiles,
+//     which measured fastest for it;
+//   * split-K raises the workgroup count to about four per CU (one
+//     workgroup per CU leaves the FP64 MFMA pipe idle at every barrier),
+//     keeping at least 512 of K per split.
+GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
+  GemmShape sh{C64x64x16, 1};
+  if (g_force_cfg >= 0) {
+    sh.cfg = g_force_cfg;
+  } else if (kcontig_a) {
+    sh.cfg = C64x64x16;
+  } else {
+    const int cands[3] = {C64x64x16, C64x112x16, C112x64x16};
+    double best_cost = 1e300, best_tiles = 0;
+    for (int id : cands) {
+      const CfgInfo& c = kCfg[id];
+      const double tiles = (double)((M + c.bm - 1) / c.bm) * (double)((N + c.bn - 1) / c.bn);
+      const double rounds = (double)(((int64_t)tiles + 255) / 256);
+      const double cost = rounds * c.bm * c.bn;
+      if (cost < best_cost || (cost == best_cost && tiles > best_tiles)) {
+        best_cost = cost; sh.cfg = id; best_tiles = tiles;
+      }
     }
   }
-  return best;
+  const CfgInfo& c = kCfg[sh.cfg];
+  const int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+  int ks = 1;
+  while (tiles * ks < 1024 && K / (ks * 2) >= 512 && ks < 32) ks *= 2;
+  sh.ksplit = ks;
+  return sh;
 }
 
-template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int WM, int WN,
-          OpA OA, OpB OB>
+template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
+          int WN, int NBUF, OpA OA, OpB OB>
 hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
   dim3 grid((unsigned)((d.M + BM - 1) / BM), (unsigned)((d.N + BN - 1) / BN), (unsigned)ksplit);
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, WM, WN, OA, OB>), grid,
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>), grid,
                      dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A, d.lda, d.astep,
                      (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap, ksplit,
                      (TO*)d.partial);
@@ -208,15 +260,22 @@ hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
 
 template <typename TA, typename TB, typename TC, typename TO, OpA OA, OpB OB>
 hipError_t launch_ops(const GemmDesc& d, hipStream_t s) {
-  const Cfg c = choose_cfg(d.M, d.N);
-  const int ks = d.ksplit > 1 ? d.ksplit : 1;
+  GemmShape sh = choose_shape(d.M, d.N, d.K, OA == OpA::LvT);
+  const int c = sh.cfg;
+  // ksplit 0 = automatic (needs the partial workspace); 1 = no split
+  const int ks = d.ksplit == 0 ? (d.partial ? sh.ksplit : 1) : d.ksplit;
   hipError_t e;
-  if (c.bm == 64 && c.bn == 64)
-    e = launch_cfg<TA, TB, TC, TO, 64, 64, 2, 2, OA, OB>(d, ks, s);
-  else if (c.bm == 64)
-    e = launch_cfg<TA, TB, TC, TO, 64, 112, 4, 1, OA, OB>(d, ks, s);
-  else
-    e = launch_cfg<TA, TB, TC, TO, 112, 64, 1, 4, OA, OB>(d, ks, s);
+  switch (c) {
+    case C64x64x16: e = launch_cfg<TA, TB, TC, TO, 64, 64, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
+    case C64x112x16: e = launch_cfg<TA, TB, TC, TO, 64, 112, 16, 4, 1, 2, OA, OB>(d, ks, s); break;
+    case C112x64x16: e = launch_cfg<TA, TB, TC, TO, 112, 64, 16, 1, 4, 2, OA, OB>(d, ks, s); break;
+    case C64x112x32: e = launch_cfg<TA, TB, TC, TO, 64, 112, 32, 4, 1, 2, OA, OB>(d, ks, s); break;
+    case C112x64x32: e = launch_cfg<TA, TB, TC, TO, 112, 64, 32, 1, 4, 2, OA, OB>(d, ks, s); break;
+    case C112x64x64: e = launch_cfg<TA, TB, TC, TO, 112, 64, 64, 1, 4, 1, OA, OB>(d, ks, s); break;
+    case C64x64x32: e = launch_cfg<TA, TB, TC, TO, 64, 64, 32, 2, 2, 2, OA, OB>(d, ks, s); break;
+    case C128x64x16: e = launch_cfg<TA, TB, TC, TO, 128, 64, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
+    default: e = launch_cfg<TA, TB, TC, TO, 64, 128, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
+  }
   if (e != hipSuccess || ks == 1) return e;
   const int64_t total = d.M * d.N;
   int64_t blocks = (total + 255) / 256;
@@ -245,6 +304,12 @@ hipError_t dispatch(const GemmDesc& d, hipStream_t s) {
 size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit) {
   return ksplit > 1 ? (size_t)ksplit * (size_t)M * (size_t)N : 0;
 }
+
+size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa) {
+  return gemm_partial_elems(M, N, choose_shape(M, N, K, opa == OpA::LvT).ksplit);
+}
+
+void gemm_force_config(int id) { g_force_cfg = (id >= 0 && id < CFG_COUNT) ? id : -1; }
 
 // FP64 path: every operand and the output in FP64.
 template <>

@@ -12,14 +12,28 @@
 //     factorization; rows never move ("virtual" pivoting): each row records
 //     its current position (to reproduce LAPACK's swap bookkeeping and its
 //     lowest-position tie break) and the step that chose it.
-//   * step j: every workgroup finds its best candidate in column j (largest
-//     magnitude, lowest current position on ties) and publishes it, with the
-//     candidate's current row from column j on, in an exchange record; every
-//     workgroup then reads all records, selects the same winner and applies
-//     the rank-one update to its own rows.  One exchange per step, no grid
-//     barrier; records alternate between two buffers by step parity, which
-//     is enough because a workgroup cannot publish step j+2 before every
-//     workgroup has finished reading step j.
+//   * step j: wave 0 brings column j up to date, finds the workgroup's best
+//     candidate (largest magnitude, lowest current position on ties) and
+//     publishes it in an exchange record: its value in column j, its
+//     multiplier of step j-1 and its row from column j+1 on *one update
+//     behind* (through step j-2).  Every workgroup reads all records, selects
+//     the same winner and completes the winner's row itself,
+//         U(j, c) = row(c) - l(j-1) U(j-1, c),
+//     with the same fused multiply-add the winner's own workgroup applies to
+//     its copy, so all copies agree bitwise.  Publishing the row one update
+//     behind lets waves 1-3 apply the bulk rank-one update of step j-1 while
+//     wave 0 waits on the exchange: only the exchange latency and
+//     O(R/64 + ncols/64) work per lane sit on the critical path.
+//   * exchange protocol: every 64-bit word of a record carries the step tag
+//     in its upper half and 32 bits of payload in its lower half (a double
+//     takes two words).  Words are written and read with device-coherent
+//     (agent-scope) relaxed atomic accesses, whose 64-bit single-copy
+//     atomicity is all the protocol relies on: a reader accepts a record only
+//     when every word it needs shows the current tag, so no store ordering,
+//     fence or cache maintenance is needed and the writer never waits.
+//     Records alternate between two buffers by step parity, which is enough
+//     because a workgroup cannot publish step j+2 before every workgroup has
+//     finished reading step j.
 //   * every wait is bounded by a wall-clock limit; on expiry the kernel sets
 //     a failure flag and all workgroups leave.
 #include "rlu_device.h"
@@ -30,31 +44,107 @@
 namespace rlu {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kNone = INT_MAX;
 
-struct RecHeader {
-  unsigned long long tag;  // step + 1 once the record is complete
-  double absval;           // candidate magnitude, -1 if the workgroup has none
-  int pos;                 // candidate's current position
-  int row;                 // candidate's original row index
-  int pad[2];
-};
+// Record: 10 header words, then 2 words per column (entries from column j+2
+// on are written at step j).  Header words: [0,1] candidate magnitude,
+// [2] current position, [3] original row (or -1), [4,5] value in column j,
+// [6,7] multiplier of step j-1, [8,9] value in column j+1 (one update
+// behind, like the row).
+constexpr int kHdrWords = 10;
 
-__device__ __forceinline__ void pick(double& a, int& p, int& r, double a2, int p2, int r2) {
-  if (a2 > a || (a2 == a && p2 < p)) { a = a2; p = p2; r = r2; }
+__device__ __forceinline__ void put32(unsigned long long* w, unsigned tag, unsigned v) {
+  st_agent(w, ((unsigned long long)tag << 32) | v);
+}
+__device__ __forceinline__ void put64(unsigned long long* w, unsigned tag, unsigned long long v) {
+  st_agent(w, ((unsigned long long)tag << 32) | (v & 0xffffffffull));
+  st_agent(w + 1, ((unsigned long long)tag << 32) | (v >> 32));
+}
+__device__ __forceinline__ bool tagged(unsigned long long x, unsigned tag) {
+  return (unsigned)(x >> 32) == tag;
+}
+__device__ __forceinline__ unsigned long long join64(unsigned long long lo,
+                                                     unsigned long long hi) {
+  return (lo & 0xffffffffull) | (hi << 32);
 }
 
-__device__ __forceinline__ void wave_pick(double& a, int& p, int& r) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const double a2 = __shfl_xor(a, off, 64);
-    const int p2 = __shfl_xor(p, off, 64);
-    const int r2 = __shfl_xor(r, off, 64);
-    pick(a, p, r, a2, p2, r2);
-  }
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+__device__ __forceinline__ double bitsd(unsigned long long x) {
+  return __longlong_as_double((long long)x);
+}
+// Workgroup barrier that orders LDS only.  __syncthreads() also drains every
+// outstanding global store of the wave first, which would put a full memory
+// round trip (the exchange record just published) in front of each barrier;
+// workgroup members here communicate through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): LDS (and scalar) ops done
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// larger magnitude wins; equal magnitudes go to the lower current position
+__device__ __forceinline__ bool better(double a2, int p2, double a, int p) {
+  return a2 > a || (a2 == a && p2 < p);
+}
+
+// One step of a wavefront reduction through DPP: every lane receives the
+// (magnitude, position, payload) triple of the lane selected by CTRL and
+// keeps the better of the two.  Lanes without a source keep their own value
+// (old operand = own value), which the comparison leaves unchanged.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_pick(double& a, int& p, int& x) {
+  const int alo = __double2loint(a), ahi = __double2hiint(a);
+  const int lo2 = __builtin_amdgcn_update_dpp(alo, alo, CTRL, ROW_MASK, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(ahi, ahi, CTRL, ROW_MASK, 0xF, false);
+  const int p2 = __builtin_amdgcn_update_dpp(p, p, CTRL, ROW_MASK, 0xF, false);
+  const int x2 = __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xF, false);
+  const double a2 = __hiloint2double(hi2, lo2);
+  if (better(a2, p2, a, p)) { a = a2; p = p2; x = x2; }
+}
+
+// Best (largest magnitude, then lowest position) over the 64 lanes, returned
+// in every lane: an inclusive scan inside each row of 16 lanes (row_shr 1, 2,
+// 4, 8), then row_bcast 15 and 31 carry rows 0-1 and 0-3 into lane 63, whose
+// value is broadcast.
+__device__ __forceinline__ void wave_argbest(double& a, int& p, int& x) {
+  dpp_pick<0x111, 0xF>(a, p, x);  // row_shr:1
+  dpp_pick<0x112, 0xF>(a, p, x);  // row_shr:2
+  dpp_pick<0x114, 0xF>(a, p, x);  // row_shr:4
+  dpp_pick<0x118, 0xF>(a, p, x);  // row_shr:8
+  dpp_pick<0x142, 0xA>(a, p, x);  // row_bcast:15 into rows 1 and 3
+  dpp_pick<0x143, 0xC>(a, p, x);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(a), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(a), 63);
+  a = __hiloint2double(hi, lo);
+  p = __builtin_amdgcn_readlane(p, 63);
+  x = __builtin_amdgcn_readlane(x, 63);
+}
+
+// Value of lane `src` (uniform) in every lane.
+__device__ __forceinline__ double lane_bcast(double v, int src) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+  return __hiloint2double(hi, lo);
+}
+
+// RPL = rows per lane: lane l of a wave handles rows l, l+64, ..., so the
+// workgroup holds at most 64 * RPL rows.
+//
+// Step j, with U(i, .) the U row of step i (the winner's row through step
+// i-1) kept in a two-slot ring urow[i & 1]:
+//   wave 0      U(j-1, j) from the step j-1 header; column j brought up to
+//               date; local candidate; header + row published        | B1 |
+//               wait for all headers, select the winner, bookkeeping,
+//               multipliers of step j                                 | B0 |
+//   waves 1-7   fetch the step j-1 winner's row, complete U(j-1, c)
+//               for c > j                                             | B1 |
+//               rank-one update of step j-1 on columns c > j          | B0 |
+// so the only device round trip on wave 0's path is the header exchange.
+template <int RPL>
 __global__ void __launch_bounds__(kThreads)
 panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R,
                 int nwg, int* __restrict__ pos_out, int* __restrict__ rstep_out,
@@ -62,12 +152,17 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
                 int* __restrict__ info_out, int* __restrict__ fail, char* __restrict__ xch,
                 int64_t rec_stride, long long timeout_ticks) {
   extern __shared__ double smem[];
-  double* Ts = smem;                      // R x ncols, column-major (ld R)
-  double* urow = Ts + (int64_t)R * ncols; // ncols
-  double* mult = urow + ncols;            // R
-  int* pos_s = (int*)(mult + R);          // R
-  int* step_s = pos_s + R;                // R
-  __shared__ int sh_win_wg, sh_win_row, sh_win_pos, sh_stop, sh_info;
+  double* Ts = smem;                        // R x ncols, column-major (ld R)
+  double* urow = Ts + (int64_t)R * ncols;   // 2 x ncols: U rows by step parity
+  double* lbody = urow + 2 * ncols;         // 2 x ncols: single-workgroup "records"
+  int* pos_s = (int*)(lbody + 2 * ncols);   // R: final positions (written at the end)
+  int* step_s = pos_s + R;                  // R: step that chose the row, kNone if none
+  int* pivrow_s = step_s + R;               // ncols: row chosen at each step
+  int* ipiv_s = pivrow_s + ncols;           // ncols: its position before the swap
+  __shared__ int sh_stop, sh_bw[2];
+  __shared__ double sh_piv[2], sh_lm[2], sh_v1[2];   // winner header, by step parity
+  __shared__ int sh_cr, sh_cp;                        // local candidate (one workgroup)
+  __shared__ double sh_cpiv, sh_clm, sh_cv1;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int w = blockIdx.x;
@@ -86,149 +181,298 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
       Ts[(int64_t)c * R + r] = r < nr ? X[(int64_t)(row0 + r) * rs + (int64_t)c * cs] : 0.0;
     }
   }
-  for (int r = tid; r < R; r += kThreads) {
-    pos_s[r] = row0 + r;
-    step_s[r] = r < nr ? kNone : -1;  // -1: padding, never active
+  for (int r = tid; r < R; r += kThreads) step_s[r] = kNone;
+  if (tid == 0) {
+    sh_stop = 0;
+    for (int t = 0; t < 2; ++t) { sh_bw[t] = -1; sh_piv[t] = 0.0; sh_lm[t] = 0.0; sh_v1[t] = 0.0; }
   }
-  if (tid == 0) { sh_stop = 0; sh_info = 0; }
+  // wave 0's per-row state, in registers: position, choosing step, current
+  // pivot-column value and the multiplier of the previous step
+  int pos_q[RPL], st_q[RPL];
+  double val_q[RPL], mlt_q[RPL];
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const int r = lane + 64 * q;
+    pos_q[q] = row0 + r;
+    st_q[q] = r < nr ? kNone : -1;  // -1: no such row
+    val_q[q] = 0.0;
+    mlt_q[q] = 0.0;
+  }
+  int info = 0;
   __syncthreads();
 
   const long long t_start = now_ticks();
 
   for (int j = 0; j < ncols; ++j) {
-    // ---- (a) local candidate and (b) exchange: wave 0 ------------------------
+    const int sj = j & 1, sp = sj ^ 1;
+    double* Uj = urow + sj * ncols;   // U(j, .); until overwritten it still holds U(j-2, .)
+    double* Up = urow + sp * ncols;   // U(j-1, .)
+    const bool upd1 = j >= 1 && sh_piv[sp] != 0.0;  // step j-1 updated the trailing part
+    const bool upd2 = j >= 2 && sh_piv[sj] != 0.0;  // step j-2 did
+    const unsigned tag = (unsigned)(j + 1);
+    char* base = xch + (int64_t)sj * nwg * rec_stride;
+
     if (wave == 0) {
+      // ---- (1) column j up to date, local candidate, publish -----------------
+      double uj = 0.0;  // U(j-1, j)
+      if (upd1) {
+        uj = upd2 ? __fma_rn(-sh_lm[sp], Uj[j], sh_v1[sp]) : sh_v1[sp];
+        if (lane == 0) Up[j] = uj;
+      }
       double a = -1.0; int p = INT_MAX, r = -1;
-      for (int rr = lane; rr < nr; rr += 64) {
-        if (step_s[rr] == kNone) {
-          // a NaN entry ranks above every number so that it is always chosen
-          // (and propagates) instead of leaving a step without a candidate
-          const double v = Ts[(int64_t)j * R + rr];
-          pick(a, p, r, v != v ? __builtin_inf() : fabs(v), pos_s[rr], rr);
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        if (st_q[q] == kNone) {
+          const int rr = lane + 64 * q;
+          double v = Ts[(int64_t)j * R + rr];
+          if (upd1) {
+            v = __fma_rn(-mlt_q[q], uj, v);
+            Ts[(int64_t)j * R + rr] = v;
+          }
+          val_q[q] = v;
+          // NaN ranks above every number, so no step is ever left without
+          // a candidate (and the NaN propagates)
+          const double key = v != v ? __builtin_inf() : fabs(v);
+          if (better(key, pos_q[q], a, p)) { a = key; p = pos_q[q]; r = rr; }
         }
       }
-      wave_pick(a, p, r);   // every lane now holds the local winner
-      if (nwg == 1) {
-        if (r < 0) {  // cannot happen for ncols <= nrows; leave rather than index with -1
-          if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
-        } else {
+      wave_argbest(a, p, r);
+      // the candidate's multiplier of step j-1 (row r's lane holds it)
+      double lmr = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q)
+        if (r >= 0 && r == lane + 64 * q) lmr = mlt_q[q];
+      const double lm = upd1 ? lane_bcast(lmr, r >= 0 ? (r & 63) : 0) : 0.0;
+      const double cpiv = r >= 0 ? Ts[(int64_t)j * R + r] : 0.0;
+      const double cv1 = (r >= 0 && j + 1 < ncols) ? Ts[(int64_t)(j + 1) * R + r] : 0.0;
+      if (nwg > 1) {
+        unsigned long long* rec = (unsigned long long*)(base + (int64_t)w * rec_stride);
+        unsigned long long* body = rec + kHdrWords;
+        if (r >= 0)
+          for (int c = j + 2 + lane; c < ncols; c += 64)
+            put64(body + 2 * c, tag, dbits(Ts[(int64_t)c * R + r]));
         if (lane == 0) {
-          sh_win_wg = 0;
-          sh_win_row = row0 + r;
-          sh_win_pos = p;
-        }
-        for (int c = j + lane; c < ncols; c += 64) urow[c] = Ts[(int64_t)c * R + r];
+          put64(rec + 0, tag, dbits(a));
+          put32(rec + 2, tag, (unsigned)p);
+          put32(rec + 3, tag, (unsigned)(r >= 0 ? row0 + r : -1));
+          put64(rec + 4, tag, dbits(cpiv));
+          put64(rec + 6, tag, dbits(lm));
+          put64(rec + 8, tag, dbits(cv1));
         }
       } else {
-        char* base = xch + (int64_t)(j & 1) * nwg * rec_stride;
-        {
-          char* rec = base + (int64_t)w * rec_stride;
-          double* rrow = (double*)(rec + sizeof(RecHeader));
-          for (int c = j + lane; c < ncols; c += 64) rrow[c] = r >= 0 ? Ts[(int64_t)c * R + r] : 0.0;
-          if (lane == 0) {
-            RecHeader* h = (RecHeader*)rec;
-            h->absval = a;
-            h->pos = p;
-            h->row = r >= 0 ? row0 + r : -1;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          if (lane == 0) st_agent(&((RecHeader*)rec)->tag, (unsigned long long)(j + 1));
+        if (r >= 0)
+          for (int c = j + 2 + lane; c < ncols; c += 64) lbody[sj * ncols + c] = Ts[(int64_t)c * R + r];
+        if (lane == 0) {
+          sh_cr = r; sh_cp = p; sh_cpiv = cpiv; sh_clm = lm; sh_cv1 = cv1;
+          if (r < 0) { st_agent_i(fail, 1); sh_stop = 1; }  // cannot happen for ncols <= nrows
         }
-        // wait for every record of this step
-        const int nq = (nwg + 63) / 64;
-        unsigned seen = 0, need = 0;
-        for (int q = 0; q < nq; ++q)
-          if (lane + 64 * q < nwg) need |= 1u << q;
-        bool stop = false;
-        while (true) {
-          for (int q = 0; q < nq; ++q) {
-            if ((need >> q & 1u) && !(seen >> q & 1u)) {
-              const RecHeader* h = (const RecHeader*)(base + (int64_t)(lane + 64 * q) * rec_stride);
-              if (ld_agent(&h->tag) == (unsigned long long)(j + 1)) seen |= 1u << q;
+      }
+    } else if (upd1) {
+      // ---- (2a) waves 1-7: U(j-1, c) for c > j from the step j-1 winner's row --
+      const int t = tid - 64;
+      const double lmw = sh_lm[sp];
+      const unsigned long long* pbody = nullptr;
+      if (nwg > 1)
+        pbody = (const unsigned long long*)(xch + ((int64_t)sp * nwg + sh_bw[sp]) * rec_stride) +
+                kHdrWords;
+      bool stop = false;
+      for (int c = j + 1 + t; c < ncols; c += kThreads - 64) {
+        double b;
+        if (nwg > 1) {
+          unsigned long long lo, hi;
+          while (true) {
+            lo = ld_agent(pbody + 2 * c);
+            hi = ld_agent(pbody + 2 * c + 1);
+            if (tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j)) break;
+            if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+              stop = true;
+              break;
             }
           }
-          const bool mine_done = seen == need;
-          if (__all(mine_done)) break;
+          if (stop) break;
+          b = bitsd(join64(lo, hi));
+        } else {
+          b = lbody[sp * ncols + c];
+        }
+        Up[c] = upd2 ? __fma_rn(-lmw, Uj[c], b) : b;
+      }
+      if (stop) { st_agent_i(fail, 1); sh_stop = 1; }
+    }
+    lds_barrier();  // B1: candidate published; U(j-1, .) complete
+    if (sh_stop) break;
+
+    if (wave == 0) {
+      // ---- (3) exchange: wait for every header, select the winner ---------------
+      int win_row = -1, win_pos = INT_MAX, bw = -1;
+      double piv = 0.0, wlm = 0.0, wv1 = 0.0;
+      bool stop = false;
+      if (nwg > 1) {
+        // every lane owns the records lane, lane + 64, ... (nwg <= 256) and
+        // reads whole headers, so the winner's fields need no second trip
+        const int nq = (nwg + 63) / 64;
+        double qa[4], qpiv[4], qlm[4], qv1[4];
+        int qp[4], qrow[4];
+        unsigned seen = 0, need = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          qa[q] = -1.0; qp[q] = INT_MAX; qrow[q] = -1; qpiv[q] = 0.0; qlm[q] = 0.0; qv1[q] = 0.0;
+          if (q < nq && lane + 64 * q < nwg) need |= 1u << q;
+        }
+        while (true) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if ((need >> q & 1u) && !(seen >> q & 1u)) {
+              const unsigned long long* h =
+                  (const unsigned long long*)(base + (int64_t)(lane + 64 * q) * rec_stride);
+              unsigned long long x[kHdrWords];
+#pragma unroll
+              for (int t = 0; t < kHdrWords; ++t) x[t] = ld_agent(h + t);
+              bool ok = true;
+#pragma unroll
+              for (int t = 0; t < kHdrWords; ++t) ok = ok && tagged(x[t], tag);
+              if (ok) {
+                seen |= 1u << q;
+                qa[q] = bitsd(join64(x[0], x[1]));
+                qp[q] = (int)(unsigned)x[2];
+                qrow[q] = (int)(unsigned)x[3];
+                qpiv[q] = bitsd(join64(x[4], x[5]));
+                qlm[q] = bitsd(join64(x[6], x[7]));
+                qv1[q] = bitsd(join64(x[8], x[9]));
+              }
+            }
+          }
+          if (__all(seen == need)) break;
           if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
             stop = true;
             break;
           }
         }
-        if (stop) {
-          if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
-        } else {
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          double ba = -1.0; int bp = INT_MAX, br = -1, bw = -1;
-          for (int q = 0; q < nq; ++q) {
-            const int i = lane + 64 * q;
-            if (i < nwg) {
-              const RecHeader* h = (const RecHeader*)(base + (int64_t)i * rec_stride);
-              const double a2 = h->absval;
-              const int p2 = h->pos, r2 = h->row;
-              if (a2 > ba || (a2 == ba && p2 < bp)) { ba = a2; bp = p2; br = r2; bw = i; }
-            }
-          }
+        if (!stop) {
+          double ba = -1.0; int bp = INT_MAX;
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const double a2 = __shfl_xor(ba, off, 64);
-            const int p2 = __shfl_xor(bp, off, 64);
-            const int r2 = __shfl_xor(br, off, 64);
-            const int w2 = __shfl_xor(bw, off, 64);
-            if (a2 > ba || (a2 == ba && p2 < bp)) { ba = a2; bp = p2; br = r2; bw = w2; }
-          }
-          if (bw < 0 || br < 0) {  // no candidate anywhere: cannot happen for ncols <= nrows
-            if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
+          for (int q = 0; q < 4; ++q)
+            if ((need >> q & 1u) && (bw < 0 || better(qa[q], qp[q], ba, bp))) {
+              ba = qa[q]; bp = qp[q]; bw = lane + 64 * q;
+            }
+          wave_argbest(ba, bp, bw);
+          if (bw < 0 || ba < 0.0) {
+            stop = true;  // no candidate anywhere: cannot happen for ncols <= nrows
           } else {
-            if (lane == 0) { sh_win_wg = bw; sh_win_row = br; sh_win_pos = bp; }
-            const double* wrow =
-                (const double*)(base + (int64_t)bw * rec_stride + sizeof(RecHeader));
-            for (int c = j + lane; c < ncols; c += 64) urow[c] = wrow[c];
+            // the winner's header fields live in lane bw % 64, slot bw / 64
+            int hrow = -1; double hpiv = 0.0, hlm = 0.0, hv1 = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (bw == lane + 64 * q) { hrow = qrow[q]; hpiv = qpiv[q]; hlm = qlm[q]; hv1 = qv1[q]; }
+            const int src = bw & 63;
+            win_row = __builtin_amdgcn_readlane(hrow, src);
+            piv = lane_bcast(hpiv, src);
+            wlm = lane_bcast(hlm, src);
+            wv1 = lane_bcast(hv1, src);
+            win_pos = bp;
+            if (win_row < 0) stop = true;
           }
         }
+      } else {
+        win_row = row0 + sh_cr;
+        win_pos = sh_cp;
+        piv = sh_cpiv; wlm = sh_clm; wv1 = sh_cv1;
+        bw = 0;
+      }
+      if (stop) {
+        if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
+      } else {
+        // ---- (4) bookkeeping and multipliers of step j --------------------------
+        const int wr = win_row - row0;  // local index if the winner is ours
+        const bool big_piv = fabs(piv) >= 2.2250738585072014e-308;  // smallest normal
+        const double rpiv = 1.0 / piv;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = lane + 64 * q;
+          if (st_q[q] == -1) continue;
+          if (r == wr) {
+            pos_q[q] = j;
+            st_q[q] = j;
+            step_s[r] = j;
+            mlt_q[q] = 0.0;
+          } else {
+            if (pos_q[q] == j) pos_q[q] = win_pos;  // row at position j moves away
+            double m = 0.0;
+            if (st_q[q] == kNone && piv != 0.0) {
+              // multiply by the reciprocal pivot unless it would overflow
+              m = big_piv ? val_q[q] * rpiv : val_q[q] / piv;
+              Ts[(int64_t)j * R + r] = m;
+            }
+            mlt_q[q] = m;
+          }
+        }
+        if (lane == 0) {
+          Uj[j] = piv;
+          sh_piv[sj] = piv;
+          sh_lm[sj] = wlm;
+          sh_v1[sj] = wv1;
+          sh_bw[sj] = bw;
+          pivrow_s[j] = win_row;
+          ipiv_s[j] = win_pos;
+        }
+        if (piv == 0.0 && info == 0) info = j + 1;
+      }
+    } else if (upd1) {
+      // ---- (2b) waves 1-7: rank-one update of step j-1 on columns j+1.. --------
+      // Rows still active after step j-1 (step_s > j-1).  A row being chosen
+      // at step j right now has step_s kNone or j: included either way, as it
+      // must be (its U row is its values through step j-1).
+      double m[RPL];
+      bool act[RPL];
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        const int r = lane + 64 * q;
+        act[q] = r < nr && step_s[r] > j - 1;
+        m[q] = act[q] ? Ts[(int64_t)(j - 1) * R + r] : 0.0;
+      }
+      constexpr int kBulkWaves = kThreads / 64 - 1;
+      constexpr int kU = 4;  // columns per iteration: all loads issued before any FMA
+      int c = j + 1 + (wave - 1);
+      for (; c + (kU - 1) * kBulkWaves < ncols; c += kU * kBulkWaves) {
+        double u[kU], x[kU][RPL];
+#pragma unroll
+        for (int t = 0; t < kU; ++t) {
+          u[t] = Up[c + t * kBulkWaves];
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+            x[t][q] = Ts[(int64_t)(c + t * kBulkWaves) * R + lane + 64 * q];
+        }
+#pragma unroll
+        for (int t = 0; t < kU; ++t)
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+            if (act[q])
+              Ts[(int64_t)(c + t * kBulkWaves) * R + lane + 64 * q] = __fma_rn(-m[q], u[t], x[t][q]);
+      }
+      for (; c < ncols; c += kBulkWaves) {
+        const double u = Up[c];
+        double* col = Ts + (int64_t)c * R + lane;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q)
+          if (act[q]) col[64 * q] = __fma_rn(-m[q], u, col[64 * q]);
       }
     }
-    __syncthreads();
+    lds_barrier();  // B0 of the next step
     if (sh_stop) break;
-
-    // ---- (c) positions, pivot bookkeeping, multipliers ------------------------
-    const int win_row = sh_win_row, win_pos = sh_win_pos;
-    const double piv = urow[j];
-    const int wr = win_row - row0;  // local index if the winner is ours
-    for (int r = tid; r < nr; r += kThreads) {
-      const bool is_win = (r == wr);
-      if (is_win) {
-        pos_s[r] = j;
-        step_s[r] = j;
-      } else if (pos_s[r] == j) {
-        pos_s[r] = win_pos;  // the row at position j moves to the winner's position
-      }
-      double mlt = 0.0;
-      if (step_s[r] == kNone && piv != 0.0) {
-        mlt = Ts[(int64_t)j * R + r] / piv;
-        Ts[(int64_t)j * R + r] = mlt;
-      }
-      mult[r] = mlt;
-    }
-    if (w == 0 && tid == 0) {
-      piv_row_out[j] = win_row;
-      ipiv_out[j] = win_pos;
-      if (piv == 0.0 && sh_info == 0) sh_info = j + 1;
-    }
-    __syncthreads();
-
-    // ---- (d) rank-one update of the trailing columns ---------------------------
-    const int width = ncols - j - 1;
-    if (piv != 0.0 && width > 0) {
-      const int total = nr * width;
-      for (int idx = tid; idx < total; idx += kThreads) {
-        const int r = idx % nr, c = j + 1 + idx / nr;
-        if (step_s[r] == kNone) Ts[(int64_t)c * R + r] -= mult[r] * urow[c];
-      }
-    }
-    __syncthreads();
   }
 
   // ---- write back -------------------------------------------------------------
+  if (wave == 0) {
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int r = lane + 64 * q;
+      if (r < nr) {
+        pos_s[r] = pos_q[q];
+        step_s[r] = st_q[q];
+      }
+    }
+    if (lane == 0 && w == 0) *info_out = info;
+  }
+  __syncthreads();
   if (rs == 1) {
     for (int idx = tid; idx < R * ncols; idx += kThreads) {
       const int r = idx % R, c = idx / R;
@@ -244,13 +488,21 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
     pos_out[row0 + r] = pos_s[r];
     rstep_out[row0 + r] = step_s[r] == kNone ? ncols : step_s[r];
   }
-  if (w == 0 && tid == 0) *info_out = sh_info;
+  if (w == 0)
+    for (int c = tid; c < ncols; c += kThreads) {
+      piv_row_out[c] = pivrow_s[c];
+      ipiv_out[c] = ipiv_s[c];
+    }
 }
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t lds_for(int R, int ncols) {
-  return (size_t)R * ncols * 8 + (size_t)ncols * 8 + (size_t)R * 8 + (size_t)R * 8;
+  return (size_t)R * ncols * 8 + (size_t)4 * ncols * 8 + (size_t)R * 8 + (size_t)ncols * 8;
+}
+
+int64_t rec_stride_for(int ncols) {
+  return (8 * (int64_t)kHdrWords + 16 * (int64_t)ncols + 127) / 128 * 128;
 }
 
 }  // namespace
@@ -261,32 +513,28 @@ PanelPlan panel_plan(int nrows, int ncols, int device_cus, int /*max_wg_per_cu_h
   if (nrows <= 0 || ncols <= 0 || ncols > nrows) return p;
   // largest row block that fits the LDS (leaving room for static shared data)
   const size_t budget = kLdsLimit - 1024;
-  int R = (int)((budget - (size_t)ncols * 8) / ((size_t)ncols * 8 + 16));
-  if (R > 4096) R = 4096;
+  if ((size_t)5 * ncols * 8 >= budget) return p;
+  int R = (int)((budget - (size_t)5 * ncols * 8) / ((size_t)ncols * 8 + 8));
+  if (R > 512) R = 512;  // at most 8 rows per lane
   if (R < 1) return p;
   int nwg = (nrows + R - 1) / R;
   // spread the rows evenly over that many workgroups
   R = (nrows + nwg - 1) / nwg;
   nwg = (nrows + R - 1) / R;
-  // one workgroup per CU is what the LDS footprint guarantees; 32 slots per
-  // lane bound the exchange width
-  if (nwg > device_cus || nwg > 64 * 32) return p;
+  // one workgroup per CU is what the LDS footprint guarantees; four records
+  // per lane bound the exchange width
+  if (nwg > device_cus || nwg > 256) return p;
   p.rows_per_wg = R;
   p.nwg = nwg;
   p.lds_bytes = lds_for(R, ncols);
-  const int64_t stride = ((int64_t)sizeof(RecHeader) + 8 * (int64_t)ncols + 127) / 128 * 128;
-  p.xch_bytes = (size_t)(2 * (int64_t)nwg * stride);
+  p.xch_bytes = (size_t)(2 * (int64_t)nwg * rec_stride_for(ncols));
   p.ok = true;
   return p;
 }
 
 hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s) {
   if (!plan.ok) return hipErrorInvalidValue;
-  const int64_t stride = ((int64_t)sizeof(RecHeader) + 8 * (int64_t)d.ncols + 127) / 128 * 128;
-  hipError_t e = hipFuncSetAttribute((const void*)panel_lu_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)plan.lds_bytes);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   // clear the exchange tags of both parities
   if (plan.nwg > 1) {
     e = launch_fill_u32((uint32_t*)d.xch, plan.xch_bytes / 4, 0u, s);
@@ -298,11 +546,17 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
   int* pos = d.pos; int* rstep = d.rstep; int* piv_row = d.piv_row; int* ipiv = d.ipiv;
   int* info = d.info; int* fail = d.fail; char* xch = (char*)d.xch;
   long long tmo = d.timeout_ticks;
-  int64_t rec_stride = stride;
+  int64_t rec_stride = rec_stride_for(d.ncols);
   void* args[] = {&X, &rs, &cs, &nrows, &ncols, &R, &nwg, &pos, &rstep, &piv_row, &ipiv,
                   &info, &fail, &xch, &rec_stride, &tmo};
-  return hipLaunchCooperativeKernel((const void*)panel_lu_kernel, dim3(nwg), dim3(kThreads), args,
-                                    (unsigned)plan.lds_bytes, s);
+  const void* fn = R <= 64 ? (const void*)panel_lu_kernel<1>
+                 : R <= 128 ? (const void*)panel_lu_kernel<2>
+                 : R <= 256 ? (const void*)panel_lu_kernel<4>
+                            : (const void*)panel_lu_kernel<8>;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
+  if (e != hipSuccess) return e;
+  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kThreads), args, (unsigned)plan.lds_bytes,
+                                    s);
 }
 
 }  // namespace rlu

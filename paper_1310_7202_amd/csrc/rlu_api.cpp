@@ -26,8 +26,28 @@
 #include <cstring>
 #include <new>
 
+// Phases of rlu_factor that the timing facility reports.
+enum Phase {
+  PH_GAUSSIAN = 0, PH_SKETCH, PH_PANEL_Y, PH_GRAM, PH_GRAM_INV, PH_PROJECT, PH_SOLVE,
+  PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_COUNT
+};
+static const char* const kPhaseNames[PH_COUNT] = {
+    "gaussian", "sketch_gemm", "panel_lu_y", "gram_gemm", "gram_inverse", "project_gemm",
+    "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm"};
+
+struct TimingSlot {
+  hipEvent_t ev[PH_COUNT][2] = {};
+  bool used[PH_COUNT] = {};
+  bool valid = false;
+};
+
 struct rlu_handle_s {
   int device = 0;
+  bool timing = false;
+  int ring_next = 0;        // next slot to fill
+  int ring_filled = 0;      // number of valid slots
+  TimingSlot ring[RLU_TIMING_RING];
+  TimingSlot* cur = nullptr;
   int cus = 256;
   hipStream_t side = nullptr;    // second stream for the Gram inverse
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -48,17 +68,8 @@ struct Layout {
   size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
   size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0, flags = 0, xch = 0;
   size_t total = 0;
-  int ksplit_gram = 1, ksplit_y = 1;
   PanelPlan py{}, pb{};
 };
-
-// Split K of a GEMM when its output alone cannot fill the device.
-int suggest_ksplit(int64_t M, int64_t N, int64_t K, int cus) {
-  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
-  int ks = 1;
-  while (tiles * ks * 2 <= (int64_t)cus * 2 && K / (ks * 2) >= 512 && ks < 32) ks *= 2;
-  return ks;
-}
 
 bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
@@ -70,9 +81,13 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   const size_t d = sizeof(double);
   take(L.G, pb.G ? 0 : (size_t)n * l * d);
   take(L.Y, (size_t)m * l * d);
-  L.ksplit_gram = suggest_ksplit(k, k, m, cus);
-  L.ksplit_y = 1;
-  take(L.part, gemm_partial_elems(k, k, L.ksplit_gram) * d);
+  // one partial-sum area, sized for the largest automatic split-K product
+  size_t part = gemm_auto_partial_elems(m, l, n, OpA::Plain);
+  part = std::max(part, gemm_auto_partial_elems(k, k, m, OpA::LvT));
+  part = std::max(part, gemm_auto_partial_elems(k, n, m, OpA::LvT));
+  part = std::max(part, gemm_auto_partial_elems(k, n, k, OpA::Plain));
+  part = std::max(part, gemm_auto_partial_elems(m, k, k, OpA::Lv));
+  take(L.part, part * d);
   take(L.S, (size_t)k * k * d);
   take(L.C, (size_t)k * n * d);
   take(L.Bst, (size_t)k * n * d);
@@ -158,6 +173,37 @@ rlu_status_t ensure_ws(rlu_handle_s* h, size_t bytes) {
 template <typename P>
 P* at(void* base, size_t off) { return (P*)((char*)base + off); }
 
+// Event pair around a phase when timing is on (recorded on the phase's stream).
+struct PhaseScope {
+  rlu_handle_s* h; int id; hipStream_t s; bool on;
+  PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
+      : h(h_), id(id_), s(s_), on(h_->timing && h_->cur) {
+    if (on) {
+      h->cur->used[id] = true;
+      hipEventRecord(h->cur->ev[id][0], s);
+    }
+  }
+  ~PhaseScope() {
+    if (on) hipEventRecord(h->cur->ev[id][1], s);
+  }
+};
+
+rlu_status_t begin_timing(rlu_handle_s* h) {
+  h->cur = nullptr;
+  if (!h->timing) return RLU_OK;
+  TimingSlot& t = h->ring[h->ring_next];
+  for (int p = 0; p < PH_COUNT; ++p) {
+    for (int e = 0; e < 2; ++e)
+      if (!t.ev[p][e] && hipEventCreate(&t.ev[p][e]) != hipSuccess) return RLU_ERR_DEVICE;
+    t.used[p] = false;
+  }
+  t.valid = true;
+  h->cur = &t;
+  h->ring_next = (h->ring_next + 1) % RLU_TIMING_RING;
+  if (h->ring_filled < RLU_TIMING_RING) ++h->ring_filled;
+  return RLU_OK;
+}
+
 rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buffers_t& io,
                          hipStream_t s, const Layout& Ly) {
   const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
@@ -186,6 +232,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   int64_t ldg = pb.ldg;
   if (!G) {
     double* Gw = at<double>(ws, Ly.G);
+    PhaseScope ph(h, PH_GAUSSIAN, s);
     HIP_TRY(launch_gaussian<double>(Gw, n, n, l, pb.seed, s));
     G = Gw;
     ldg = n;
@@ -197,7 +244,8 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.A = io.A; d.lda = io.lda; d.opa = OpA::Plain;
     d.B = G; d.ldb = ldg; d.opb = OpB::Plain;
     d.C = Y; d.ldc = m;
-    d.ksplit = 1;
+    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    PhaseScope ph(h, PH_SKETCH, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
   if (diag && io.Y) HIP_TRY(launch_copy2d<double>(Y, m, (double*)io.Y, io.ldy, m, l, s));
@@ -207,6 +255,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.X = Y; d.rs = 1; d.cs = m; d.nrows = (int)m; d.ncols = (int)l;
     d.pos = pos_y; d.rstep = rstep_y; d.piv_row = piv_y; d.ipiv = ipiv_y;
     d.info = flags + 0; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    PhaseScope ph(h, PH_PANEL_Y, s);
     HIP_TRY(launch_panel_lu(d, Ly.py, s));
   }
   if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
@@ -217,12 +266,16 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
     d.B = Y; d.ldb = m; d.opb = OpB::Lv; d.bstep = rstep_y;
     d.C = S; d.ldc = k;
-    d.ksplit = Ly.ksplit_gram; d.partial = at<void>(ws, Ly.part);
+    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    PhaseScope ph(h, PH_GRAM, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
   HIP_TRY(hipEventRecord(h->ev_fork, s));
   HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  HIP_TRY(launch_spd_inverse(S, k, h->side));
+  {
+    PhaseScope ph(h, PH_GRAM_INV, h->side);
+    HIP_TRY(launch_spd_inverse(S, k, h->side));
+  }
   HIP_TRY(hipEventRecord(h->ev_join, h->side));
   {
     GemmDesc d{};
@@ -230,7 +283,8 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
     d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
     d.C = C; d.ldc = k;
-    d.ksplit = 1;
+    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    PhaseScope ph(h, PH_PROJECT, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
   HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
@@ -241,6 +295,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.B = C; d.ldb = k; d.opb = OpB::Plain;
     d.C = Bst; d.ldc = k;
     d.ksplit = 1;
+    PhaseScope ph(h, PH_SOLVE, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
   if (diag && io.B) HIP_TRY(launch_copy2d<double>(Bst, k, (double*)io.B, io.ldb, k, n, s));
@@ -250,15 +305,19 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.X = Bst; d.rs = k; d.cs = 1; d.nrows = (int)n; d.ncols = (int)k;
     d.pos = pos_b; d.rstep = rstep_b; d.piv_row = piv_b; d.ipiv = ipiv_b;
     d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    PhaseScope ph(h, PH_PANEL_B, s);
     HIP_TRY(launch_panel_lu(d, Ly.pb, s));
   }
   if (diag && io.qpiv) HIP_TRY(launch_copy_i32(ipiv_b, io.qpiv, k, s));
-  HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
-  HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
-  // Step 8: U = U_b
-  HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
-  // Step 7: L = L_y L_b, rows written at their positions
-  HIP_TRY(launch_build_lb<double>(Bst, k, k, piv_b, Lb, s));
+  {
+    PhaseScope ph(h, PH_ASSEMBLE, s);
+    HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
+    HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
+    // Step 8: U = U_b
+    HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
+    // Step 7 needs L_b
+    HIP_TRY(launch_build_lb<double>(Bst, k, k, piv_b, Lb, s));
+  }
   {
     GemmDesc d{};
     d.M = m; d.N = k; d.K = k;
@@ -267,6 +326,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = io.L; d.ldc = io.ldl;
     d.rowmap = pos_y;
     d.ksplit = 1;
+    PhaseScope ph(h, PH_FORM_L, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
   HIP_TRY(launch_info_merge(flags + 0, flags + 1, flags + 2, io.info, s));
@@ -310,6 +370,10 @@ rlu_status_t rlu_destroy(rlu_handle_t h) {
   hipSetDevice(h->device);
   hipDeviceSynchronize();
   if (h->ws) hipFree(h->ws);
+  for (auto& t : h->ring)
+    for (int p = 0; p < PH_COUNT; ++p)
+      for (int e = 0; e < 2; ++e)
+        if (t.ev[p][e]) hipEventDestroy(t.ev[p][e]);
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
   if (h->ev_join) hipEventDestroy(h->ev_join);
   if (h->side) hipStreamDestroy(h->side);
@@ -341,9 +405,37 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffe
   hipGetDevice(&prev);
   if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RLU_ERR_DEVICE;
   st = ensure_ws(h, L.total);
+  if (st == RLU_OK) st = begin_timing(h);
   if (st == RLU_OK) st = factor_fp64(h, *pb, *io, (hipStream_t)stream, L);
   if (prev != h->device) hipSetDevice(prev);
   return st;
+}
+
+rlu_status_t rlu_set_timing(rlu_handle_t h, int enable) {
+  if (!h) return RLU_ERR_INVALID_ARG;
+  h->timing = enable != 0;
+  if (!h->timing) { h->ring_filled = 0; h->ring_next = 0; }
+  return RLU_OK;
+}
+
+rlu_status_t rlu_phase_times(rlu_handle_t h, int back, float* ms, const char** names, int cap,
+                             int* count) {
+  if (!h || back < 0 || back >= h->ring_filled || cap < 0) return RLU_ERR_INVALID_ARG;
+  const int slot = ((h->ring_next - 1 - back) % RLU_TIMING_RING + RLU_TIMING_RING) % RLU_TIMING_RING;
+  TimingSlot& t = h->ring[slot];
+  if (!t.valid) return RLU_ERR_INVALID_ARG;
+  for (int p = 0; p < PH_COUNT && p < cap; ++p) {
+    float v = 0.f;
+    if (t.used[p]) {
+      if (hipEventSynchronize(t.ev[p][1]) != hipSuccess ||
+          hipEventElapsedTime(&v, t.ev[p][0], t.ev[p][1]) != hipSuccess)
+        return RLU_ERR_DEVICE;
+    }
+    if (ms) ms[p] = v;
+    if (names) names[p] = kPhaseNames[p];
+  }
+  if (count) *count = PH_COUNT;
+  return RLU_OK;
 }
 
 rlu_status_t rlu_check_info(const int32_t info_host[3]) {

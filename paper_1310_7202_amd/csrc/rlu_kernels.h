@@ -30,12 +30,16 @@ struct GemmDesc {
   const void* B; int64_t ldb; OpB opb; const int* bstep;
   void* C; int64_t ldc;
   const int* rowmap;   // optional: output row i goes to C row rowmap[i]
-  int ksplit;          // >1: partial sums to `partial`, then a fixed-order sum
-  void* partial;       // ksplit * M * N elements of workspace
+  int ksplit;          // 0: automatic split-K (uses `partial` if given), 1: none,
+                       // >1: that many partial sums, added in a fixed order
+  void* partial;       // partial-sum workspace (gemm_auto_partial_elems elements)
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
 size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit);
+size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa);
+// Tuning override of the tile shape (index into the compiled shapes; -1 = automatic).
+void gemm_force_config(int id);
 
 // ----- Pivoted LU of a tall matrix, rows spread over workgroups (panel_lu.hip)
 struct PanelDesc {
