@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy a 256 MiB buffer once (a plain copy "
+                         "kernel of known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -204,6 +207,15 @@ def main():
                 "algorithmic_flops_per_launch": flops_sketch}
     flops_total = (2.0 * m * n * (l + k) + m * l * l - l ** 3 / 3.0 + 3.0 * m * k * k + k ** 3
                    + n * k * k - k ** 3 / 3.0 + m * k * k)
+
+    if args.calibrate_copy:
+        src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 256 MiB read + 256 MiB written")
+        del src, dst
 
     rel_res = power_residual(A, out.L, out.U, out.p, out.q)
     log(f"relative residual {rel_res:.3e}")

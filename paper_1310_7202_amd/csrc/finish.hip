@@ -65,6 +65,18 @@ __global__ void __launch_bounds__(256) build_u_kernel(const TI* __restrict__ Bst
   }
 }
 
+template <typename TI, typename TO>
+__global__ void __launch_bounds__(256) convert2d_kernel(const TI* __restrict__ src, int64_t lds,
+                                                        TO* __restrict__ dst, int64_t ldd,
+                                                        int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, j = e / rows;
+    dst[i + j * ldd] = (TO)src[i + j * lds];
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) copy2d_kernel(const T* __restrict__ src, int64_t lds,
                                                      T* __restrict__ dst, int64_t ldd,
@@ -134,6 +146,26 @@ hipError_t launch_build_u(const T* Bst, int64_t ldb, int64_t k, int64_t n, const
 template hipError_t launch_build_u<double>(const double*, int64_t, int64_t, int64_t, const int*,
                                            const int*, const int64_t*, double*, int64_t,
                                            hipStream_t);
+
+hipError_t launch_build_u_f32(const double* Bst, int64_t ldb, int64_t k, int64_t n,
+                              const int* piv_row, const int* rstep, const int64_t* q, float* U,
+                              int64_t ldu, hipStream_t s) {
+  hipLaunchKernelGGL((build_u_kernel<double, float>), dim3(grid_for(k * n)), dim3(256), 0, s, Bst,
+                     ldb, k, n, piv_row, rstep, q, U, ldu);
+  return hipGetLastError();
+}
+
+template <typename TI, typename TO>
+hipError_t launch_convert2d(const TI* src, int64_t lds, TO* dst, int64_t ldd, int64_t rows,
+                            int64_t cols, hipStream_t s) {
+  hipLaunchKernelGGL((convert2d_kernel<TI, TO>), dim3(grid_for(rows * cols)), dim3(256), 0, s,
+                     src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+template hipError_t launch_convert2d<double, float>(const double*, int64_t, float*, int64_t,
+                                                    int64_t, int64_t, hipStream_t);
+template hipError_t launch_convert2d<float, double>(const float*, int64_t, double*, int64_t,
+                                                    int64_t, int64_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,

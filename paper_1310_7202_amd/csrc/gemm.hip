@@ -311,7 +311,20 @@ size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa) {
 
 void gemm_force_config(int id) { g_force_cfg = (id >= 0 && id < CFG_COUNT) ? id : -1; }
 
+template <typename TA, typename TB, typename TC, typename TO>
+hipError_t launch_gemm_t(const GemmDesc& d, hipStream_t s) {
+  return dispatch<TA, TB, TC, TO>(d, s);
+}
+
 // FP64 path: every operand and the output in FP64.
+template hipError_t launch_gemm_t<double, double, double, double>(const GemmDesc&, hipStream_t);
+// FP32 path: FP32 MFMA on FP32 storage (A, G) or on Lv rounded to FP32;
+// results widened to FP64 for the pivoted LUs and the Gram solve.
+template hipError_t launch_gemm_t<float, float, float, double>(const GemmDesc&, hipStream_t);
+template hipError_t launch_gemm_t<double, float, float, double>(const GemmDesc&, hipStream_t);
+// FP64 arithmetic, FP32 output (L of the FP32 path).
+template hipError_t launch_gemm_t<double, double, double, float>(const GemmDesc&, hipStream_t);
+
 template <>
 hipError_t launch_gemm<double>(const GemmDesc& d, hipStream_t s) {
   return dispatch<double, double, double, double>(d, s);

@@ -25,6 +25,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 // Phases of rlu_factor that the timing facility reports.
 enum Phase {
@@ -79,7 +80,8 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
     off = align_up(off + std::max<size_t>(bytes, 1));
   };
   const size_t d = sizeof(double);
-  take(L.G, pb.G ? 0 : (size_t)n * l * d);
+  const size_t sa = pb.dtype == RLU_F32 ? sizeof(float) : sizeof(double);
+  take(L.G, pb.G ? 0 : (size_t)n * l * sa);
   take(L.Y, (size_t)m * l * d);
   // one partial-sum area, sized for the largest automatic split-K product
   size_t part = gemm_auto_partial_elems(m, l, n, OpA::Plain);
@@ -120,6 +122,8 @@ rlu_status_t validate(const rlu_problem_t* pb) {
       if (pb->dtype != RLU_F64) return RLU_ERR_INVALID_ARG;
       break;
     case RLU_PREC_FP32:
+      if (pb->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
+      break;
     case RLU_PREC_MIXED_BF16:
     case RLU_PREC_MIXED_FP16:
       if (pb->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
@@ -204,8 +208,13 @@ rlu_status_t begin_timing(rlu_handle_s* h) {
   return RLU_OK;
 }
 
-rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buffers_t& io,
+// The FP64 path (T = double) and the FP32 path (T = float: FP32 storage of
+// A, G, L, U and FP32 MFMA for the two products with A).  The pivoted LUs,
+// the Gram matrix, its inverse and B are FP64 in both.
+template <typename T>
+rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buffers_t& io,
                          hipStream_t s, const Layout& Ly) {
+  constexpr bool kF32 = std::is_same<T, float>::value;
   const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
   void* ws = h->ws;
   double* Y = at<double>(ws, Ly.Y);
@@ -228,12 +237,12 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   HIP_TRY(launch_fill_u32((uint32_t*)flags, 16, 0u, s));
 
   // Step 1
-  const double* G = (const double*)pb.G;
+  const T* G = (const T*)pb.G;
   int64_t ldg = pb.ldg;
   if (!G) {
-    double* Gw = at<double>(ws, Ly.G);
+    T* Gw = at<T>(ws, Ly.G);
     PhaseScope ph(h, PH_GAUSSIAN, s);
-    HIP_TRY(launch_gaussian<double>(Gw, n, n, l, pb.seed, s));
+    HIP_TRY(launch_gaussian<T>(Gw, n, n, l, pb.seed, s));
     G = Gw;
     ldg = n;
   }
@@ -246,9 +255,12 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     PhaseScope ph(h, PH_SKETCH, s);
-    HIP_TRY(launch_gemm<double>(d, s));
+    HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
   }
-  if (diag && io.Y) HIP_TRY(launch_copy2d<double>(Y, m, (double*)io.Y, io.ldy, m, l, s));
+  if (diag && io.Y) {
+    if (kF32) HIP_TRY((launch_convert2d<double, float>(Y, m, (float*)io.Y, io.ldy, m, l, s)));
+    else HIP_TRY(launch_copy2d<double>(Y, m, (double*)io.Y, io.ldy, m, l, s));
+  }
   // Step 3 (+ Step 4: only the first k columns of the unit-lower factor are used)
   {
     PanelDesc d{};
@@ -285,7 +297,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = C; d.ldc = k;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     PhaseScope ph(h, PH_PROJECT, s);
-    HIP_TRY(launch_gemm<double>(d, s));
+    HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
   }
   HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {
@@ -298,7 +310,10 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     PhaseScope ph(h, PH_SOLVE, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
-  if (diag && io.B) HIP_TRY(launch_copy2d<double>(Bst, k, (double*)io.B, io.ldb, k, n, s));
+  if (diag && io.B) {
+    if (kF32) HIP_TRY((launch_convert2d<double, float>(Bst, k, (float*)io.B, io.ldb, k, n, s)));
+    else HIP_TRY(launch_copy2d<double>(Bst, k, (double*)io.B, io.ldb, k, n, s));
+  }
   // Step 6 through the LU of B^T
   {
     PanelDesc d{};
@@ -314,7 +329,10 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
     HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
     // Step 8: U = U_b
-    HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
+    if (kF32)
+      HIP_TRY(launch_build_u_f32(Bst, k, k, n, piv_b, rstep_b, io.q, (float*)io.U, io.ldu, s));
+    else
+      HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
     // Step 7 needs L_b
     HIP_TRY(launch_build_lb<double>(Bst, k, k, piv_b, Lb, s));
   }
@@ -327,7 +345,7 @@ rlu_status_t factor_fp64(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.rowmap = pos_y;
     d.ksplit = 1;
     PhaseScope ph(h, PH_FORM_L, s);
-    HIP_TRY(launch_gemm<double>(d, s));
+    HIP_TRY((launch_gemm_t<double, double, double, T>(d, s)));
   }
   HIP_TRY(launch_info_merge(flags + 0, flags + 1, flags + 2, io.info, s));
   return RLU_OK;
@@ -406,7 +424,12 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffe
   if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RLU_ERR_DEVICE;
   st = ensure_ws(h, L.total);
   if (st == RLU_OK) st = begin_timing(h);
-  if (st == RLU_OK) st = factor_fp64(h, *pb, *io, (hipStream_t)stream, L);
+  if (st == RLU_OK) {
+    if (pb->precision == RLU_PREC_FP64)
+      st = factor_path<double>(h, *pb, *io, (hipStream_t)stream, L);
+    else
+      st = factor_path<float>(h, *pb, *io, (hipStream_t)stream, L);
+  }
   if (prev != h->device) hipSetDevice(prev);
   return st;
 }

@@ -36,6 +36,10 @@ struct GemmDesc {
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
+// Operand storage types TA, TB, MFMA type TC, output type TO (instantiated for
+// the combinations the library uses).
+template <typename TA, typename TB, typename TC, typename TO>
+hipError_t launch_gemm_t(const GemmDesc& d, hipStream_t s);
 size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit);
 size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa);
 // Tuning override of the tile shape (index into the compiled shapes; -1 = automatic).
@@ -73,6 +77,13 @@ template <typename T>
 hipError_t launch_build_u(const T* Bst, int64_t ldb, int64_t k, int64_t n,
                           const int* piv_row, const int* rstep, const int64_t* q,
                           T* U, int64_t ldu, hipStream_t s);
+hipError_t launch_build_u_f32(const double* Bst, int64_t ldb, int64_t k, int64_t n,
+                              const int* piv_row, const int* rstep, const int64_t* q, float* U,
+                              int64_t ldu, hipStream_t s);
+// dst (rows x cols, TO) = src (TI), element-wise conversion
+template <typename TI, typename TO>
+hipError_t launch_convert2d(const TI* src, int64_t lds, TO* dst, int64_t ldd, int64_t rows,
+                            int64_t cols, hipStream_t s);
 template <typename T>
 hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,
                          int64_t cols, hipStream_t s);

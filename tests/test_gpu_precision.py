@@ -1,0 +1,91 @@
+"""Reduced-precision forms of the HIP path against the FP64 CPU oracle.
+
+Rule (reduced precision): the relative residual ||L U - P A Q||_2 / ||A||_2 of
+the GPU factors may exceed the oracle's by at most 1e-3, both computed the
+same way on the same FP32-stored A (upcast to FP64) with the same G; the
+structure of the factors is exact; and the pivots agree on every step whose
+choice is decided by a wide margin (relative gap >= 1e-3 and magnitude >= 1e3
+FP32 unit roundoffs of max|Y|, far above FP32 rounding of the sketch).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from tests.helpers import ensure_built, to_dev_colmajor, to_host
+from oracle import rlu as orl
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+BAR = 1e-3
+
+
+@pytest.fixture(scope="module")
+def rlu():
+    ensure_built()
+    import paper_1310_7202_amd as m
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return m
+
+
+def rel_residual(A, L, U, p, q):
+    return np.linalg.norm(L @ U - A[np.ix_(p, q)], 2) / np.linalg.norm(A, 2)
+
+
+def check(rlu, A64, k, l, seed, precision, label):
+    A32 = A64.astype(np.float32)
+    A = A32.astype(np.float64)            # the matrix both sides factor
+    m, n = A.shape
+    G32 = workloads.gaussian((n, l), seed).astype(np.float32)
+    print(f"[precision] {label} m={m} n={n} k={k} l={l} prec={precision}", flush=True)
+    out = rlu.factor(to_dev_colmajor(A32, dtype=torch.float32), k, l,
+                     G=to_dev_colmajor(G32, dtype=torch.float32), precision=precision,
+                     diagnostics=True)
+    torch.cuda.synchronize()
+    assert out.L.dtype == torch.float32 and out.U.dtype == torch.float32
+    info = to_host(out.info)
+    assert info[2] == 0
+    o = orl.randomized_lu(A, k, l, G32.astype(np.float64))
+    L = to_host(out.L).astype(np.float64)
+    U = to_host(out.U).astype(np.float64)
+    p, q = to_host(out.p), to_host(out.q)
+    np.testing.assert_array_equal(np.sort(p), np.arange(m))
+    np.testing.assert_array_equal(np.sort(q), np.arange(n))
+    assert np.all(np.diag(L[:k]) == 1.0) and np.all(np.triu(L[:k], 1) == 0.0)
+    assert np.all(np.tril(U, -1) == 0.0)
+    r_gpu = rel_residual(A, L, U, p, q)
+    r_ora = rel_residual(A, o["L"], o["U"], o["p"], o["q"])
+    print(f"  residual gpu {r_gpu:.3e} oracle {r_ora:.3e}", flush=True)
+    assert r_gpu <= r_ora + BAR
+    # decided by a margin FP32 rounding of the sketch cannot flip: relative
+    # gap >= 1e-3 and magnitude >= 1e3 FP32 unit roundoffs of max|Y|
+    gy = orl.pivot_gate(o["diag_y"], u=2.0 ** -24, gap_min=1e-3, mag_factor=1e3)
+    np.testing.assert_array_equal(to_host(out.ipiv)[:gy], o["ipiv"][:gy])
+    return r_gpu, r_ora
+
+
+@pytest.mark.parametrize("m,n,k,l,rate", [
+    (3000, 2500, 50, 60, 20.0),
+    (700, 1300, 33, 41, 8.0),
+    (97, 131, 5, 9, 3.0),
+])
+def test_fp32_spectral(rlu, m, n, k, l, rate):
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), rate), 300 + m)
+    check(rlu, A, k, l, 400 + n, rlu.PREC_FP32, "fp32 spectral")
+
+
+def test_fp32_low_rank(rlu):
+    A, k, l = workloads.config_small(101)
+    r_gpu, r_ora = check(rlu, A, k, l, 7203, rlu.PREC_FP32, "fp32 512^2 rank-10")
+    # the FP32 storage of A itself limits the attainable residual
+    assert r_gpu < 1e-5
+
+
+def test_fp32_default_precision_for_float_input(rlu):
+    A = workloads.spectral_matrix(400, 300, workloads.exp_decay(300, 6.0), 9).astype(np.float32)
+    out = rlu.factor(to_dev_colmajor(A, dtype=torch.float32), 10, 14, seed=3)
+    torch.cuda.synchronize()
+    assert tuple(to_host(out.info)) == (0, 0, 0)
+    assert out.L.dtype == torch.float32
