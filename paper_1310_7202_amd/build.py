@@ -28,7 +28,7 @@ HIP_FLAGS = [
     "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["rng.hip", "gemm.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
+SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
            "rlu_api.cpp"]
 
 

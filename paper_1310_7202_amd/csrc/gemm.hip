@@ -309,6 +309,17 @@ size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa) {
   return gemm_partial_elems(M, N, choose_shape(M, N, K, opa == OpA::LvT).ksplit);
 }
 
+hipError_t launch_splitk_sum_f64(int64_t M, int64_t N, int ksplit, const double* partial,
+                                 double* C, int64_t ldc, const int* rowmap, hipStream_t s) {
+  const int64_t total = M * N;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(splitk_sum_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, M, N,
+                     ksplit, partial, C, ldc, rowmap);
+  return hipGetLastError();
+}
+
 void gemm_force_config(int id) { g_force_cfg = (id >= 0 && id < CFG_COUNT) ? id : -1; }
 
 template <typename TA, typename TB, typename TC, typename TO>

@@ -1,0 +1,212 @@
+// Low-precision MFMA GEMM for the mixed-precision form of Algorithm 4.1
+// (Shabat et al., Section 4): the two products with A,
+//   Step 2   Y = A G        and      Step 5   C = L_y^T P A = Lv^T A,
+// run on BF16 (or FP16) matrix cores with FP32 accumulation, while the
+// pivoted LUs, the Gram matrix and its inverse stay in FP64.
+//
+// Operands are read in their storage type (FP32 A and G, FP64 Lv) and
+// rounded to the 16-bit type in registers on the way to LDS, so no
+// low-precision copy of A is ever written.  The unit-lower factor Lv can be
+// carried as a pair hi + lo of 16-bit numbers (hi = round(x),
+// lo = round(x - hi)), two MFMAs per fragment: rounding Lv alone to 8
+// significant bits perturbs the projection by about u kappa(L_y) sqrt(k/m)
+// ||A||, which the pair reduces by another factor u.
+//
+// Tiles: 64 x 64 outputs per workgroup of four waves (2 x 2, each 32 x 32 =
+// 2 x 2 MFMA 16x16x32 tiles), K slices of 32 staged in LDS as [row][k]
+// (k contiguous, so each lane fetches its 8 consecutive k with one 16-byte
+// LDS read), register prefetch of the next slice, two LDS buffers.
+// MFMA 16x16x32 (bf16 / f16) layout: lane i + 16 g holds row i, k 8g..8g+7
+// of either operand; lane l, slot v of the result holds D[4(l/16) + v][l%16].
+#include "rlu_device.h"
+#include "rlu_kernels.h"
+
+namespace rlu {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <typename LP> struct LpMfma;
+template <> struct LpMfma<__bf16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ f4 mma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct LpMfma<_Float16> {
+  typedef f16x8 vec;
+  static __device__ __forceinline__ f4 mma(vec a, vec b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int LBK = 32;      // K slice
+constexpr int LPAD = 8;      // row padding (16 bytes keeps rows 16-byte aligned)
+constexpr int LLD = LBK + LPAD;
+
+template <typename LP, typename TA, typename TB, typename TO, OpA OA, bool SPLIT, int BM, int BN,
+          int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
+               const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
+               TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
+  constexpr int AE = BM * LBK / NT, BE = BN * LBK / NT;
+  constexpr int NS = SPLIT ? 2 : 1;
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
+  static_assert((BM * LBK) % NT == 0 && (BN * LBK) % NT == 0, "tile vs threads");
+  typedef typename LpMfma<LP>::vec vec;
+  __shared__ __attribute__((aligned(16))) LP As[2][NS][BM * LLD];
+  __shared__ __attribute__((aligned(16))) LP Bs[2][BN * LLD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t kchunk = ((K + ksplit - 1) / ksplit + LBK - 1) / LBK * LBK;
+  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+
+  // raw (storage-type) prefetch registers
+  double ra[AE];
+  float rb[BE];
+
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = tid + q * NT;
+      int i, kk;
+      if (OA == OpA::LvT) { kk = e % LBK; i = e / LBK; } else { i = e % BM; kk = e / BM; }
+      const int64_t gi = m0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < M && gk < kend) {
+        if (OA == OpA::Plain) v = (double)A[gi + gk * lda];
+        else v = (double)lv_value<TA>(A[gk + gi * lda], (int)gi, astep[gk]);
+      }
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = tid + q * NT;
+      const int kk = e % LBK, j = e / LBK;
+      const int64_t gj = n0 + j, gk = k0 + kk;
+      rb[q] = (gj < N && gk < kend) ? (float)B[gk + gj * ldb] : 0.f;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < AE; ++q) {
+      const int e = tid + q * NT;
+      int i, kk;
+      if (OA == OpA::LvT) { kk = e % LBK; i = e / LBK; } else { i = e % BM; kk = e / BM; }
+      const float x = (float)ra[q];
+      const LP hi = (LP)x;
+      As[buf][0][i * LLD + kk] = hi;
+      if (SPLIT) As[buf][NS - 1][i * LLD + kk] = (LP)(float)(ra[q] - (double)(float)hi);
+    }
+#pragma unroll
+    for (int q = 0; q < BE; ++q) {
+      const int e = tid + q * NT;
+      const int kk = e % LBK, j = e / LBK;
+      Bs[buf][j * LLD + kk] = (LP)rb[q];
+    }
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = kbeg; kt < kend; kt += LBK) {
+    const bool more = kt + LBK < kend;
+    if (more) load(kt + LBK);
+    const int kof = 8 * (lane >> 4);
+    vec af[NS][TM], bf[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int row = wm * WTM + a * 16 + (lane & 15);
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) af[s2][a] = *(const vec*)&As[buf][s2][row * LLD + kof];
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int col = wn * WTN + b * 16 + (lane & 15);
+      bf[b] = *(const vec*)&Bs[buf][col * LLD + kof];
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        acc[a][b] = LpMfma<LP>::mma(af[0][a], bf[b], acc[a][b]);
+        if (SPLIT) acc[a][b] = LpMfma<LP>::mma(af[NS - 1][a], bf[b], acc[a][b]);
+      }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = m0 + wm * WTM + a * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = n0 + wn * WTN + b * 16 + (lane & 15);
+        if (gi < M && gj < N) {
+          const TO val = (TO)acc[a][b][v];
+          if (ksplit > 1) partial[(int64_t)blockIdx.z * M * N + gi + gj * M] = val;
+          else C[gi + gj * ldc] = val;
+        }
+      }
+}
+
+template <typename LP, typename TA, typename TB, OpA OA, bool SPLIT>
+hipError_t launch_lp(const GemmDesc& d, hipStream_t s) {
+  constexpr int BM = 64, BN = 64, WM = 2, WN = 2;
+  const int64_t tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  int ks = 1;
+  if (d.partial)
+    while (tiles * ks < 1024 && d.K / (ks * 2) >= 1024 && ks < 32) ks *= 2;
+  dim3 grid((unsigned)((d.M + BM - 1) / BM), (unsigned)((d.N + BN - 1) / BN), (unsigned)ks);
+  hipLaunchKernelGGL((gemm_lp_kernel<LP, TA, TB, double, OA, SPLIT, BM, BN, WM, WN>), grid,
+                     dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A, d.lda, d.astep,
+                     (const TB*)d.B, d.ldb, (double*)d.C, d.ldc, ks, (double*)d.partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1) return e;
+  return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
+                               nullptr, s);
+}
+
+}  // namespace
+
+size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int ks = 1;
+  while (tiles * ks < 1024 && K / (ks * 2) >= 1024 && ks < 32) ks *= 2;
+  return ks > 1 ? (size_t)ks * (size_t)M * (size_t)N : 0;
+}
+
+hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  if (d.opb != OpB::Plain) return hipErrorInvalidValue;
+  if (d.opa == OpA::Plain) {  // Y = A G: FP32 A and G
+    return fp16 ? launch_lp<_Float16, float, float, OpA::Plain, false>(d, s)
+                : launch_lp<__bf16, float, float, OpA::Plain, false>(d, s);
+  }
+  if (d.opa == OpA::LvT) {    // C = Lv^T A: FP64 Lv as a hi + lo pair, FP32 A
+    return fp16 ? launch_lp<_Float16, double, float, OpA::LvT, true>(d, s)
+                : launch_lp<__bf16, double, float, OpA::LvT, true>(d, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace rlu

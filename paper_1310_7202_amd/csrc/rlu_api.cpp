@@ -89,6 +89,10 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   part = std::max(part, gemm_auto_partial_elems(k, n, m, OpA::LvT));
   part = std::max(part, gemm_auto_partial_elems(k, n, k, OpA::Plain));
   part = std::max(part, gemm_auto_partial_elems(m, k, k, OpA::Lv));
+  if (pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16) {
+    part = std::max(part, gemm_lp_partial_elems(m, l, n));
+    part = std::max(part, gemm_lp_partial_elems(k, n, m));
+  }
   take(L.part, part * d);
   take(L.S, (size_t)k * k * d);
   take(L.C, (size_t)k * n * d);
@@ -127,7 +131,7 @@ rlu_status_t validate(const rlu_problem_t* pb) {
     case RLU_PREC_MIXED_BF16:
     case RLU_PREC_MIXED_FP16:
       if (pb->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
-      return RLU_ERR_UNSUPPORTED;
+      break;
     default:
       return RLU_ERR_INVALID_ARG;
   }
@@ -211,10 +215,15 @@ rlu_status_t begin_timing(rlu_handle_s* h) {
 // The FP64 path (T = double) and the FP32 path (T = float: FP32 storage of
 // A, G, L, U and FP32 MFMA for the two products with A).  The pivoted LUs,
 // the Gram matrix, its inverse and B are FP64 in both.
+//
+// The mixed forms (T = float) replace the FP32 MFMA of the two products with
+// BF16 or FP16 MFMA accumulating in FP32 (gemm_lp.hip).
 template <typename T>
 rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buffers_t& io,
                          hipStream_t s, const Layout& Ly) {
-  constexpr bool kF32 = std::is_same<T, float>::value;
+  const bool lp = pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16;
+  const bool fp16 = pb.precision == RLU_PREC_MIXED_FP16;
+  const bool kF32 = pb.precision == RLU_PREC_FP32;   // diagnostics stored in FP32
   const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
   void* ws = h->ws;
   double* Y = at<double>(ws, Ly.Y);
@@ -255,7 +264,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     PhaseScope ph(h, PH_SKETCH, s);
-    HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
+    if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
+    else HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
   }
   if (diag && io.Y) {
     if (kF32) HIP_TRY((launch_convert2d<double, float>(Y, m, (float*)io.Y, io.ldy, m, l, s)));
@@ -297,7 +307,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = C; d.ldc = k;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     PhaseScope ph(h, PH_PROJECT, s);
-    HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
+    if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
+    else HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
   }
   HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {
@@ -329,7 +340,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
     HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
     // Step 8: U = U_b
-    if (kF32)
+    if (std::is_same<T, float>::value)
       HIP_TRY(launch_build_u_f32(Bst, k, k, n, piv_b, rstep_b, io.q, (float*)io.U, io.ldu, s));
     else
       HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));

@@ -42,6 +42,16 @@ template <typename TA, typename TB, typename TC, typename TO>
 hipError_t launch_gemm_t(const GemmDesc& d, hipStream_t s);
 size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit);
 size_t gemm_auto_partial_elems(int64_t M, int64_t N, int64_t K, OpA opa);
+// C = sum of ksplit partial products (M x N each, stored contiguously), added
+// in a fixed order; optional output row map.
+hipError_t launch_splitk_sum_f64(int64_t M, int64_t N, int ksplit, const double* partial,
+                                 double* C, int64_t ldc, const int* rowmap, hipStream_t s);
+// Low-precision products of the mixed form (gemm_lp.hip): BF16 (or FP16) MFMA
+// with FP32 accumulation and an FP64 result.  Y = A G (opa Plain: FP32 A and
+// G) or C = Lv^T A (opa LvT: FP64 Lv carried as a 16-bit hi + lo pair, FP32
+// A).  ksplit is chosen internally when `partial` is given.
+hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s);
+size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K);
 // Tuning override of the tile shape (index into the compiled shapes; -1 = automatic).
 void gemm_force_config(int id);
 

@@ -89,3 +89,63 @@ def test_fp32_default_precision_for_float_input(rlu):
     torch.cuda.synchronize()
     assert tuple(to_host(out.info)) == (0, 0, 0)
     assert out.L.dtype == torch.float32
+
+
+def _round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32 values to the nearest bfloat16 (ties to even), kept in FP32."""
+    b = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32)
+
+
+def check_mixed(rlu, A64, k, l, seed, fp16, label):
+    """As check(), with G already representable in the 16-bit type so that
+    both sides use the same sketch matrix."""
+    A32 = A64.astype(np.float32)
+    A = A32.astype(np.float64)
+    m, n = A.shape
+    G = workloads.gaussian((n, l), seed).astype(np.float32)
+    G = G.astype(np.float16).astype(np.float32) if fp16 else _round_bf16(G)
+    prec = rlu.PREC_MIXED_FP16 if fp16 else rlu.PREC_MIXED_BF16
+    print(f"[precision] {label} m={m} n={n} k={k} l={l} fp16={fp16}", flush=True)
+    out = rlu.factor(to_dev_colmajor(A32, dtype=torch.float32), k, l,
+                     G=to_dev_colmajor(G, dtype=torch.float32), precision=prec, diagnostics=True)
+    torch.cuda.synchronize()
+    assert out.Y.dtype == torch.float64  # diagnostics of the mixed form are FP64
+    info = to_host(out.info)
+    assert info[2] == 0
+    o = orl.randomized_lu(A, k, l, G.astype(np.float64))
+    L = to_host(out.L).astype(np.float64)
+    U = to_host(out.U).astype(np.float64)
+    p, q = to_host(out.p), to_host(out.q)
+    np.testing.assert_array_equal(np.sort(p), np.arange(m))
+    np.testing.assert_array_equal(np.sort(q), np.arange(n))
+    assert np.all(np.diag(L[:k]) == 1.0) and np.all(np.triu(L[:k], 1) == 0.0)
+    assert np.all(np.tril(U, -1) == 0.0)
+    r_gpu = rel_residual(A, L, U, p, q)
+    r_ora = rel_residual(A, o["L"], o["U"], o["p"], o["q"])
+    print(f"  residual gpu {r_gpu:.3e} oracle {r_ora:.3e}", flush=True)
+    assert r_gpu <= r_ora + BAR
+    # the sketch itself: A rounded to 16 bits times an exact G, FP32 sums
+    u = 2.0 ** -11 if fp16 else 2.0 ** -8
+    Yd = to_host(out.Y)
+    assert np.abs(Yd - o["Y"]).max() <= 4 * u * (np.abs(A) @ np.abs(G.astype(np.float64))).max()
+    return r_gpu, r_ora
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("m,n,k,l,rate", [
+    (3000, 2500, 50, 60, 20.0),
+    (700, 1300, 33, 41, 8.0),
+])
+def test_mixed_spectral(rlu, m, n, k, l, rate, fp16):
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), rate), 500 + m)
+    check_mixed(rlu, A, k, l, 600 + n, fp16, "mixed spectral")
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+def test_mixed_slow_decay_inverse_square(rlu, fp16):
+    # sigma_i = i^-2 (the spectrum of the mixed-precision workload), smaller size
+    m = n = 2048
+    A = workloads.spectral_matrix(m, n, workloads.inv_square(m), 77)
+    check_mixed(rlu, A, 120, 130, 78, fp16, "mixed i^-2")
