@@ -145,6 +145,23 @@ rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
 rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
                         const rlu_buffers_t* io, rlu_stream_t stream);
 
+/* Many independent problems (Algorithm 4.1 for each), enqueued on `stream`
+ * as one launch per kernel of the method for the whole batch.
+ *
+ * pbs[i] and ios[i] describe problem i exactly as for rlu_factor; shapes may
+ * all differ, but every problem must use the same dtype and precision, and
+ * RLU_FLAG_DIAGNOSTICS is not available here (RLU_ERR_INVALID_ARG).  Each
+ * problem's results are those rlu_factor defines for it (same pivot rules;
+ * products may round differently because tile shapes and K splits differ).
+ * The handle owns a separate batch workspace.  The launch sequence is
+ * recorded once as a HIP graph and replayed for later calls with identical
+ * arrays (same problems, same buffers); phase timing, when enabled, runs it
+ * without the graph.  RLU_ERR_UNSUPPORTED if a panel (l or k columns) is too
+ * wide for the batched pivoted LU or a problem needs more workgroups than
+ * the device holds at once.  count = 0 is a no-op. */
+rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count, const rlu_problem_t* pbs,
+                                const rlu_buffers_t* ios, rlu_stream_t stream);
+
 /* Phase timing for measurement tools.  When enabled, rlu_factor records a
  * HIP event pair around each phase on the stream that runs the phase (the
  * caller's stream, or the handle's side stream for the Gram inverse).  The

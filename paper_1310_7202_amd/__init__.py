@@ -13,7 +13,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
-__all__ = ["RluError", "Handle", "factor", "lib", "status_string", "LIB_PATH",
+__all__ = ["RluError", "Handle", "factor", "factor_batched", "Batch", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
            "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS"]
 
@@ -32,7 +32,7 @@ STATUS = {
 
 # every function include/rlu.h declares
 EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                    "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
+                    "rlu_factor_batched", "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
                     "rlu_status_string", "rlu_version"]
 
 
@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
         L.rlu_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
         L.rlu_factor.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
                                  ctypes.POINTER(Buffers), ctypes.c_void_p]
+        L.rlu_factor_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
+                                         ctypes.POINTER(Buffers), ctypes.c_void_p]
         L.rlu_check_info.argtypes = [ctypes.POINTER(ctypes.c_int32)]
         L.rlu_status_string.argtypes = [ctypes.c_int]
         L.rlu_status_string.restype = ctypes.c_char_p
@@ -85,7 +87,8 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_char_p), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]
         for name in ("rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                     "rlu_check_info", "rlu_set_timing", "rlu_phase_times"):
+                     "rlu_factor_batched", "rlu_check_info", "rlu_set_timing",
+                     "rlu_phase_times"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -178,14 +181,9 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
-           diagnostics: bool = False, handle: Handle | None = None, stream=None,
-           out: Factors | None = None) -> Factors:
-    """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
-    float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
-    tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
-    p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
-    current torch stream by default) and not synchronized."""
+def _prepare(A, k, l, precision, seed, G, diagnostics, out):
+    """ctypes problem and buffer structs for one factorization (allocating
+    the outputs that `out` does not provide)."""
     import torch
 
     if A.dim() != 2 or not A.is_cuda:
@@ -203,7 +201,6 @@ def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=
     else:
         raise ValueError("A must be float64 or float32")
     dev = A.device
-    h = handle or default_handle(dev.index or 0)
     if out is None:
         L = torch.empty((k, m), dtype=A.dtype, device=dev).t()
         U = torch.empty((n, k), dtype=A.dtype, device=dev).t()
@@ -233,11 +230,70 @@ def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=
                  (max(out.B.stride(1), k) if n > 1 else k) if out.B is not None else 0,
                  out.ipiv.data_ptr() if out.ipiv is not None else None,
                  out.qpiv.data_ptr() if out.qpiv is not None else None)
-    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    return pb, io, out
+
+
+def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
+           diagnostics: bool = False, handle: Handle | None = None, stream=None,
+           out: Factors | None = None) -> Factors:
+    """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
+    float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
+    tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
+    p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
+    current torch stream by default) and not synchronized."""
+    import torch
+
+    pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out)
+    h = handle or default_handle(A.device.index or 0)
+    s = stream if stream is not None else torch.cuda.current_stream(A.device)
     st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),
                           ctypes.c_void_p(s.cuda_stream))
     _check(st, "rlu_factor")
     return out
+
+
+class Batch:
+    """A prepared batch for rlu_factor_batched: the problem and buffer
+    arrays stay alive (and unchanged) so that repeated calls replay the
+    library's recorded launch graph."""
+
+    def __init__(self, problems, *, precision: int | None = None, outs=None):
+        """problems: sequence of (A, k, l) or (A, k, l, seed) or
+        (A, k, l, seed, G) with A a column-major device tensor."""
+        items = [tuple(p) + (0, None)[len(p) - 3:] if len(p) < 5 else tuple(p) for p in problems]
+        self.count = len(items)
+        self.pbs = (Problem * max(1, self.count))()
+        self.ios = (Buffers * max(1, self.count))()
+        self.outs = []
+        self.inputs = []
+        for i, (A, k, l, seed, G) in enumerate(items):
+            o = outs[i] if outs is not None else None
+            pb, io, o = _prepare(A, k, l, precision, seed, G, False, o)
+            self.pbs[i] = pb
+            self.ios[i] = io
+            self.outs.append(o)
+            self.inputs.append((A, G))
+        self.device = items[0][0].device if items else None
+
+    def run(self, handle: Handle | None = None, stream=None):
+        import torch
+
+        if self.count == 0:
+            return self.outs
+        h = handle or default_handle(self.device.index or 0)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = lib().rlu_factor_batched(h.ptr, self.count, self.pbs, self.ios,
+                                      ctypes.c_void_p(s.cuda_stream))
+        _check(st, "rlu_factor_batched")
+        return self.outs
+
+
+def factor_batched(problems, *, precision: int | None = None, handle: Handle | None = None,
+                   stream=None, outs=None) -> list:
+    """Algorithm 4.1 for every (A, k, l[, seed[, G]]) in `problems`, as one
+    batched call.  Returns a list of Factors (device tensors, not
+    synchronized)."""
+    return Batch(problems, precision=precision, outs=outs).run(handle, stream)
 
 
 def check_info(info) -> int:

@@ -112,6 +112,47 @@ __global__ void __launch_bounds__(256) copy_i32_kernel(const int* __restrict__ s
     dst[e] = src[e];
 }
 
+// Steps 7-8 assembly for a batch (blockIdx.y = problem): the permutations p
+// and q from the row positions, U = U_b scattered by column position (the
+// same values build_u computes), L_b, and the info words.
+template <typename TO>
+__global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev* __restrict__ tasks) {
+  const AsmTaskDev& t = tasks[blockIdx.y];
+  const int64_t m = t.m, n = t.n, k = t.k;
+  const int64_t e_q = m, e_u = m + n, e_lb = m + n + k * n, total = e_lb + k * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < e_q) {
+      t.p[t.pos_y[e]] = e;
+    } else if (e < e_u) {
+      const int64_t o = e - e_q;
+      t.q[t.pos_b[o]] = o;
+    } else if (e < e_lb) {
+      const int64_t x = e - e_u, r = x % k, o = x / k;
+      const double d = t.Bst[r + (int64_t)t.piv_b[r] * k];
+      const double lv = lv_value<double>(t.Bst[r + o * k], (int)r, t.rstep_b[o]);
+      ((TO*)t.U)[r + (int64_t)t.pos_b[o] * t.ldu] = (TO)(d * lv);
+    } else {
+      const int64_t x = e - e_lb, i = x % k, r = x / k;
+      double v = 0.0;
+      if (i == r) {
+        v = 1.0;
+      } else if (i > r) {
+        const int64_t o = t.piv_b[r];
+        const double d = t.Bst[r + o * k];
+        const double u = t.Bst[i + o * k];
+        v = d != 0.0 ? u / d : 0.0;
+      }
+      t.Lb[i + r * k] = v;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    t.info[0] = t.flags[0];
+    t.info[1] = t.flags[1];
+    t.info[2] = t.flags[2];
+  }
+}
+
 inline unsigned grid_for(int64_t n, int64_t cap = 8192) {
   int64_t b = (n + 255) / 256;
   if (b < 1) b = 1;
@@ -196,5 +237,19 @@ hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t 
   hipLaunchKernelGGL(copy_i32_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
+
+template <typename TO>
+hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  int64_t bx = (max_elems + 255) / 256;
+  if (bx < 1) bx = 1;
+  if (bx > 128) bx = 128;
+  hipLaunchKernelGGL(assemble_batched_kernel<TO>, dim3((unsigned)bx, (unsigned)count), dim3(256),
+                     0, s, tasks);
+  return hipGetLastError();
+}
+template hipError_t launch_assemble_batched<double>(const AsmTaskDev*, int, int64_t, hipStream_t);
+template hipError_t launch_assemble_batched<float>(const AsmTaskDev*, int, int64_t, hipStream_t);
 
 }  // namespace rlu

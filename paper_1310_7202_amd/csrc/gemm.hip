@@ -43,13 +43,15 @@ struct Tile {
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
 };
 
+// One BM x BN output tile (bx, by) over K split bz of ksplit.
 template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
           int WN, int NBUF, OpA OA, OpB OB>
-__global__ void __launch_bounds__(64 * WM * WN)
-gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
-            const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
-            const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
-            const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial) {
+__device__ __forceinline__ void gemm_tile(
+    int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
+    const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
+    const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
+    const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int bx, int by,
+    int bz) {
   constexpr bool AK = (OA == OpA::LvT);  // A operand contiguous along K
   constexpr bool BKC = true;             // B operands are contiguous along K
   typedef Tile<BM, BN, BK, WM, WN, AK, BKC, NBUF> Tl;
@@ -60,11 +62,11 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int64_t n0 = (int64_t)blockIdx.y * BN;
+  const int64_t m0 = (int64_t)bx * BM;
+  const int64_t n0 = (int64_t)by * BN;
   // K range of this split (multiples of BK)
   const int64_t kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kbeg = (int64_t)bz * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
   TC ra[Tl::AE], rb[Tl::BE];
@@ -175,13 +177,60 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
         if (gi < M && gj < N) {
           const TO val = (TO)acc[a][b][v];
           if (ksplit > 1) {
-            partial[(int64_t)blockIdx.z * M * N + gi + gj * M] = val;
+            partial[(int64_t)bz * M * N + gi + gj * M] = val;
           } else {
             const int64_t oi = rowmap ? (int64_t)rowmap[gi] : gi;
             C[oi + gj * ldc] = val;
           }
         }
       }
+}
+
+template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
+          int WN, int NBUF, OpA OA, OpB OB>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
+            const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
+            const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
+            const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial) {
+  gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
+      M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, (int)blockIdx.x,
+      (int)blockIdx.y, (int)blockIdx.z);
+}
+
+// Many independent products in one launch: workgroup b computes the tile
+// named by map[b] = (task, bx + tiles_m (by + tiles_n bz)).
+template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
+          int WN, int NBUF, OpA OA, OpB OB>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_grouped_kernel(const GemmTaskDev* __restrict__ tasks, const int2* __restrict__ map) {
+  const int2 e = map[blockIdx.x];
+  if (e.x < 0) return;  // padding of the XCD layout
+  const GemmTaskDev& t = tasks[e.x];
+  const int bx = e.y % t.tiles_m, rest = e.y / t.tiles_m;
+  const int by = rest % t.tiles_n, bz = rest / t.tiles_n;
+  gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
+      t.M, t.N, t.K, (const TA*)t.A, t.lda, t.astep, (const TB*)t.B, t.ldb, t.bstep, (TO*)t.C,
+      t.ldc, t.rowmap, t.ksplit, (TO*)t.partial, bx, by, bz);
+}
+
+// Split-K sums of a group: blockIdx.y is the task; tasks without a split
+// are skipped.
+__global__ void __launch_bounds__(256) splitk_sum_grouped_kernel(
+    const GemmTaskDev* __restrict__ tasks) {
+  const GemmTaskDev& t = tasks[blockIdx.y];
+  if (t.ksplit <= 1) return;
+  const int64_t total = t.M * t.N;
+  const double* partial = (const double*)t.partial;
+  double* C = (double*)t.C;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = partial[e];
+    for (int z = 1; z < t.ksplit; ++z) s += partial[(int64_t)z * total + e];  // fixed order
+    const int64_t i = e % t.M, j = e / t.M;
+    const int64_t oi = t.rowmap ? (int64_t)t.rowmap[i] : i;
+    C[oi + j * t.ldc] = s;
+  }
 }
 
 template <typename TO>
@@ -264,6 +313,7 @@ hipError_t launch_ops(const GemmDesc& d, hipStream_t s) {
   const int c = sh.cfg;
   // ksplit 0 = automatic (needs the partial workspace); 1 = no split
   const int ks = d.ksplit == 0 ? (d.partial ? sh.ksplit : 1) : d.ksplit;
+  if (d.ksplit_out) *d.ksplit_out = ks;
   hipError_t e;
   switch (c) {
     case C64x64x16: e = launch_cfg<TA, TB, TC, TO, 64, 64, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
@@ -276,7 +326,7 @@ hipError_t launch_ops(const GemmDesc& d, hipStream_t s) {
     case C128x64x16: e = launch_cfg<TA, TB, TC, TO, 128, 64, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
     default: e = launch_cfg<TA, TB, TC, TO, 64, 128, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
   }
-  if (e != hipSuccess || ks == 1) return e;
+  if (e != hipSuccess || ks == 1 || d.no_sum) return e;
   const int64_t total = d.M * d.N;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 8192) blocks = 8192;
@@ -299,7 +349,68 @@ hipError_t dispatch(const GemmDesc& d, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+template <typename TA, typename TB, typename TC, typename TO, OpA OA, OpB OB>
+hipError_t launch_grouped_ops(int cfg, const GemmTaskDev* tasks, const int2* map, int nwg,
+                              hipStream_t s) {
+#define RLU_GG(BM, BN, BK, WM, WN, NB)                                                       \
+  hipLaunchKernelGGL((gemm_grouped_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NB, OA, OB>), \
+                     dim3((unsigned)nwg), dim3(64 * WM * WN), 0, s, tasks, map)
+  switch (cfg) {
+    case C64x64x16: RLU_GG(64, 64, 16, 2, 2, 2); break;
+    case C64x112x16: RLU_GG(64, 112, 16, 4, 1, 2); break;
+    case C112x64x16: RLU_GG(112, 64, 16, 1, 4, 2); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef RLU_GG
+  return hipGetLastError();
+}
+
+template <typename TA, typename TB, typename TC, typename TO>
+hipError_t dispatch_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks, const int2* map,
+                            int nwg, hipStream_t s) {
+  if (nwg <= 0) return hipSuccess;
+  if (opa == OpA::Plain && opb == OpB::Plain)
+    return launch_grouped_ops<TA, TB, TC, TO, OpA::Plain, OpB::Plain>(cfg, tasks, map, nwg, s);
+  if (opa == OpA::LvT && opb == OpB::Plain)
+    return launch_grouped_ops<TA, TB, TC, TO, OpA::LvT, OpB::Plain>(cfg, tasks, map, nwg, s);
+  if (opa == OpA::LvT && opb == OpB::Lv)
+    return launch_grouped_ops<TA, TB, TC, TO, OpA::LvT, OpB::Lv>(cfg, tasks, map, nwg, s);
+  if (opa == OpA::Lv && opb == OpB::Plain)
+    return launch_grouped_ops<TA, TB, TC, TO, OpA::Lv, OpB::Plain>(cfg, tasks, map, nwg, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+void gemm_group_tile(int cfg, int* bm, int* bn) {
+  const int c = (cfg >= 0 && cfg < CFG_COUNT) ? cfg : C64x64x16;
+  *bm = kCfg[c].bm;
+  *bn = kCfg[c].bn;
+}
+
+template <typename TA, typename TB, typename TC, typename TO>
+hipError_t launch_gemm_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks,
+                               const int2* map, int nwg, hipStream_t s) {
+  return dispatch_grouped<TA, TB, TC, TO>(opa, opb, cfg, tasks, map, nwg, s);
+}
+template hipError_t launch_gemm_grouped<double, double, double, double>(
+    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
+template hipError_t launch_gemm_grouped<float, float, float, double>(
+    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
+template hipError_t launch_gemm_grouped<double, float, float, double>(
+    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
+template hipError_t launch_gemm_grouped<double, double, double, float>(
+    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
+
+hipError_t launch_splitk_sum_grouped(const GemmTaskDev* tasks, int count, int64_t max_elems,
+                                     hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  int64_t bx = (max_elems + 255) / 256;
+  if (bx > 64) bx = 64;
+  hipLaunchKernelGGL(splitk_sum_grouped_kernel, dim3((unsigned)bx, (unsigned)count), dim3(256), 0,
+                     s, tasks);
+  return hipGetLastError();
+}
 
 size_t gemm_partial_elems(int64_t M, int64_t N, int ksplit) {
   return ksplit > 1 ? (size_t)ksplit * (size_t)M * (size_t)N : 0;

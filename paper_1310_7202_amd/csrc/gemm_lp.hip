@@ -47,10 +47,12 @@ constexpr int LLD = LBK + LPAD;
 
 template <typename LP, typename TA, typename TB, typename TO, OpA OA, bool SPLIT, int BM, int BN,
           int WM, int WN>
-__global__ void __launch_bounds__(64 * WM * WN)
-gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
-               const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
-               TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial) {
+__device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
+                                             const TA* __restrict__ A, int64_t lda,
+                                             const int* __restrict__ astep,
+                                             const TB* __restrict__ B, int64_t ldb,
+                                             TO* __restrict__ C, int64_t ldc, int ksplit,
+                                             TO* __restrict__ partial, int bx, int by, int bz) {
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
   constexpr int AE = BM * LBK / NT, BE = BN * LBK / NT;
@@ -63,9 +65,9 @@ gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
   const int64_t kchunk = ((K + ksplit - 1) / ksplit + LBK - 1) / LBK * LBK;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  const int64_t kbeg = (int64_t)bz * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
   // raw (storage-type) prefetch registers
@@ -163,10 +165,36 @@ gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_
         const int64_t gj = n0 + wn * WTN + b * 16 + (lane & 15);
         if (gi < M && gj < N) {
           const TO val = (TO)acc[a][b][v];
-          if (ksplit > 1) partial[(int64_t)blockIdx.z * M * N + gi + gj * M] = val;
+          if (ksplit > 1) partial[(int64_t)bz * M * N + gi + gj * M] = val;
           else C[gi + gj * ldc] = val;
         }
       }
+}
+
+template <typename LP, typename TA, typename TB, typename TO, OpA OA, bool SPLIT, int BM, int BN,
+          int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
+               const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
+               TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial) {
+  gemm_lp_tile<LP, TA, TB, TO, OA, SPLIT, BM, BN, WM, WN>(M, N, K, A, lda, astep, B, ldb, C, ldc,
+                                                          ksplit, partial, (int)blockIdx.x,
+                                                          (int)blockIdx.y, (int)blockIdx.z);
+}
+
+// Grouped form: workgroup b computes the tile map[b] = (task, bx + tiles_m by)
+// of one of many independent products (no split-K).
+template <typename LP, typename TA, typename TB, typename TO, OpA OA, bool SPLIT, int BM, int BN,
+          int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_lp_grouped_kernel(const GemmTaskDev* __restrict__ tasks, const int2* __restrict__ map) {
+  const int2 e = map[blockIdx.x];
+  if (e.x < 0) return;  // padding of the XCD layout
+  const GemmTaskDev& t = tasks[e.x];
+  const int bx = e.y % t.tiles_m, by = e.y / t.tiles_m;
+  gemm_lp_tile<LP, TA, TB, TO, OA, SPLIT, BM, BN, WM, WN>(
+      t.M, t.N, t.K, (const TA*)t.A, t.lda, t.astep, (const TB*)t.B, t.ldb, (TO*)t.C, t.ldc, 1,
+      nullptr, bx, by, 0);
 }
 
 template <typename LP, typename TA, typename TB, OpA OA, bool SPLIT>
@@ -180,8 +208,9 @@ hipError_t launch_lp(const GemmDesc& d, hipStream_t s) {
   hipLaunchKernelGGL((gemm_lp_kernel<LP, TA, TB, double, OA, SPLIT, BM, BN, WM, WN>), grid,
                      dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A, d.lda, d.astep,
                      (const TB*)d.B, d.ldb, (double*)d.C, d.ldc, ks, (double*)d.partial);
+  if (d.ksplit_out) *d.ksplit_out = ks;
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || ks == 1) return e;
+  if (e != hipSuccess || ks == 1 || d.no_sum) return e;
   return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
                                nullptr, s);
 }
@@ -207,6 +236,25 @@ hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s) {
                 : launch_lp<__bf16, double, float, OpA::LvT, true>(d, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemm_lp_grouped(OpA opa, bool fp16, const GemmTaskDev* tasks, const int2* map,
+                                  int nwg, hipStream_t s) {
+  if (nwg <= 0) return hipSuccess;
+#define RLU_LPG(LP, TA, OA, SPLIT)                                                              \
+  hipLaunchKernelGGL((gemm_lp_grouped_kernel<LP, TA, float, double, OA, SPLIT, 64, 64, 2, 2>), \
+                     dim3((unsigned)nwg), dim3(256), 0, s, tasks, map)
+  if (opa == OpA::Plain) {
+    if (fp16) RLU_LPG(_Float16, float, OpA::Plain, false);
+    else RLU_LPG(__bf16, float, OpA::Plain, false);
+  } else if (opa == OpA::LvT) {
+    if (fp16) RLU_LPG(_Float16, double, OpA::LvT, true);
+    else RLU_LPG(__bf16, double, OpA::LvT, true);
+  } else {
+    return hipErrorInvalidValue;
+  }
+#undef RLU_LPG
+  return hipGetLastError();
 }
 
 }  // namespace rlu

@@ -145,13 +145,12 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 //               rank-one update of step j-1 on columns c > j          | B0 |
 // so the only device round trip on wave 0's path is the header exchange.
 template <int RPL>
-__global__ void __launch_bounds__(kThreads)
-panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R,
-                int nwg, int* __restrict__ pos_out, int* __restrict__ rstep_out,
-                int* __restrict__ piv_row_out, int* __restrict__ ipiv_out,
-                int* __restrict__ info_out, int* __restrict__ fail, char* __restrict__ xch,
-                int64_t rec_stride, long long timeout_ticks) {
-  extern __shared__ double smem[];
+__device__ __forceinline__ void panel_body(
+    double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R, int nwg,
+    int* __restrict__ pos_out, int* __restrict__ rstep_out, int* __restrict__ piv_row_out,
+    int* __restrict__ ipiv_out, int* __restrict__ info_out, int* __restrict__ fail,
+    char* __restrict__ xch, int64_t rec_stride, long long timeout_ticks, int w, double* smem,
+    long long t_start) {
   double* Ts = smem;                        // R x ncols, column-major (ld R)
   double* urow = Ts + (int64_t)R * ncols;   // 2 x ncols: U rows by step parity
   double* lbody = urow + 2 * ncols;         // 2 x ncols: single-workgroup "records"
@@ -165,7 +164,6 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
   __shared__ double sh_cpiv, sh_clm, sh_cv1;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int w = blockIdx.x;
   const int row0 = w * R;
   const int nr = min(R, nrows - row0);
 
@@ -200,8 +198,6 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
   }
   int info = 0;
   __syncthreads();
-
-  const long long t_start = now_ticks();
 
   for (int j = 0; j < ncols; ++j) {
     const int sj = j & 1, sp = sj ^ 1;
@@ -495,6 +491,40 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
     }
 }
 
+template <int RPL>
+__global__ void __launch_bounds__(kThreads)
+panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R,
+                int nwg, int* __restrict__ pos_out, int* __restrict__ rstep_out,
+                int* __restrict__ piv_row_out, int* __restrict__ ipiv_out,
+                int* __restrict__ info_out, int* __restrict__ fail, char* __restrict__ xch,
+                int64_t rec_stride, long long timeout_ticks) {
+  extern __shared__ double smem[];
+  panel_body<RPL>(X, rs, cs, nrows, ncols, R, nwg, pos_out, rstep_out, piv_row_out, ipiv_out,
+                  info_out, fail, xch, rec_stride, timeout_ticks, (int)blockIdx.x, smem,
+                  now_ticks());
+}
+
+// Many panels in one persistent launch.  Workgroup b runs, round by round,
+// the member of the panel named by sched[round * nslots + b] (task << 8 |
+// member, or -1 when idle).  All members of a panel are scheduled in the
+// same round, so a member waiting on its partners only waits for work of
+// the same or earlier rounds, which always completes.
+template <int RPL>
+__global__ void __launch_bounds__(kThreads)
+panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __restrict__ sched,
+                        int rounds, int nslots, long long timeout_ticks) {
+  extern __shared__ double smem[];
+  const long long t0 = now_ticks();
+  for (int r = 0; r < rounds; ++r) {
+    const int e = sched[(int64_t)r * nslots + blockIdx.x];
+    if (e < 0) continue;
+    const PanelTaskDev t = tasks[e >> 8];
+    panel_body<RPL>(t.X, t.rs, t.cs, t.nrows, t.ncols, t.R, t.nwg, t.pos, t.rstep, t.piv_row,
+                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem, t0);
+    __syncthreads();
+  }
+}
+
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t lds_for(int R, int ncols) {
@@ -557,6 +587,46 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
   if (e != hipSuccess) return e;
   return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kThreads), args, (unsigned)plan.lds_bytes,
                                     s);
+}
+
+int64_t panel_rec_stride(int ncols) { return rec_stride_for(ncols); }
+
+size_t panel_lds_bytes(int R, int ncols) { return lds_for(R, ncols); }
+
+namespace {
+const void* batched_fn(int max_R) {
+  return max_R <= 64 ? (const void*)panel_lu_batched_kernel<1>
+       : max_R <= 128 ? (const void*)panel_lu_batched_kernel<2>
+       : max_R <= 256 ? (const void*)panel_lu_batched_kernel<4>
+                      : (const void*)panel_lu_batched_kernel<8>;
+}
+}  // namespace
+
+int panel_batched_slots(int max_R, size_t lds_bytes, int cus) {
+  const void* fn = batched_fn(max_R);
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes) !=
+      hipSuccess)
+    return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds_bytes) !=
+      hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+// An ordinary launch (so that it can be captured in a graph): the grid never
+// exceeds what the device holds at once (panel_batched_slots), and every
+// wait is bounded, so workgroups that start late only delay their partners.
+hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, int rounds,
+                                   int nslots, int max_R, size_t lds_bytes,
+                                   long long timeout_ticks, hipStream_t s) {
+  if (rounds <= 0 || nslots <= 0) return hipSuccess;
+  const void* fn = batched_fn(max_R);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds_bytes);
+  if (e != hipSuccess) return e;
+  void* args[] = {&tasks, &sched, &rounds, &nslots, &timeout_ticks};
+  return hipLaunchKernel(fn, dim3(nslots), dim3(kThreads), args, lds_bytes, s);
 }
 
 }  // namespace rlu

@@ -15,8 +15,7 @@
 // Lv is the unit-lower factor of Step 3 in original row order; P enters
 // only through the row positions, never through a gather of A (Step 5:
 // L_y^T P A = Lv^T A).
-#include "../../include/rlu.h"
-#include "rlu_kernels.h"
+#include "rlu_internal.h"
 
 #include <hip/hip_runtime.h>
 
@@ -27,42 +26,14 @@
 #include <new>
 #include <type_traits>
 
-// Phases of rlu_factor that the timing facility reports.
-enum Phase {
-  PH_GAUSSIAN = 0, PH_SKETCH, PH_PANEL_Y, PH_GRAM, PH_GRAM_INV, PH_PROJECT, PH_SOLVE,
-  PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_COUNT
-};
 static const char* const kPhaseNames[PH_COUNT] = {
     "gaussian", "sketch_gemm", "panel_lu_y", "gram_gemm", "gram_inverse", "project_gemm",
-    "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm"};
+    "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm", "sketch_splitk_sum",
+    "project_splitk_sum"};
 
-struct TimingSlot {
-  hipEvent_t ev[PH_COUNT][2] = {};
-  bool used[PH_COUNT] = {};
-  bool valid = false;
-};
-
-struct rlu_handle_s {
-  int device = 0;
-  bool timing = false;
-  int ring_next = 0;        // next slot to fill
-  int ring_filled = 0;      // number of valid slots
-  TimingSlot ring[RLU_TIMING_RING];
-  TimingSlot* cur = nullptr;
-  int cus = 256;
-  hipStream_t side = nullptr;    // second stream for the Gram inverse
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  void* ws = nullptr;
-  size_t ws_bytes = 0;
-};
-
-namespace {
+namespace rlu_detail {
 
 using namespace rlu;
-
-constexpr long long kTimeoutTicks = 200LL * 1000 * 1000;  // 2 s of the 100 MHz clock
-
-size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t G = 0, Y = 0, part = 0, S = 0, C = 0, Bst = 0, Lb = 0;
@@ -153,16 +124,6 @@ rlu_status_t validate_io(const rlu_problem_t* pb, const rlu_buffers_t* io) {
   return RLU_OK;
 }
 
-#define HIP_TRY(expr)                                  \
-  do {                                                 \
-    hipError_t e_ = (expr);                            \
-    if (e_ != hipSuccess) {                            \
-      if (getenv("RLU_LOG"))                           \
-        fprintf(stderr, "librlu: %s failed: %s\n", #expr, hipGetErrorString(e_)); \
-      return RLU_ERR_DEVICE;                           \
-    }                                                  \
-  } while (0)
-
 rlu_status_t ensure_ws(rlu_handle_s* h, size_t bytes) {
   if (bytes <= h->ws_bytes) return RLU_OK;
   if (h->ws) {
@@ -177,24 +138,6 @@ rlu_status_t ensure_ws(rlu_handle_s* h, size_t bytes) {
   h->ws_bytes = bytes;
   return RLU_OK;
 }
-
-template <typename P>
-P* at(void* base, size_t off) { return (P*)((char*)base + off); }
-
-// Event pair around a phase when timing is on (recorded on the phase's stream).
-struct PhaseScope {
-  rlu_handle_s* h; int id; hipStream_t s; bool on;
-  PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
-      : h(h_), id(id_), s(s_), on(h_->timing && h_->cur) {
-    if (on) {
-      h->cur->used[id] = true;
-      hipEventRecord(h->cur->ev[id][0], s);
-    }
-  }
-  ~PhaseScope() {
-    if (on) hipEventRecord(h->cur->ev[id][1], s);
-  }
-};
 
 rlu_status_t begin_timing(rlu_handle_s* h) {
   h->cur = nullptr;
@@ -211,6 +154,13 @@ rlu_status_t begin_timing(rlu_handle_s* h) {
   if (h->ring_filled < RLU_TIMING_RING) ++h->ring_filled;
   return RLU_OK;
 }
+
+}  // namespace rlu_detail
+
+namespace {
+
+using namespace rlu;
+using namespace rlu_detail;
 
 // The FP64 path (T = double) and the FP32 path (T = float: FP32 storage of
 // A, G, L, U and FP32 MFMA for the two products with A).  The pivoted LUs,
@@ -263,9 +213,17 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.B = G; d.ldb = ldg; d.opb = OpB::Plain;
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
-    PhaseScope ph(h, PH_SKETCH, s);
-    if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
-    else HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
+    int ks = 1;
+    d.no_sum = true; d.ksplit_out = &ks;
+    {
+      PhaseScope ph(h, PH_SKETCH, s);
+      if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
+      else HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
+    }
+    if (ks > 1) {
+      PhaseScope ph(h, PH_SKETCH_SUM, s);
+      HIP_TRY(launch_splitk_sum_f64(m, l, ks, (const double*)d.partial, Y, m, nullptr, s));
+    }
   }
   if (diag && io.Y) {
     if (kF32) HIP_TRY((launch_convert2d<double, float>(Y, m, (float*)io.Y, io.ldy, m, l, s)));
@@ -306,9 +264,17 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
     d.C = C; d.ldc = k;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
-    PhaseScope ph(h, PH_PROJECT, s);
-    if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
-    else HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
+    int ks = 1;
+    d.no_sum = true; d.ksplit_out = &ks;
+    {
+      PhaseScope ph(h, PH_PROJECT, s);
+      if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
+      else HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
+    }
+    if (ks > 1) {
+      PhaseScope ph(h, PH_PROJECT_SUM, s);
+      HIP_TRY(launch_splitk_sum_f64(k, n, ks, (const double*)d.partial, C, k, nullptr, s));
+    }
   }
   HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {
@@ -364,6 +330,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
 
 }  // namespace
 
+using namespace rlu_detail;
+
 extern "C" {
 
 rlu_status_t rlu_create(rlu_handle_t* out, int device) {
@@ -381,8 +349,10 @@ rlu_status_t rlu_create(rlu_handle_t* out, int device) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cus = prop.multiProcessorCount;
   if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess) {
     hipSetDevice(prev);
     delete h;
     return RLU_ERR_DEVICE;
@@ -406,6 +376,12 @@ rlu_status_t rlu_destroy(rlu_handle_t h) {
   if (h->ev_fork) hipEventDestroy(h->ev_fork);
   if (h->ev_join) hipEventDestroy(h->ev_join);
   if (h->side) hipStreamDestroy(h->side);
+  if (h->bgraph.exec) hipGraphExecDestroy(h->bgraph.exec);
+  if (h->bgraph.graph) hipGraphDestroy(h->bgraph.graph);
+  if (h->bws) hipFree(h->bws);
+  if (h->stage) hipHostFree(h->stage);
+  if (h->ev_stage) hipEventDestroy(h->ev_stage);
+  if (h->cap) hipStreamDestroy(h->cap);
   hipSetDevice(prev);
   delete h;
   return RLU_OK;

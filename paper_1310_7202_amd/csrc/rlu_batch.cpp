@@ -1,0 +1,701 @@
+// rlu_factor_batched: Algorithm 4.1 (Shabat et al., Section 4) for many
+// independent problems of different shapes, each kernel of the method
+// launched once for the whole batch.
+//
+//   * Products (Steps 2, 5, 7) are grouped GEMMs: one launch computes the
+//     tiles of every problem, listed in a table of (problem, tile) pairs.
+//     Whole problems are dealt to the eight XCDs (largest first, to the
+//     least loaded) and a workgroup's index decides its XCD (b mod 8), so
+//     the tiles of one problem share that XCD's L2 (G in Step 2, Lv in
+//     Step 5).  The tile shape of each product comes from the tuning table
+//     below; the Gram product splits its long K.
+//   * The two pivoted LUs (Steps 3 and 6) run as one persistent launch each:
+//     every problem's panel is a "gang" of workgroups that exchange pivots,
+//     gangs are packed into rounds of at most the number of workgroups the
+//     device holds at once (chains of equal length together, members of a
+//     gang on one XCD where it fits), and each workgroup runs its members of
+//     successive rounds back to back.
+//   * The Gram inverses take one workgroup per problem; the assembly of p,
+//     q, U, L_b and info is one launch.
+// The launch sequence is captured once into a HIP graph and replayed while
+// the same problems and buffers come back; the task tables live in the
+// handle's batch workspace and are uploaded only when the batch changes.
+#include "rlu_internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+namespace {
+
+using namespace rlu;
+using namespace rlu_detail;
+
+struct Item {
+  rlu_problem_t pb;
+  rlu_buffers_t io;
+  size_t G = 0, Y = 0, S = 0, part = 0, C = 0, Bst = 0, Lb = 0;
+  size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
+  size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0;
+  size_t flags = 0, xy = 0, xb = 0;  // cleared before each run
+  int gram_ks = 1;
+  int nwg_y = 0, R_y = 0, nwg_b = 0, R_b = 0;
+};
+
+struct GemmLaunch {
+  int cfg = 0;
+  bool lp = false;
+  size_t tasks = 0, map = 0;  // table offsets
+  int ntasks = 0, nwg = 0;
+};
+
+struct PanelLaunch {
+  size_t tasks = 0, sched = 0;
+  int rounds = 0, nslots = 0, maxR = 0;
+  size_t lds = 0;
+};
+
+struct Plan {
+  std::vector<Item> items;
+  bool lp = false, fp16 = false, f32 = false;
+  size_t zero_bytes = 0;  // [0, zero_bytes) of the workspace: flags and exchange areas
+  size_t data_end = 0;
+  size_t tab_off = 0;     // tables start here
+  size_t total = 0;
+  std::vector<char> tab;  // host image of the tables
+  // launches
+  size_t gauss = 0; int n_gauss = 0; int64_t gauss_max = 0;
+  std::vector<GemmLaunch> sketch, gram, project, solve, forml;
+  size_t gram_all = 0; int gram_count = 0; int64_t gram_max = 0; bool gram_split = false;
+  PanelLaunch py, pbt;
+  size_t spd = 0; int64_t kmax = 0;
+  size_t asmb = 0; int64_t asm_max = 0;
+};
+
+// Panel shape of a batch: the largest rows-per-workgroup (a multiple of 64,
+// at most 512) whose LDS image fits for the widest panel.
+constexpr size_t kPanelLdsBudget = 159 * 1024;
+
+int panel_rows_for(int maxcols) {
+  for (int rpl = 8; rpl >= 1; rpl >>= 1)
+    if (panel_lds_bytes(64 * rpl, maxcols) <= kPanelLdsBudget) return 64 * rpl;
+  return 0;
+}
+
+// Tuning table of the grouped products (tile shape by output width N of
+// Step 2; every other product uses 64 x 64): a tile at least as wide as
+// the sketch reads each tile row of A once.
+int sketch_cfg(int64_t N) {
+  if (N <= 64) return GEMM_CFG_64x64;
+  if (N <= 112) return GEMM_CFG_64x112;
+  return GEMM_CFG_64x64;
+}
+
+// Gram product S = Lv^T Lv has a k x k output and K = m: split K so that a
+// problem's tiles are at most 512 deep.
+int gram_split_for(int64_t m) {
+  int ks = 1;
+  while (ks < 16 && m / (2 * ks) >= 512) ks *= 2;
+  return ks;
+}
+
+class TableWriter {
+ public:
+  explicit TableWriter(std::vector<char>& buf) : buf_(buf) {}
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    const size_t off = align_up(buf_.size(), 64);
+    buf_.resize(off + std::max<size_t>(v.size() * sizeof(T), 1));
+    if (!v.empty()) std::memcpy(buf_.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+ private:
+  std::vector<char>& buf_;
+};
+
+// Deal whole tasks to the 8 XCDs (largest first, least loaded XCD) and lay
+// the tiles out so that workgroup b, which runs on XCD b % 8, takes the next
+// tile of its XCD.  Padding entries have task -1.
+std::vector<int2> xcd_map(const std::vector<int>& ntiles, const std::vector<int>& task_id) {
+  std::vector<int> order(ntiles.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return ntiles[a] > ntiles[b]; });
+  std::array<std::vector<int2>, 8> lists;
+  std::array<long long, 8> load{};
+  for (int t : order) {
+    int x = 0;
+    for (int c = 1; c < 8; ++c)
+      if (load[c] < load[x]) x = c;
+    for (int i = 0; i < ntiles[t]; ++i) lists[x].push_back(int2{task_id[t], i});
+    load[x] += ntiles[t];
+  }
+  size_t len = 0;
+  for (auto& l : lists) len = std::max(len, l.size());
+  std::vector<int2> map(8 * len, int2{-1, 0});
+  for (int x = 0; x < 8; ++x)
+    for (size_t i = 0; i < lists[x].size(); ++i) map[x + 8 * i] = lists[x][i];
+  return map;
+}
+
+// Build the grouped launches of one product: tasks[i] with their tile shape
+// cfg[i]; one launch per distinct shape.
+void add_gemm_launches(TableWriter& tw, std::vector<GemmTaskDev> tasks, const std::vector<int>& cfg,
+                       bool lp, std::vector<GemmLaunch>& out) {
+  std::vector<int> shapes(cfg);
+  std::sort(shapes.begin(), shapes.end());
+  shapes.erase(std::unique(shapes.begin(), shapes.end()), shapes.end());
+  for (int c : shapes) {
+    std::vector<GemmTaskDev> sel;
+    std::vector<int> ntiles, ids;
+    for (size_t i = 0; i < tasks.size(); ++i) {
+      if (cfg[i] != c) continue;
+      GemmTaskDev t = tasks[i];
+      int bm, bn;
+      gemm_group_tile(c, &bm, &bn);
+      t.tiles_m = (int)((t.M + bm - 1) / bm);
+      t.tiles_n = (int)((t.N + bn - 1) / bn);
+      if (t.M <= 0 || t.N <= 0) continue;
+      ids.push_back((int)sel.size());
+      ntiles.push_back(t.tiles_m * t.tiles_n * std::max(1, t.ksplit));
+      sel.push_back(t);
+    }
+    if (sel.empty()) continue;
+    GemmLaunch L;
+    L.cfg = c;
+    L.lp = lp;
+    L.ntasks = (int)sel.size();
+    std::vector<int2> map = xcd_map(ntiles, ids);
+    L.nwg = (int)map.size();
+    L.tasks = tw.put(sel);
+    L.map = tw.put(map);
+    out.push_back(L);
+  }
+}
+
+// Pack gangs (one per panel) into rounds of nslots workgroups.  Longer
+// chains first; a gang goes to the first round with room, on one XCD if one
+// has enough free slots (the fullest such XCD), else spread over XCDs.
+int schedule_gangs(const std::vector<int>& nwg, const std::vector<int>& ncols, int nslots,
+                   std::vector<int>& sched) {
+  std::vector<int> order(nwg.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return ncols[a] != ncols[b] ? ncols[a] > ncols[b] : nwg[a] > nwg[b];
+  });
+  typedef std::array<std::vector<int>, 8> Free;
+  std::vector<Free> rounds;
+  std::vector<std::vector<int>> entries;  // per round: slot -> entry
+  auto new_round = [&]() {
+    Free f;
+    for (int b = nslots - 1; b >= 0; --b) f[b % 8].push_back(b);  // pop_back gives lowest
+    rounds.push_back(f);
+    entries.push_back(std::vector<int>(nslots, -1));
+  };
+  for (int t : order) {
+    const int need = nwg[t];
+    for (size_t r = 0;; ++r) {
+      if (r == rounds.size()) new_round();
+      Free& f = rounds[r];
+      int total = 0, best = -1;
+      for (int x = 0; x < 8; ++x) {
+        total += (int)f[x].size();
+        if ((int)f[x].size() >= need && (best < 0 || f[x].size() < f[best].size())) best = x;
+      }
+      if (total < need) continue;
+      std::vector<int> slots;
+      if (best >= 0) {
+        for (int i = 0; i < need; ++i) { slots.push_back(f[best].back()); f[best].pop_back(); }
+      } else {
+        while ((int)slots.size() < need) {
+          int x = 0;
+          for (int c = 1; c < 8; ++c)
+            if (f[c].size() > f[x].size()) x = c;
+          slots.push_back(f[x].back());
+          f[x].pop_back();
+        }
+      }
+      for (int i = 0; i < need; ++i) entries[r][slots[i]] = (t << 8) | i;
+      break;
+    }
+  }
+  sched.clear();
+  for (auto& e : entries) sched.insert(sched.end(), e.begin(), e.end());
+  return (int)rounds.size();
+}
+
+rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableWriter& tw,
+                         PanelLaunch& L) {
+  int maxcols = 0;
+  for (const Item& it : P.items) maxcols = std::max<int>(maxcols, (int)(second ? it.pb.k : it.pb.l));
+  const int R = panel_rows_for(maxcols);
+  if (R == 0) return RLU_ERR_UNSUPPORTED;
+  const size_t lds = panel_lds_bytes(R, maxcols);
+  int slots = panel_batched_slots(R, lds, cus);
+  if (slots <= 0) return RLU_ERR_DEVICE;
+  std::vector<PanelTaskDev> tasks;
+  std::vector<int> nwg, ncols;
+  for (const Item& it : P.items) {
+    PanelTaskDev t{};
+    if (!second) {
+      t.X = (double*)(base + it.Y); t.rs = 1; t.cs = it.pb.m;
+      t.nrows = (int)it.pb.m; t.ncols = (int)it.pb.l;
+      t.nwg = it.nwg_y; t.R = it.R_y;
+      t.pos = (int*)(base + it.pos_y); t.rstep = (int*)(base + it.rstep_y);
+      t.piv_row = (int*)(base + it.piv_y); t.ipiv = (int*)(base + it.ipiv_y);
+      t.info = (int*)(base + it.flags) + 0;
+      t.xch = base + it.xy;
+    } else {
+      t.X = (double*)(base + it.Bst); t.rs = it.pb.k; t.cs = 1;
+      t.nrows = (int)it.pb.n; t.ncols = (int)it.pb.k;
+      t.nwg = it.nwg_b; t.R = it.R_b;
+      t.pos = (int*)(base + it.pos_b); t.rstep = (int*)(base + it.rstep_b);
+      t.piv_row = (int*)(base + it.piv_b); t.ipiv = (int*)(base + it.ipiv_b);
+      t.info = (int*)(base + it.flags) + 1;
+      t.xch = base + it.xb;
+    }
+    t.fail = (int*)(base + it.flags) + 2;
+    t.rec_stride = panel_rec_stride(t.ncols);
+    if (t.nwg > slots || t.nwg > 255) return RLU_ERR_UNSUPPORTED;
+    tasks.push_back(t);
+    nwg.push_back(t.nwg);
+    ncols.push_back(t.ncols);
+  }
+  std::vector<int> sched;
+  L.rounds = schedule_gangs(nwg, ncols, slots, sched);
+  L.nslots = slots;
+  L.maxR = R;
+  L.lds = lds;
+  L.tasks = tw.put(tasks);
+  L.sched = tw.put(sched);
+  return RLU_OK;
+}
+
+// Data layout (no device addresses needed) and panel shapes.
+rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu_buffers_t* ios) {
+  P.items.resize(count);
+  const rlu_precision_t prec = pbs[0].precision;
+  P.lp = prec == RLU_PREC_MIXED_BF16 || prec == RLU_PREC_MIXED_FP16;
+  P.fp16 = prec == RLU_PREC_MIXED_FP16;
+  P.f32 = pbs[0].dtype == RLU_F32;
+  int maxl = 0, maxk = 0;
+  for (int i = 0; i < count; ++i) {
+    maxl = std::max<int>(maxl, (int)pbs[i].l);
+    maxk = std::max<int>(maxk, (int)pbs[i].k);
+  }
+  const int Ry = panel_rows_for(maxl), Rb = panel_rows_for(maxk);
+  if (Ry == 0 || Rb == 0) return RLU_ERR_UNSUPPORTED;
+  size_t off = 0;
+  auto take = [&](size_t& slot, size_t bytes) {
+    slot = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+  };
+  // cleared region first
+  for (int i = 0; i < count; ++i) {
+    Item& it = P.items[i];
+    it.pb = pbs[i];
+    it.io = ios[i];
+    const rlu_problem_t& pb = it.pb;
+    it.nwg_y = (int)((pb.m + Ry - 1) / Ry);
+    it.R_y = (int)((pb.m + it.nwg_y - 1) / it.nwg_y);
+    it.nwg_b = (int)((pb.n + Rb - 1) / Rb);
+    it.R_b = (int)((pb.n + it.nwg_b - 1) / it.nwg_b);
+    take(it.flags, 64);
+    take(it.xy, it.nwg_y > 1 ? 2 * (size_t)it.nwg_y * panel_rec_stride((int)pb.l) : 0);
+    take(it.xb, it.nwg_b > 1 ? 2 * (size_t)it.nwg_b * panel_rec_stride((int)pb.k) : 0);
+  }
+  P.zero_bytes = off;
+  const size_t d = sizeof(double);
+  for (int i = 0; i < count; ++i) {
+    Item& it = P.items[i];
+    const int64_t m = it.pb.m, n = it.pb.n, k = it.pb.k, l = it.pb.l;
+    const size_t sa = it.pb.dtype == RLU_F32 ? sizeof(float) : sizeof(double);
+    take(it.G, it.pb.G ? 0 : (size_t)n * l * sa);
+    take(it.Y, (size_t)m * l * d);
+    it.gram_ks = gram_split_for(m);
+    take(it.part, it.gram_ks > 1 ? (size_t)it.gram_ks * k * k * d : 0);
+    take(it.S, (size_t)k * k * d);
+    take(it.C, (size_t)k * n * d);
+    take(it.Bst, (size_t)k * n * d);
+    take(it.Lb, (size_t)k * k * d);
+    take(it.pos_y, (size_t)m * 4);
+    take(it.rstep_y, (size_t)m * 4);
+    take(it.piv_y, (size_t)l * 4);
+    take(it.ipiv_y, (size_t)l * 4);
+    take(it.pos_b, (size_t)n * 4);
+    take(it.rstep_b, (size_t)n * 4);
+    take(it.piv_b, (size_t)k * 4);
+    take(it.ipiv_b, (size_t)k * 4);
+  }
+  P.data_end = off;
+  P.tab_off = off;
+  return RLU_OK;
+}
+
+// Task tables for the workspace at `base` (base may be null to size them).
+rlu_status_t build_tables(Plan& P, char* base, int cus) {
+  P.tab.clear();
+  P.sketch.clear(); P.gram.clear(); P.project.clear(); P.solve.clear(); P.forml.clear();
+  TableWriter tw(P.tab);
+  // Step 1
+  std::vector<GaussTaskDev> gauss;
+  P.gauss_max = 0;
+  for (const Item& it : P.items) {
+    if (it.pb.G) continue;
+    gauss.push_back(GaussTaskDev{base + it.G, it.pb.n, it.pb.n, it.pb.l, it.pb.seed});
+    P.gauss_max = std::max<int64_t>(P.gauss_max, it.pb.n * it.pb.l);
+  }
+  P.n_gauss = (int)gauss.size();
+  P.gauss = tw.put(gauss);
+  // Step 2: Y = A G
+  {
+    std::vector<GemmTaskDev> t;
+    std::vector<int> cfg;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};
+      g.M = it.pb.m; g.N = it.pb.l; g.K = it.pb.n;
+      g.A = it.io.A; g.lda = it.io.lda;
+      g.B = it.pb.G ? it.pb.G : (const void*)(base + it.G);
+      g.ldb = it.pb.G ? it.pb.ldg : it.pb.n;
+      g.C = base + it.Y; g.ldc = it.pb.m;
+      g.ksplit = 1;
+      t.push_back(g);
+      cfg.push_back(P.lp ? GEMM_CFG_64x64 : sketch_cfg(g.N));
+    }
+    add_gemm_launches(tw, t, cfg, P.lp, P.sketch);
+  }
+  // Step 3
+  rlu_status_t st = plan_panels(P, false, cus, base, tw, P.py);
+  if (st != RLU_OK) return st;
+  // Step 5: S = Lv^T Lv (split K), S <- S^{-1}, C = Lv^T A, B = S^{-1} C
+  {
+    std::vector<GemmTaskDev> t;
+    std::vector<int> cfg;
+    P.gram_max = 0;
+    P.gram_split = false;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};
+      g.M = it.pb.k; g.N = it.pb.k; g.K = it.pb.m;
+      g.A = base + it.Y; g.lda = it.pb.m; g.astep = (const int*)(base + it.rstep_y);
+      g.B = base + it.Y; g.ldb = it.pb.m; g.bstep = (const int*)(base + it.rstep_y);
+      g.C = base + it.S; g.ldc = it.pb.k;
+      g.ksplit = it.gram_ks;
+      g.partial = it.gram_ks > 1 ? (void*)(base + it.part) : nullptr;
+      if (it.gram_ks > 1) P.gram_split = true;
+      P.gram_max = std::max<int64_t>(P.gram_max, it.pb.k * it.pb.k);
+      t.push_back(g);
+      cfg.push_back(GEMM_CFG_64x64);
+    }
+    add_gemm_launches(tw, t, cfg, false, P.gram);
+    // all tasks again, in problem order, for the split-K sums
+    for (auto& g : t) {
+      g.tiles_m = g.tiles_n = 1;
+    }
+    P.gram_count = (int)t.size();
+    P.gram_all = tw.put(t);
+  }
+  {
+    std::vector<SpdTaskDev> spd;
+    P.kmax = 0;
+    for (const Item& it : P.items) {
+      spd.push_back(SpdTaskDev{(double*)(base + it.S), (int)it.pb.k});
+      P.kmax = std::max<int64_t>(P.kmax, it.pb.k);
+    }
+    P.spd = tw.put(spd);
+  }
+  {
+    std::vector<GemmTaskDev> t;
+    std::vector<int> cfg;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};
+      g.M = it.pb.k; g.N = it.pb.n; g.K = it.pb.m;
+      g.A = base + it.Y; g.lda = it.pb.m; g.astep = (const int*)(base + it.rstep_y);
+      g.B = it.io.A; g.ldb = it.io.lda;
+      g.C = base + it.C; g.ldc = it.pb.k;
+      g.ksplit = 1;
+      t.push_back(g);
+      cfg.push_back(GEMM_CFG_64x64);
+    }
+    add_gemm_launches(tw, t, cfg, P.lp, P.project);
+  }
+  {
+    std::vector<GemmTaskDev> t;
+    std::vector<int> cfg;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};
+      g.M = it.pb.k; g.N = it.pb.n; g.K = it.pb.k;
+      g.A = base + it.S; g.lda = it.pb.k;
+      g.B = base + it.C; g.ldb = it.pb.k;
+      g.C = base + it.Bst; g.ldc = it.pb.k;
+      g.ksplit = 1;
+      t.push_back(g);
+      cfg.push_back(GEMM_CFG_64x64);
+    }
+    add_gemm_launches(tw, t, cfg, false, P.solve);
+  }
+  // Step 6
+  st = plan_panels(P, true, cus, base, tw, P.pbt);
+  if (st != RLU_OK) return st;
+  // Steps 7-8
+  {
+    std::vector<AsmTaskDev> a;
+    P.asm_max = 0;
+    for (const Item& it : P.items) {
+      AsmTaskDev x{};
+      x.pos_y = (const int*)(base + it.pos_y);
+      x.pos_b = (const int*)(base + it.pos_b);
+      x.Bst = (const double*)(base + it.Bst);
+      x.piv_b = (const int*)(base + it.piv_b);
+      x.rstep_b = (const int*)(base + it.rstep_b);
+      x.m = it.pb.m; x.n = it.pb.n; x.k = it.pb.k;
+      x.p = it.io.p; x.q = it.io.q;
+      x.U = it.io.U; x.ldu = it.io.ldu;
+      x.Lb = (double*)(base + it.Lb);
+      x.flags = (const int*)(base + it.flags);
+      x.info = it.io.info;
+      a.push_back(x);
+      P.asm_max = std::max<int64_t>(P.asm_max, x.m + x.n + x.k * x.n + x.k * x.k);
+    }
+    P.asmb = tw.put(a);
+  }
+  {
+    std::vector<GemmTaskDev> t;
+    std::vector<int> cfg;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};
+      g.M = it.pb.m; g.N = it.pb.k; g.K = it.pb.k;
+      g.A = base + it.Y; g.lda = it.pb.m; g.astep = (const int*)(base + it.rstep_y);
+      g.B = base + it.Lb; g.ldb = it.pb.k;
+      g.C = it.io.L; g.ldc = it.io.ldl;
+      g.rowmap = (const int*)(base + it.pos_y);
+      g.ksplit = 1;
+      t.push_back(g);
+      cfg.push_back(GEMM_CFG_64x64);
+    }
+    add_gemm_launches(tw, t, cfg, false, P.forml);
+  }
+  P.total = P.tab_off + align_up(P.tab.size());
+  return RLU_OK;
+}
+
+template <typename T>
+rlu_status_t enqueue_gemms(const std::vector<GemmLaunch>& ls, char* tab, OpA opa, OpB opb,
+                           int which, bool fp16, hipStream_t s) {
+  for (const GemmLaunch& L : ls) {
+    const GemmTaskDev* t = (const GemmTaskDev*)(tab + L.tasks);
+    const int2* map = (const int2*)(tab + L.map);
+    if (L.lp) {
+      HIP_TRY(launch_gemm_lp_grouped(opa, fp16, t, map, L.nwg, s));
+      continue;
+    }
+    switch (which) {
+      case 0: HIP_TRY((launch_gemm_grouped<T, T, T, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
+      case 1: HIP_TRY((launch_gemm_grouped<double, T, T, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
+      case 2: HIP_TRY((launch_gemm_grouped<double, double, double, T>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
+      default: HIP_TRY((launch_gemm_grouped<double, double, double, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
+    }
+  }
+  return RLU_OK;
+}
+
+// The launch sequence of a batch on stream s.
+template <typename T>
+rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, hipStream_t s) {
+  char* base = (char*)h->bws;
+  char* tab = base + P.tab_off;
+  const int count = (int)P.items.size();
+  HIP_TRY(launch_fill_u32((uint32_t*)base, P.zero_bytes / 4, 0u, s));
+  if (P.n_gauss > 0) {
+    PhaseScope ph(h, PH_GAUSSIAN, s);
+    HIP_TRY(launch_gaussian_batched<T>((const GaussTaskDev*)(tab + P.gauss), P.n_gauss,
+                                       P.gauss_max, s));
+  }
+  {
+    PhaseScope ph(h, PH_SKETCH, s);
+    rlu_status_t st = enqueue_gemms<T>(P.sketch, tab, OpA::Plain, OpB::Plain, 0, P.fp16, s);
+    if (st != RLU_OK) return st;
+  }
+  {
+    PhaseScope ph(h, PH_PANEL_Y, s);
+    HIP_TRY(launch_panel_lu_batched((const PanelTaskDev*)(tab + P.py.tasks),
+                                    (const int*)(tab + P.py.sched), P.py.rounds, P.py.nslots,
+                                    P.py.maxR, P.py.lds, kTimeoutTicks, s));
+  }
+  {
+    PhaseScope ph(h, PH_GRAM, s);
+    rlu_status_t st = enqueue_gemms<T>(P.gram, tab, OpA::LvT, OpB::Lv, 3, false, s);
+    if (st != RLU_OK) return st;
+    if (P.gram_split)
+      HIP_TRY(launch_splitk_sum_grouped((const GemmTaskDev*)(tab + P.gram_all), P.gram_count,
+                                        P.gram_max, s));
+  }
+  {
+    PhaseScope ph(h, PH_GRAM_INV, s);
+    HIP_TRY(launch_spd_inverse_batched((const SpdTaskDev*)(tab + P.spd), count, P.kmax, s));
+  }
+  {
+    PhaseScope ph(h, PH_PROJECT, s);
+    rlu_status_t st = enqueue_gemms<T>(P.project, tab, OpA::LvT, OpB::Plain, 1, P.fp16, s);
+    if (st != RLU_OK) return st;
+  }
+  {
+    PhaseScope ph(h, PH_SOLVE, s);
+    rlu_status_t st = enqueue_gemms<T>(P.solve, tab, OpA::Plain, OpB::Plain, 3, false, s);
+    if (st != RLU_OK) return st;
+  }
+  {
+    PhaseScope ph(h, PH_PANEL_B, s);
+    HIP_TRY(launch_panel_lu_batched((const PanelTaskDev*)(tab + P.pbt.tasks),
+                                    (const int*)(tab + P.pbt.sched), P.pbt.rounds, P.pbt.nslots,
+                                    P.pbt.maxR, P.pbt.lds, kTimeoutTicks, s));
+  }
+  {
+    PhaseScope ph(h, PH_ASSEMBLE, s);
+    HIP_TRY(launch_assemble_batched<T>((const AsmTaskDev*)(tab + P.asmb), count, P.asm_max, s));
+  }
+  {
+    PhaseScope ph(h, PH_FORM_L, s);
+    rlu_status_t st = enqueue_gemms<T>(P.forml, tab, OpA::Lv, OpB::Plain, 2, false, s);
+    if (st != RLU_OK) return st;
+  }
+  return RLU_OK;
+}
+
+rlu_status_t ensure_bws(rlu_handle_s* h, size_t bytes) {
+  if (bytes <= h->bws_bytes) return RLU_OK;
+  // the cached graph refers to the old workspace
+  if (h->bgraph.exec) { hipGraphExecDestroy(h->bgraph.exec); h->bgraph.exec = nullptr; }
+  if (h->bgraph.graph) { hipGraphDestroy(h->bgraph.graph); h->bgraph.graph = nullptr; }
+  h->bgraph.sig.clear();
+  if (h->bws) {
+    if (hipFree(h->bws) != hipSuccess) return RLU_ERR_DEVICE;
+    h->bws = nullptr;
+    h->bws_bytes = 0;
+  }
+  if (hipMalloc(&h->bws, bytes) != hipSuccess) {
+    h->bws = nullptr;
+    return RLU_ERR_OUT_OF_MEMORY;
+  }
+  h->bws_bytes = bytes;
+  return RLU_OK;
+}
+
+rlu_status_t upload_tables(rlu_handle_s* h, const Plan& P, hipStream_t s) {
+  const size_t bytes = P.tab.size();
+  if (bytes == 0) return RLU_OK;
+  HIP_TRY(hipEventSynchronize(h->ev_stage));  // the previous upload has left the stage
+  if (bytes > h->stage_bytes) {
+    if (h->stage) HIP_TRY(hipHostFree(h->stage));
+    h->stage = nullptr;
+    h->stage_bytes = 0;
+    if (hipHostMalloc(&h->stage, bytes, hipHostMallocDefault) != hipSuccess) {
+      h->stage = nullptr;
+      return RLU_ERR_OUT_OF_MEMORY;
+    }
+    h->stage_bytes = bytes;
+  }
+  std::memcpy(h->stage, P.tab.data(), bytes);
+  HIP_TRY(hipMemcpyAsync((char*)h->bws + P.tab_off, h->stage, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(h->ev_stage, s));
+  return RLU_OK;
+}
+
+void drop_graph(rlu_handle_s* h) {
+  if (h->bgraph.exec) hipGraphExecDestroy(h->bgraph.exec);
+  if (h->bgraph.graph) hipGraphDestroy(h->bgraph.graph);
+  h->bgraph.exec = nullptr;
+  h->bgraph.graph = nullptr;
+  h->bgraph.sig.clear();
+}
+
+template <typename T>
+rlu_status_t capture(rlu_handle_s* h, const Plan& P) {
+  HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  rlu_status_t st = enqueue<T>(h, P, h->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap, &g);
+  if (st != RLU_OK || e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return st != RLU_OK ? st : RLU_ERR_DEVICE;
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(g);
+    return RLU_ERR_DEVICE;
+  }
+  h->bgraph.graph = g;
+  h->bgraph.exec = x;
+  return RLU_OK;
+}
+
+std::vector<char> signature(rlu_handle_s* h, int count, const rlu_problem_t* pbs,
+                            const rlu_buffers_t* ios) {
+  std::vector<char> sig(sizeof(int) + sizeof(void*) + sizeof(int) +
+                        count * (sizeof(rlu_problem_t) + sizeof(rlu_buffers_t)));
+  char* p = sig.data();
+  std::memcpy(p, &count, sizeof(int)); p += sizeof(int);
+  std::memcpy(p, &h->bws, sizeof(void*)); p += sizeof(void*);
+  std::memcpy(p, &h->cus, sizeof(int)); p += sizeof(int);
+  std::memcpy(p, pbs, count * sizeof(rlu_problem_t)); p += count * sizeof(rlu_problem_t);
+  std::memcpy(p, ios, count * sizeof(rlu_buffers_t));
+  return sig;
+}
+
+}  // namespace
+
+extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
+                                           const rlu_problem_t* pbs, const rlu_buffers_t* ios,
+                                           rlu_stream_t stream) {
+  if (!h || count < 0 || (count > 0 && (!pbs || !ios))) return RLU_ERR_INVALID_ARG;
+  if (count == 0) return RLU_OK;
+  for (int i = 0; i < count; ++i) {
+    rlu_status_t st = validate(&pbs[i]);
+    if (st != RLU_OK) return st;
+    st = validate_io(&pbs[i], &ios[i]);
+    if (st != RLU_OK) return st;
+    if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
+    if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
+      return RLU_ERR_INVALID_ARG;
+  }
+  DeviceScope dev(h->device);
+  if (!dev.ok) return RLU_ERR_DEVICE;
+  hipStream_t s = (hipStream_t)stream;
+
+  Plan P;
+  rlu_status_t st = plan_layout(P, count, pbs, ios);
+  if (st != RLU_OK) return st;
+  st = build_tables(P, nullptr, h->cus);  // sizes only
+  if (st != RLU_OK) return st;
+  st = ensure_bws(h, P.total);
+  if (st != RLU_OK) return st;
+
+  const bool f32 = pbs[0].dtype == RLU_F32;
+  if (!h->timing) {
+    std::vector<char> sig = signature(h, count, pbs, ios);
+    if (h->bgraph.exec && sig == h->bgraph.sig) {
+      HIP_TRY(hipGraphLaunch(h->bgraph.exec, s));
+      return RLU_OK;
+    }
+    drop_graph(h);
+    st = build_tables(P, (char*)h->bws, h->cus);
+    if (st != RLU_OK) return st;
+    st = upload_tables(h, P, s);
+    if (st != RLU_OK) return st;
+    st = f32 ? capture<float>(h, P) : capture<double>(h, P);
+    if (st != RLU_OK) return st;
+    h->bgraph.sig = std::move(sig);
+    HIP_TRY(hipGraphLaunch(h->bgraph.exec, s));
+    return RLU_OK;
+  }
+  // timed calls run the same sequence eagerly, with phase events
+  drop_graph(h);
+  st = build_tables(P, (char*)h->bws, h->cus);
+  if (st != RLU_OK) return st;
+  st = upload_tables(h, P, s);
+  if (st != RLU_OK) return st;
+  st = begin_timing(h);
+  if (st != RLU_OK) return st;
+  return f32 ? enqueue<float>(h, P, s) : enqueue<double>(h, P, s);
+}

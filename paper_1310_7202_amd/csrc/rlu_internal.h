@@ -1,0 +1,107 @@
+// Host-side state shared by the translation units of the C ABI (rlu_api.cpp,
+// rlu_batch.cpp): the handle, argument validation, workspace and timing
+// helpers.
+#pragma once
+
+#include "../../include/rlu.h"
+#include "rlu_kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+// Phases of rlu_factor / rlu_factor_batched that the timing facility reports.
+enum Phase {
+  PH_GAUSSIAN = 0, PH_SKETCH, PH_PANEL_Y, PH_GRAM, PH_GRAM_INV, PH_PROJECT, PH_SOLVE,
+  PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_SKETCH_SUM, PH_PROJECT_SUM, PH_COUNT
+};
+
+struct TimingSlot {
+  hipEvent_t ev[PH_COUNT][2] = {};
+  bool used[PH_COUNT] = {};
+  bool valid = false;
+};
+
+// The launch sequence of one batch, captured once and replayed while the
+// same problems and buffers come back.
+struct BatchGraph {
+  std::vector<char> sig;       // problems, buffers and workspace base it was built for
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct rlu_handle_s {
+  int device = 0;
+  bool timing = false;
+  int ring_next = 0;        // next slot to fill
+  int ring_filled = 0;      // number of valid slots
+  TimingSlot ring[RLU_TIMING_RING];
+  TimingSlot* cur = nullptr;
+  int cus = 256;
+  hipStream_t side = nullptr;    // second stream for the Gram inverse
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void* ws = nullptr;            // workspace of rlu_factor
+  size_t ws_bytes = 0;
+  // rlu_factor_batched
+  void* bws = nullptr;           // batch workspace (data, exchange areas, task tables)
+  size_t bws_bytes = 0;
+  void* stage = nullptr;         // pinned staging of the task tables
+  size_t stage_bytes = 0;
+  hipEvent_t ev_stage = nullptr; // last upload from `stage` done
+  hipStream_t cap = nullptr;     // capture stream
+  BatchGraph bgraph;
+};
+
+namespace rlu_detail {
+
+constexpr long long kTimeoutTicks = 200LL * 1000 * 1000;  // 2 s of the 100 MHz clock
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+template <typename P>
+P* at(void* base, size_t off) { return (P*)((char*)base + off); }
+
+#define HIP_TRY(expr)                                                                \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      if (getenv("RLU_LOG"))                                                         \
+        fprintf(stderr, "librlu: %s failed: %s\n", #expr, hipGetErrorString(e_));    \
+      return RLU_ERR_DEVICE;                                                         \
+    }                                                                                \
+  } while (0)
+
+rlu_status_t validate(const rlu_problem_t* pb);
+rlu_status_t validate_io(const rlu_problem_t* pb, const rlu_buffers_t* io);
+rlu_status_t begin_timing(rlu_handle_s* h);
+
+// Event pair around a phase when timing is on (recorded on the phase's stream).
+struct PhaseScope {
+  rlu_handle_s* h; int id; hipStream_t s; bool on;
+  PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
+      : h(h_), id(id_), s(s_), on(h_->timing && h_->cur) {
+    if (on) {
+      h->cur->used[id] = true;
+      hipEventRecord(h->cur->ev[id][0], s);
+    }
+  }
+  ~PhaseScope() {
+    if (on) hipEventRecord(h->cur->ev[id][1], s);
+  }
+};
+
+// Scoped switch to the handle's device.
+struct DeviceScope {
+  int prev = 0; int dev; bool ok = true;
+  explicit DeviceScope(int d) : dev(d) {
+    hipGetDevice(&prev);
+    if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceScope() {
+    if (prev != dev) hipSetDevice(prev);
+  }
+};
+
+}  // namespace rlu_detail

@@ -11,6 +11,11 @@ namespace rlu {
 template <typename T>
 hipError_t launch_gaussian(T* G, int64_t ldg, int64_t n, int64_t l, uint64_t seed,
                            hipStream_t s);
+struct GaussTaskDev { void* G; int64_t ldg, n, l; uint64_t seed; };
+// One launch for a batch of test matrices (max_elems = largest n l).
+template <typename T>
+hipError_t launch_gaussian_batched(const GaussTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s);
 
 // ----- MFMA GEMM (gemm.hip) -----------------------------------------------
 // C(M x N) = op(A)(M x K) * op(B)(K x N), all column-major with leading
@@ -33,6 +38,8 @@ struct GemmDesc {
   int ksplit;          // 0: automatic split-K (uses `partial` if given), 1: none,
                        // >1: that many partial sums, added in a fixed order
   void* partial;       // partial-sum workspace (gemm_auto_partial_elems elements)
+  bool no_sum;         // with a split: leave the partial sums (launch_splitk_sum_f64 adds them)
+  int* ksplit_out;     // optional: receives the split used (1 = none)
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
@@ -54,6 +61,29 @@ hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s);
 size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K);
 // Tuning override of the tile shape (index into the compiled shapes; -1 = automatic).
 void gemm_force_config(int id);
+// Grouped form: many independent products in one launch.  Each workgroup
+// reads its (task, tile) from `map` (one int2 per workgroup).  Split-K
+// tasks (ksplit > 1) write `partial` (ksplit x M x N, FP64 output only) and
+// need launch_splitk_sum_grouped afterwards.
+struct GemmTaskDev {
+  int64_t M, N, K;
+  const void* A; int64_t lda; const int* astep;
+  const void* B; int64_t ldb; const int* bstep;
+  void* C; int64_t ldc; const int* rowmap;
+  void* partial; int ksplit; int tiles_m, tiles_n;
+};
+// Compiled shapes usable in grouped launches: 0 = 64 x 64, 1 = 64 x 112, 2 = 112 x 64.
+enum { GEMM_CFG_64x64 = 0, GEMM_CFG_64x112 = 1, GEMM_CFG_112x64 = 2 };
+void gemm_group_tile(int cfg, int* bm, int* bn);
+template <typename TA, typename TB, typename TC, typename TO>
+hipError_t launch_gemm_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks,
+                               const int2* map, int nwg, hipStream_t s);
+hipError_t launch_splitk_sum_grouped(const GemmTaskDev* tasks, int count, int64_t max_elems,
+                                     hipStream_t s);
+// Grouped low-precision products (64 x 64 tiles, no split-K): opa Plain
+// (FP32 A and G) or LvT (FP64 Lv as a hi + lo pair, FP32 A), FP64 output.
+hipError_t launch_gemm_lp_grouped(OpA opa, bool fp16, const GemmTaskDev* tasks, const int2* map,
+                                  int nwg, hipStream_t s);
 
 // ----- Pivoted LU of a tall matrix, rows spread over workgroups (panel_lu.hip)
 struct PanelDesc {
@@ -71,10 +101,31 @@ struct PanelDesc {
 struct PanelPlan { int rows_per_wg; int nwg; size_t lds_bytes; size_t xch_bytes; bool ok; };
 PanelPlan panel_plan(int nrows, int ncols, int device_cus, int max_wg_per_cu_hint);
 hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s);
+// One panel of a batched launch, as the device reads it.
+struct PanelTaskDev {
+  double* X; int64_t rs, cs;
+  int nrows, ncols, R, nwg;
+  int* pos; int* rstep; int* piv_row; int* ipiv; int* info; int* fail;
+  char* xch; int64_t rec_stride;
+};
+int64_t panel_rec_stride(int ncols);
+size_t panel_lds_bytes(int R, int ncols);
+// Workgroups of the batched panel kernel the device holds at once (0 on error).
+int panel_batched_slots(int max_R, size_t lds_bytes, int cus);
+// Persistent launch over many panels (tasks and the round schedule in device
+// memory; nslots workgroups, each round one panel member per workgroup).
+// Exchange areas must be zeroed beforehand.
+hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, int rounds,
+                                   int nslots, int max_R, size_t lds_bytes,
+                                   long long timeout_ticks, hipStream_t s);
 
 // ----- Inverse of the k x k Gram matrix (spd_inverse.hip) ------------------
 hipError_t launch_spd_inverse(double* S, int64_t k, hipStream_t s);  // in place
 bool spd_inverse_supported(int64_t k);
+struct SpdTaskDev { double* S; int k; };
+// One workgroup per matrix; the register tiling is chosen by the largest k.
+hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_t kmax,
+                                     hipStream_t s);
 
 // ----- Permutations and factor assembly (finish.hip) ------------------------
 hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
@@ -101,5 +152,16 @@ hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s)
 hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
                              int32_t* info_out, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);
+// Batched assembly of p, q, U (TO), L_b and info (max_elems = largest
+// m + n + k n + k k of the batch).
+struct AsmTaskDev {
+  const int* pos_y; const int* pos_b; const double* Bst; const int* piv_b; const int* rstep_b;
+  int64_t m, n, k;
+  int64_t* p; int64_t* q; void* U; int64_t ldu; double* Lb;
+  const int* flags; int32_t* info;
+};
+template <typename TO>
+hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s);
 
 }  // namespace rlu

@@ -29,8 +29,8 @@ __device__ __forceinline__ Words philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) gaussian_kernel(T* __restrict__ G, int64_t ldg, int64_t n,
-                                                       int64_t l, uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ void gaussian_body(T* __restrict__ G, int64_t ldg, int64_t n,
+                                              int64_t l, uint32_t k0, uint32_t k1) {
   const int64_t total = n * l;
   const int64_t npairs = (total + 1) >> 1;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs;
@@ -56,6 +56,20 @@ __global__ void __launch_bounds__(256) gaussian_kernel(T* __restrict__ G, int64_
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) gaussian_kernel(T* __restrict__ G, int64_t ldg, int64_t n,
+                                                       int64_t l, uint32_t k0, uint32_t k1) {
+  gaussian_body<T>(G, ldg, n, l, k0, k1);
+}
+
+// blockIdx.y selects the matrix of a batch
+template <typename T>
+__global__ void __launch_bounds__(256) gaussian_batched_kernel(const GaussTaskDev* __restrict__ tasks) {
+  const GaussTaskDev t = tasks[blockIdx.y];
+  gaussian_body<T>((T*)t.G, t.ldg, t.n, t.l, (uint32_t)(t.seed & 0xffffffffu),
+                   (uint32_t)(t.seed >> 32));
+}
+
 }  // namespace
 
 template <typename T>
@@ -74,5 +88,20 @@ template hipError_t launch_gaussian<double>(double*, int64_t, int64_t, int64_t, 
                                             hipStream_t);
 template hipError_t launch_gaussian<float>(float*, int64_t, int64_t, int64_t, uint64_t,
                                            hipStream_t);
+
+template <typename T>
+hipError_t launch_gaussian_batched(const GaussTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  int64_t bx = ((max_elems + 1) / 2 + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(gaussian_batched_kernel<T>, dim3((unsigned)bx, (unsigned)count), dim3(256),
+                     0, s, tasks);
+  return hipGetLastError();
+}
+template hipError_t launch_gaussian_batched<double>(const GaussTaskDev*, int, int64_t,
+                                                    hipStream_t);
+template hipError_t launch_gaussian_batched<float>(const GaussTaskDev*, int, int64_t,
+                                                   hipStream_t);
 
 }  // namespace rlu

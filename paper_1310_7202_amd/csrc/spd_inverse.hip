@@ -20,7 +20,7 @@ namespace {
 
 
 template <int TY, int NA, int NB>
-__global__ void __launch_bounds__(32 * TY) spd_inverse_kernel(double* __restrict__ S, int k) {
+__device__ __forceinline__ void spd_inverse_body(double* __restrict__ S, int k) {
   constexpr int KR = TY * NA, KC = 32 * NB;
   __shared__ double rowj[2][KC];
   __shared__ double colj[2][KR];
@@ -100,6 +100,19 @@ __global__ void __launch_bounds__(32 * TY) spd_inverse_kernel(double* __restrict
     }
 }
 
+template <int TY, int NA, int NB>
+__global__ void __launch_bounds__(32 * TY) spd_inverse_kernel(double* __restrict__ S, int k) {
+  spd_inverse_body<TY, NA, NB>(S, k);
+}
+
+// One workgroup per matrix of a batch.
+template <int TY, int NA, int NB>
+__global__ void __launch_bounds__(32 * TY)
+spd_inverse_batched_kernel(const SpdTaskDev* __restrict__ tasks) {
+  const SpdTaskDev t = tasks[blockIdx.x];
+  spd_inverse_body<TY, NA, NB>(t.S, t.k);
+}
+
 }  // namespace
 
 bool spd_inverse_supported(int64_t k) { return k >= 1 && k <= 208; }
@@ -114,6 +127,22 @@ hipError_t launch_spd_inverse(double* S, int64_t k, hipStream_t s) {
   else if (k <= 160) RLU_SPD(32, 5, 5);
   else if (k <= 192) RLU_SPD(32, 6, 6);
   else RLU_SPD(16, 13, 7);  // 208 x 224
+#undef RLU_SPD
+  return hipGetLastError();
+}
+
+hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_t kmax,
+                                     hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  if (!spd_inverse_supported(kmax)) return hipErrorInvalidValue;
+#define RLU_SPD(TY, NA, NB)                                                                 \
+  hipLaunchKernelGGL((spd_inverse_batched_kernel<TY, NA, NB>), dim3((unsigned)count),      \
+                     dim3(32 * TY), 0, s, tasks)
+  if (kmax <= 64) RLU_SPD(32, 2, 2);
+  else if (kmax <= 128) RLU_SPD(32, 4, 4);
+  else if (kmax <= 160) RLU_SPD(32, 5, 5);
+  else if (kmax <= 192) RLU_SPD(32, 6, 6);
+  else RLU_SPD(16, 13, 7);
 #undef RLU_SPD
   return hipGetLastError();
 }

@@ -143,6 +143,38 @@ def batch_problems(count: int = 256, seed: int = 104, mn_lo: int = 256,
     return out
 
 
+def batch_shapes(count: int = 256, seed: int = 104, mn_lo: int = 256, mn_hi: int = 4096,
+                 r_lo: int = 8, r_hi: int = 64):
+    """Shapes of the uneven batch (same draws as ``batch_problems``):
+    (m, n, r, data seed) with k = r and l = r + 8."""
+    g = rng(seed)
+    out = []
+    for _ in range(count):
+        m = int(g.integers(mn_lo, mn_hi + 1))
+        n = int(g.integers(mn_lo, mn_hi + 1))
+        r = int(g.integers(r_lo, r_hi + 1))
+        s = int(g.integers(0, 2 ** 62))
+        out.append((m, n, r, s))
+    return out
+
+
+def low_rank_plus_noise_torch(m: int, n: int, r: int, eps: float, seed: int,
+                              device: str = "cuda", dtype=None):
+    """Device-side ``low_rank_plus_noise`` (same recipe, torch RNG), returned
+    column-major (stride (1, m)) in ``dtype``."""
+    import torch
+
+    dtype = torch.float32 if dtype is None else dtype
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed % (2 ** 63))
+    X = torch.randn(m, r, generator=gen, device=device, dtype=torch.float64)
+    Y = torch.randn(n, r, generator=gen, device=device, dtype=torch.float64)
+    At = Y @ X.t()                       # n x m = A^T, contiguous -> A column-major
+    if eps:
+        At += eps * torch.randn(n, m, generator=gen, device=device, dtype=torch.float64)
+    return At.to(dtype).t()
+
+
 def serve_stream(count: int, seed: int = 105, m_lo: int = 512, m_hi: int = 32768,
                  n_lo: int = 512, n_hi: int = 8192, k_lo: int = 16, k_hi: int = 256):
     """Request shapes for the serving stream: m, n log-uniform, k uniform,
