@@ -6,9 +6,12 @@ arXiv 1310.7202) on one MI355X.
 
 A step is one complete rlu_factor call (Steps 1-8: Gaussian sketch matrix,
 sketch GEMM, pivoted LU of Y, Gram matrix and its inverse, projection GEMM,
-pivoted LU of B^T, assembly of L and U) on a device-resident input.  Prints
-one JSON line.  Only one GPU is used; --gpus N with N > 1 exits with a
-message.
+pivoted LU of B^T, assembly of L and U) on a device-resident input; for the
+batched workload a step is one rlu_factor_batched call over 256 problems.
+Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
+under "forms", the same matrix through the FP32 path and the 256-problem
+batch (disable with --forms none).  Only one GPU is used; --gpus N with
+N > 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -29,30 +32,41 @@ METRIC = "rank-k LU/s + %MFMA/HBM peak, mixed vs FP64 at equal error; p50/p99 la
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 
 WORKLOADS = {
-    # name: (m, n, k, l, spectrum, data seed, sketch seed, description)
-    "exp8192": (8192, 8192, 200, 210, "exp50", 102, 7204,
+    # name: (m, n, k, l, spectrum, data seed, sketch seed, precision, description)
+    "exp8192": (8192, 8192, 200, 210, "exp50", 102, 7204, "fp64",
                 "8192x8192, U and V Haar, sigma_i = exp(-i/50), k=200, l=210, FP64"),
-    "small512": (512, 512, 10, 15, "lowrank10", 101, 7203,
+    "exp8192_fp32": (8192, 8192, 200, 210, "exp50", 102, 7204, "fp32",
+                     "8192x8192, U and V Haar, sigma_i = exp(-i/50), k=200, l=210, FP32"),
+    "small512": (512, 512, 10, 15, "lowrank10", 101, 7203, "fp64",
                  "512x512, X Y^T + 1e-9 N(0,1), X, Y 512x10, k=10, l=15, FP64"),
 }
+BATCH = ("batch256", 256, 104, 7204,
+         "256 FP32 problems per call, m, n ~ U[256, 4096], A = X Y^T + 1e-6 N(0,1) with "
+         "rank r ~ U[8, 64], k = r, l = r + 8")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_input(name, torch):
+def make_input(name, torch, kind="spectral"):
     import numpy as np
     import workloads
 
-    m, n, k, l, spec, dseed, sseed, _ = WORKLOADS[name]
+    m, n, k, l, spec, dseed, sseed, prec, _ = WORKLOADS[name]
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    if kind == "gaussian":
+        # same shape, i.i.d. N(0,1) values (counter runs: traffic does not depend on values)
+        g = torch.Generator(device="cuda")
+        g.manual_seed(dseed)
+        return torch.randn(n, m, generator=g, device="cuda", dtype=dt).t(), k, l, sseed
     if spec == "exp50":
         A = workloads.spectral_matrix_torch(m, n, workloads.exp_decay(min(m, n), 50.0), dseed,
                                             device="cuda", dtype=torch.float64)
-        A = A.t().contiguous().t()       # column-major
+        A = A.t().contiguous().t().to(dt)       # column-major
     else:
         Ah, _, _ = workloads.config_small(dseed)
-        A = torch.from_numpy(np.ascontiguousarray(Ah.T)).cuda().t()
+        A = torch.from_numpy(np.ascontiguousarray(Ah.T)).cuda().t().to(dt)
     return A, k, l, sseed
 
 
@@ -127,12 +141,195 @@ def cpu_baseline(A_host, k, l, seed, budget_s):
                       f"in {el:.1f} s"}, out, G
 
 
+def phase_work(m, n, k, l, s_a, s_out):
+    """Algorithmic flops and HBM bytes of each timed phase for one problem
+    (what the method must do: dense products counted at 2 flops per
+    multiply-add, operands read once, results written once)."""
+    return {
+        "sketch_gemm": (2.0 * m * n * l, s_a * m * n + s_a * n * l + 8.0 * m * l),
+        "panel_lu_y": (m * l * l - l ** 3 / 3.0, 16.0 * m * l),
+        "gram_gemm": (2.0 * m * k * k, 8.0 * m * k),
+        "gram_inverse": (2.0 * k ** 3, 16.0 * k * k),
+        "project_gemm": (2.0 * m * n * k, s_a * m * n + 8.0 * m * k + 8.0 * k * n),
+        "solve_gemm": (2.0 * k * k * n, 16.0 * k * n + 8.0 * k * k),
+        "panel_lu_bt": (n * k * k - k ** 3 / 3.0, 16.0 * k * n),
+        "form_l_gemm": (2.0 * m * k * k, 8.0 * m * k + s_out * m * k),
+    }
+
+
+def kernel_table(phase_ms, works, mfma_peak):
+    """Per-phase achieved rates against the roofline of that phase: bound =
+    whichever of MFMA time and HBM time is larger; the two pivoted LUs are
+    chains of l (or k) dependent steps and are reported as latency-bound."""
+    out = {}
+    for name, (fl, by) in works.items():
+        t = phase_ms.get(name, 0.0) * 1e-3
+        if t <= 0:
+            continue
+        t_f, t_b = fl / mfma_peak, by / PEAK["hbm"]
+        if name.startswith("panel") or name == "gram_inverse":
+            bound = "latency"
+        else:
+            bound = "mfma" if t_f >= t_b else "hbm"
+        out[name] = {"ms": phase_ms[name], "tflops": fl / t / 1e12, "gbs": by / t / 1e9,
+                     "bound": bound, "roofline_frac": max(t_f, t_b) / t}
+    return out
+
+
+def sum_works(shapes, s_a, s_out):
+    tot = {}
+    for (m, n, k, l) in shapes:
+        for key, (f, b) in phase_work(m, n, k, l, s_a, s_out).items():
+            a = tot.get(key, (0.0, 0.0))
+            tot[key] = (a[0] + f, a[1] + b)
+    return tot
+
+
+def step_roofline(works, mfma_peak, ms_per_step):
+    """T_roof = max(GEMM flops / MFMA peak, GEMM bytes / HBM) + small-kernel
+    flops at the same peak, against the measured step time."""
+    gem = [k for k in works if k.endswith("gemm")]
+    f = sum(works[k][0] for k in gem)
+    b = sum(works[k][1] for k in gem)
+    tail = sum(v[0] for k, v in works.items() if k not in gem)
+    t_roof = max(f / mfma_peak, b / PEAK["hbm"]) + tail / PEAK["f64"]
+    return {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_per_step}
+
+
+def run_single(rlu, torch, np, name, steps, warmup, input_kind="spectral", check=True):
+    m, n, k, l = WORKLOADS[name][:4]
+    prec = WORKLOADS[name][7]
+    log(f"generating {WORKLOADS[name][8]}")
+    A, k, l, sseed = make_input(name, torch, input_kind)
+    torch.cuda.synchronize()
+    log("input ready")
+    h = rlu.Handle(0)
+    h.set_timing(True)
+    out = rlu.Factors(torch.empty((k, m), dtype=A.dtype, device="cuda").t(),
+                      torch.empty((n, k), dtype=A.dtype, device="cuda").t(),
+                      torch.empty(m, dtype=torch.int64, device="cuda"),
+                      torch.empty(n, dtype=torch.int64, device="cuda"),
+                      torch.empty(3, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
+    torch.cuda.synchronize()
+    log(f"warmup {warmup} done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"{name}: timed {steps} steps in {wall * 1e3:.1f} ms")
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    phases = [h.phase_times(back) for back in range(steps)]
+    ph = {key: float(np.mean([p[key] for p in phases])) for key in phases[0]}
+    s_a = 4.0 if prec == "fp32" else 8.0
+    peak = PEAK["f32"] if prec == "fp32" else PEAK["f64"]
+    works = phase_work(m, n, k, l, s_a, s_a)
+    res = {
+        "value": steps / wall, "ms_per_step": wall * 1e3 / steps,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean())},
+        "phase_ms": ph,
+        "kernels": kernel_table(ph, works, peak),
+        "step_roofline": step_roofline(works, peak, wall * 1e3 / steps),
+        "info": out.info.cpu().tolist(),
+    }
+    if check:
+        res["rel_residual"] = power_residual(A.double() if prec == "fp32" else A,
+                                             out.L.double(), out.U.double(), out.p, out.q)
+        log(f"{name}: relative residual {res['rel_residual']:.3e}")
+    return res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works)
+
+
+def run_batch(rlu, torch, np, steps, warmup):
+    import workloads
+
+    name, count, dseed, sseed, desc = BATCH
+    shapes = workloads.batch_shapes(count, seed=dseed)
+    log(f"generating {desc}")
+    As = [workloads.low_rank_plus_noise_torch(m, n, r, 1e-6, s) for m, n, r, s in shapes]
+    items = [(A, r, r + 8, sseed + i) for i, (A, (m, n, r, s)) in enumerate(zip(As, shapes))]
+    torch.cuda.synchronize()
+    h = rlu.Handle(0)
+    batch = rlu.Batch(items, precision=rlu.PREC_FP32)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, warmup)):
+        batch.run(h, stream)           # first call records the graph
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(stream)
+        batch.run(h, stream)           # graph replay
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    infos = torch.stack([f.info for f in batch.outs]).cpu().numpy()
+    log(f"batch: {steps} calls of {count} in {wall * 1e3:.1f} ms")
+    # phase breakdown from one eager (timed) call of the same batch
+    ht = rlu.Handle(0)
+    ht.set_timing(True)
+    rlu.Batch(items, precision=rlu.PREC_FP32).run(ht, stream)
+    torch.cuda.synchronize()
+    ph = ht.phase_times(0)
+    # the same problems as sequential rlu_factor calls
+    hs = rlu.Handle(0)
+    for (A, k, l, sd) in items[:8]:
+        rlu.factor(A, k, l, seed=sd, handle=hs, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for (A, k, l, sd) in items:
+        rlu.factor(A, k, l, seed=sd, handle=hs, stream=stream)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    dims = [(m, n, r, r + 8) for (m, n, r, s) in shapes]
+    works = sum_works(dims, 4.0, 4.0)
+    ms = wall * 1e3 / steps
+    # dominant kernel of the batch: the grouped sketch GEMM
+    f_sk, b_sk = works["sketch_gemm"]
+    t_sk = ph["sketch_gemm"] * 1e-3
+    hbm_bound = b_sk / PEAK["hbm"] >= f_sk / PEAK["f32"]
+    roof = ({"bound": "hbm", "achieved": b_sk / t_sk / 1e9, "peak": PEAK["hbm"] / 1e9,
+             "unit": "GB/s", "frac": b_sk / t_sk / PEAK["hbm"]} if hbm_bound else
+            {"bound": "mfma", "achieved": f_sk / t_sk / 1e12, "peak": PEAK["f32"] / 1e12,
+             "unit": "TFLOP/s", "frac": f_sk / t_sk / PEAK["f32"]})
+    roof.update({"traffic": None, "kernel": "grouped sketch GEMM (Step 2), FP32 MFMA 16x16x4",
+                 "algorithmic_flops_per_launch": f_sk, "algorithmic_bytes_per_launch": b_sk})
+    return {
+        "workload": desc, "value": count * steps / wall, "unit": "factorizations/s",
+        "ms_per_call": ms, "steps": steps,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "phase_ms_eager": ph,
+        "kernels": kernel_table(ph, works, PEAK["f32"]),
+        "step_roofline": step_roofline(works, PEAK["f32"], ms),
+        "roofline": roof,
+        "sequential_rlu_factor": {"factorizations_per_s": count / seq, "ms_total": seq * 1e3},
+        "exchange_failures": int((infos[:, 2] != 0).sum()),
+        "graph": "one captured HIP graph per batch, replayed",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
+    ap.add_argument("--forms", default="fp32,batch",
+                    help="extra measurements in the same line: comma list of fp32, batch, or none")
+    ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
+                    help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip the residual check after the timed steps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -160,53 +357,20 @@ def main():
         sys.exit(2)
 
     name = args.workload
-    m, n, k, l = WORKLOADS[name][:4]
-    log(f"generating {WORKLOADS[name][7]}")
-    A, k, l, sseed = make_input(name, torch)
-    torch.cuda.synchronize()
-    log("input ready")
+    res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works) = run_single(
+        rlu, torch, np, name, args.steps, args.warmup, args.input, not args.no_check)
 
-    h = rlu.Handle(0)
-    h.set_timing(True)
-    out = rlu.Factors(torch.empty((k, m), dtype=A.dtype, device="cuda").t(),
-                      torch.empty((n, k), dtype=A.dtype, device="cuda").t(),
-                      torch.empty(m, dtype=torch.int64, device="cuda"),
-                      torch.empty(n, dtype=torch.int64, device="cuda"),
-                      torch.empty(3, dtype=torch.int32, device="cuda"))
-    stream = torch.cuda.current_stream()
-    for i in range(args.warmup):
-        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
-
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs[i][0].record(stream)
-        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    log(f"timed {args.steps} steps in {wall * 1e3:.1f} ms")
-
-    lat = np.array([a.elapsed_time(b) for a, b in evs])
-    phases = [h.phase_times(back) for back in range(args.steps)]
-    ph_mean = {key: float(np.mean([p[key] for p in phases])) for key in phases[0]}
-    info = out.info.cpu().tolist()
-
-    flops_sketch = 2.0 * m * n * l
-    t_sketch = ph_mean["sketch_gemm"] * 1e-3
+    flops_sketch = works["sketch_gemm"][0]
+    t_sketch = res["phase_ms"]["sketch_gemm"] * 1e-3
     achieved = flops_sketch / t_sketch
     kernel_src = os.path.join(ROOT, "paper_1310_7202_amd", "csrc", "gemm.hip")
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["f64"] / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK["f64"],
-                "traffic": traffic_from_profiles(kernel_src),
-                "kernel": "sketch GEMM Y = A G (Step 2), FP64 MFMA 16x16x4",
-                "algorithmic_flops_per_launch": flops_sketch}
-    flops_total = (2.0 * m * n * (l + k) + m * l * l - l ** 3 / 3.0 + 3.0 * m * k * k + k ** 3
-                   + n * k * k - k ** 3 / 3.0 + m * k * k)
+    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic_from_profiles(kernel_src) if name == "exp8192" else None,
+                "kernel": "sketch GEMM Y = A G (Step 2), "
+                          + ("FP32" if prec == "fp32" else "FP64") + " MFMA 16x16x4",
+                "algorithmic_flops_per_launch": flops_sketch,
+                "algorithmic_bytes_per_launch": works["sketch_gemm"][1]}
 
     if args.calibrate_copy:
         src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -217,33 +381,68 @@ def main():
         log("copy calibration: 256 MiB read + 256 MiB written")
         del src, dst
 
-    rel_res = power_residual(A, out.L, out.U, out.p, out.q)
-    log(f"relative residual {rel_res:.3e}")
-
+    flops_total = sum(v[0] for v in works.values())
     result = {
         "metric": METRIC,
-        "value": args.steps / wall,
+        "value": res["value"],
         "unit": "factorizations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[name][7], "m": m, "n": n, "k": k, "l": l,
-                   "precision": "fp64", "sketch": "Philox4x32-10 Gaussian on device"},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean())},
-        "phase_ms": ph_mean,
-        "tflops_effective": flops_total / (wall / args.steps) / 1e12,
+        "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[name][8], "m": m, "n": n, "k": k, "l": l,
+                   "precision": prec, "sketch": "Philox4x32-10 Gaussian on device",
+                   "input": args.input},
+        "latency_ms": res["latency_ms"],
+        "phase_ms": res["phase_ms"],
+        "tflops_effective": flops_total / (res["ms_per_step"] * 1e-3) / 1e12,
         "roofline": roofline,
-        "check": {"rel_residual": rel_res, "info": info},
+        "kernels": res["kernels"],
+        "step_roofline": res["step_roofline"],
+        "check": {"rel_residual": res.get("rel_residual"), "info": res["info"]},
     }
 
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    result["forms"] = {}
+    if "fp32" in forms and name == "exp8192":
+        A32 = A.float()
+        A32 = A32.t().contiguous().t()
+        h32 = rlu.Handle(0)
+        h32.set_timing(True)
+        st = torch.cuda.current_stream()
+        for _ in range(3):
+            o32 = rlu.factor(A32, k, l, seed=sseed, handle=h32, stream=st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n32 = max(5, args.steps // 2)
+        for _ in range(n32):
+            o32 = rlu.factor(A32, k, l, seed=sseed, handle=h32, stream=st)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t0
+        ph32 = [h32.phase_times(b) for b in range(n32)]
+        ph32 = {key: float(np.mean([p[key] for p in ph32])) for key in ph32[0]}
+        works32 = phase_work(m, n, k, l, 4.0, 4.0)
+        r32 = power_residual(A, o32.L.double(), o32.U.double(), o32.p, o32.q)
+        result["forms"]["fp32"] = {
+            "workload": WORKLOADS["exp8192_fp32"][8], "value": n32 / w32,
+            "unit": "factorizations/s", "ms_per_step": w32 * 1e3 / n32, "phase_ms": ph32,
+            "kernels": kernel_table(ph32, works32, PEAK["f32"]),
+            "step_roofline": step_roofline(works32, PEAK["f32"], w32 * 1e3 / n32),
+            "rel_residual": r32,
+            "rel_residual_fp64_path": res.get("rel_residual"),
+            "speedup_vs_fp64": (n32 / w32) / res["value"]}
+        log(f"fp32 form: {n32 / w32:.1f}/s residual {r32:.3e}")
+        del A32, o32
+    if "batch" in forms:
+        result["forms"]["batch256"] = run_batch(rlu, torch, np, max(5, args.steps // 2), 2)
+        log(f"batch form: {result['forms']['batch256']['value']:.0f} factorizations/s")
+
     if not args.no_cpu_baseline:
-        A_host = A.cpu().numpy()
+        A_host = A.double().cpu().numpy() if prec == "fp32" else A.cpu().numpy()
         base, o, G = cpu_baseline(A_host, k, l, sseed, args.cpu_seconds)
         result["cpu_baseline"] = base
         # parity at full size: same G up to libm rounding on the two sides
-        L, U = out.L.cpu().numpy(), out.U.cpu().numpy()
+        L, U = out.L.double().cpu().numpy(), out.U.double().cpu().numpy()
         p, q = out.p.cpu().numpy(), out.q.cpu().numpy()
         Lu = np.empty_like(L); Lu[p] = L
         Lo = np.empty_like(o["L"]); Lo[o["p"]] = o["L"]

@@ -11,7 +11,7 @@ oracle uses 0-based index vectors with the same meaning):
     row (column) at position j was exchanged with the one at position
     ipiv[j] (qpiv[j]).
 
-Readings of the paper taken here (each is listed in the design doc as well):
+Readings of the paper taken here (where the paper is silent or leaves a choice):
   * Step 3 uses LU with partial pivoting (the Remark after Algorithm 4.1
     allows it in place of RRLU), factoring all l columns of Y; Step 4 then
     keeps the first k columns of L_y.

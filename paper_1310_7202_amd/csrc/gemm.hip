@@ -186,16 +186,36 @@ __device__ __forceinline__ void gemm_tile(
       }
 }
 
+// Workgroup b of a launch runs on XCD b mod 8.  Give each XCD a contiguous
+// range of tile indices, so that the workgroups an XCD runs at the same time
+// take consecutive tiles.
+__device__ __forceinline__ int xcd_chunked(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
+// One-dimensional grid of tm x tn x ksplit tiles.  Consecutive tiles share
+// the larger operand: with nfast the N index runs fastest (tiles of one row
+// block of A, Step 2 and Step 7), otherwise the M index (tiles of one
+// column block of B, Step 5), so that operand block is fetched from HBM once
+// and reused from the XCD's L2.
 template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
           int WN, int NBUF, OpA OA, OpB OB>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
             const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
             const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
-            const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial) {
+            const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int tm, int tn,
+            int nfast) {
+  const int t = xcd_chunked((int)blockIdx.x, (int)gridDim.x);
+  int bx, by, bz;
+  if (nfast) {
+    by = t % tn; const int rest = t / tn; bx = rest % tm; bz = rest / tm;
+  } else {
+    bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
+  }
   gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
-      M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, (int)blockIdx.x,
-      (int)blockIdx.y, (int)blockIdx.z);
+      M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, bx, by, bz);
 }
 
 // Many independent products in one launch: workgroup b computes the tile
@@ -299,11 +319,14 @@ GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
 template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, int BK, int WM,
           int WN, int NBUF, OpA OA, OpB OB>
 hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
-  dim3 grid((unsigned)((d.M + BM - 1) / BM), (unsigned)((d.N + BN - 1) / BN), (unsigned)ksplit);
-  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>), grid,
-                     dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A, d.lda, d.astep,
-                     (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap, ksplit,
-                     (TO*)d.partial);
+  const int tm = (int)((d.M + BM - 1) / BM), tn = (int)((d.N + BN - 1) / BN);
+  const int64_t nb = (int64_t)tm * tn * ksplit;
+  if (nb >= (1LL << 31)) return hipErrorInvalidValue;
+  const int nfast = d.M > d.N ? 1 : 0;  // A is the larger operand
+  hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>),
+                     dim3((unsigned)nb), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A,
+                     d.lda, d.astep, (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap,
+                     ksplit, (TO*)d.partial, tm, tn, nfast);
   return hipGetLastError();
 }
 

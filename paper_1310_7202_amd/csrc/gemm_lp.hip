@@ -171,15 +171,30 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
       }
 }
 
+// Workgroup b runs on XCD b mod 8: each XCD takes a contiguous range of
+// tiles, ordered so that consecutive tiles share the larger operand (N index
+// fastest when A is larger, else M), which is then read from HBM once.
+__device__ __forceinline__ int xcd_chunked_lp(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + min(x, r) + (b >> 3);
+}
+
 template <typename LP, typename TA, typename TB, typename TO, OpA OA, bool SPLIT, int BM, int BN,
           int WM, int WN>
 __global__ void __launch_bounds__(64 * WM * WN)
 gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
                const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
-               TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial) {
+               TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial, int tm,
+               int tn, int nfast) {
+  const int t = xcd_chunked_lp((int)blockIdx.x, (int)gridDim.x);
+  int bx, by, bz;
+  if (nfast) {
+    by = t % tn; const int rest = t / tn; bx = rest % tm; bz = rest / tm;
+  } else {
+    bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
+  }
   gemm_lp_tile<LP, TA, TB, TO, OA, SPLIT, BM, BN, WM, WN>(M, N, K, A, lda, astep, B, ldb, C, ldc,
-                                                          ksplit, partial, (int)blockIdx.x,
-                                                          (int)blockIdx.y, (int)blockIdx.z);
+                                                          ksplit, partial, bx, by, bz);
 }
 
 // Grouped form: workgroup b computes the tile map[b] = (task, bx + tiles_m by)
@@ -204,10 +219,12 @@ hipError_t launch_lp(const GemmDesc& d, hipStream_t s) {
   int ks = 1;
   if (d.partial)
     while (tiles * ks < 1024 && d.K / (ks * 2) >= 1024 && ks < 32) ks *= 2;
-  dim3 grid((unsigned)((d.M + BM - 1) / BM), (unsigned)((d.N + BN - 1) / BN), (unsigned)ks);
-  hipLaunchKernelGGL((gemm_lp_kernel<LP, TA, TB, double, OA, SPLIT, BM, BN, WM, WN>), grid,
-                     dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A, d.lda, d.astep,
-                     (const TB*)d.B, d.ldb, (double*)d.C, d.ldc, ks, (double*)d.partial);
+  const int tm = (int)((d.M + BM - 1) / BM), tn = (int)((d.N + BN - 1) / BN);
+  const int nfast = d.M > d.N ? 1 : 0;
+  hipLaunchKernelGGL((gemm_lp_kernel<LP, TA, TB, double, OA, SPLIT, BM, BN, WM, WN>),
+                     dim3((unsigned)((int64_t)tm * tn * ks)), dim3(64 * WM * WN), 0, s, d.M, d.N,
+                     d.K, (const TA*)d.A, d.lda, d.astep, (const TB*)d.B, d.ldb, (double*)d.C,
+                     d.ldc, ks, (double*)d.partial, tm, tn, nfast);
   if (d.ksplit_out) *d.ksplit_out = ks;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;
