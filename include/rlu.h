@@ -162,6 +162,81 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
 rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count, const rlu_problem_t* pbs,
                                 const rlu_buffers_t* ios, rlu_stream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * A server owns one scheduler thread, two streams and a handle on `device`.
+ * Submitted requests wait in a FIFO queue; the scheduler admits them in
+ * order while the HBM footprint of every admitted, unreleased request stays
+ * within hbm_budget_bytes (a request that alone exceeds the budget is
+ * rejected at submit with RLU_ERR_TOO_LARGE), and launches all admitted
+ * requests of the head's dtype and precision as one batch (the kernels of
+ * rlu_factor_batched) on a free stream.  Requests that arrive while batches
+ * run are admitted as memory frees up and overlap with them on the device.
+ * Each request's factors are those rlu_factor_batched gives for it alone.
+ * Footprint = the request's share of a batch workspace (freed when its batch
+ * completes) + its outputs L, U, p, q, info (held until rlu_serve_release).
+ * ---------------------------------------------------------------------- */
+typedef struct rlu_server_s* rlu_server_t;
+
+typedef struct {
+  int device;
+  size_t hbm_budget_bytes; /* 0: 90% of the device memory free at creation   */
+  int32_t max_inflight;    /* admitted, unfinished requests; 0 = no limit     */
+  int32_t max_queue;       /* queued requests; 0 = no limit                   */
+} rlu_server_config_t;
+
+typedef struct {
+  rlu_status_t status;     /* RLU_PENDING, RLU_OK, RLU_WARN_ZERO_PIVOT, or an
+                              error (RLU_ERR_DEVICE: exchange failure)        */
+  const void* L; int64_t ldl;  /* server-owned device outputs, valid until    */
+  const void* U; int64_t ldu;  /*   rlu_serve_release (NULL unless finished)  */
+  const int64_t* p;
+  const int64_t* q;
+  int32_t info[3];             /* the rlu_factor info words                   */
+  double t_submit_us, t_start_us, t_done_us;  /* server clock: submitted,
+                              launched in a batch, completion observed        */
+} rlu_result_t;
+
+rlu_status_t rlu_serve_create(const rlu_server_config_t* cfg, rlu_server_t* srv);
+
+/* Queue Algorithm 4.1 for the device matrix A (m x n, lda >= m; it must stay
+ * valid and unmodified until the request finishes).  pb->G must be NULL or a
+ * device matrix that stays valid likewise; RLU_FLAG_DIAGNOSTICS is not
+ * available.  Errors: argument errors, RLU_ERR_UNSUPPORTED (a shape the
+ * batched kernels cannot run), RLU_ERR_TOO_LARGE (footprint above the
+ * budget), RLU_ERR_QUEUE_FULL.  Thread-safe. */
+rlu_status_t rlu_serve_submit(rlu_server_t srv, const rlu_problem_t* pb, const void* A,
+                              int64_t lda, uint64_t* ticket);
+
+/* Non-blocking.  Returns the request's status (RLU_PENDING while queued or
+ * running) and, if out is not NULL, fills it.  RLU_ERR_UNKNOWN_TICKET for a
+ * ticket never issued or already released.  Thread-safe. */
+rlu_status_t rlu_serve_poll(rlu_server_t srv, uint64_t ticket, rlu_result_t* out);
+
+/* Copy a finished request's L, U, p, q (and info if dst->info is not NULL)
+ * into the caller's device buffers on `stream` (leading dimensions from
+ * dst).  RLU_PENDING if not finished.  Synchronize the stream before
+ * releasing the ticket. */
+rlu_status_t rlu_serve_copy(rlu_server_t srv, uint64_t ticket, const rlu_buffers_t* dst,
+                            rlu_stream_t stream);
+
+/* Free a finished request's outputs and forget the ticket (RLU_PENDING if
+ * it has not finished; nothing is released then). */
+rlu_status_t rlu_serve_release(rlu_server_t srv, uint64_t ticket);
+
+/* HBM footprint the server charges for this request, in bytes (no device
+ * needed). */
+rlu_status_t rlu_serve_footprint(const rlu_problem_t* pb, size_t* bytes);
+
+/* Bytes admitted and unreleased, queued and admitted-unfinished requests. */
+rlu_status_t rlu_serve_stats(rlu_server_t srv, size_t* used_bytes, int32_t* queued,
+                             int32_t* inflight);
+
+/* Finish every queued and running request, then free everything (tickets
+ * not released are freed too). */
+rlu_status_t rlu_serve_destroy(rlu_server_t srv);
+
 /* Phase timing for measurement tools.  When enabled, rlu_factor records a
  * HIP event pair around each phase on the stream that runs the phase (the
  * caller's stream, or the handle's side stream for the Gram inverse).  The

@@ -13,7 +13,8 @@ import ctypes
 import os
 from dataclasses import dataclass
 
-__all__ = ["RluError", "Handle", "factor", "factor_batched", "Batch", "lib", "status_string", "LIB_PATH",
+__all__ = ["RluError", "Handle", "factor", "factor_batched", "Batch", "Server",
+           "serve_footprint", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
            "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS"]
 
@@ -32,7 +33,10 @@ STATUS = {
 
 # every function include/rlu.h declares
 EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                    "rlu_factor_batched", "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
+                    "rlu_factor_batched", "rlu_serve_create", "rlu_serve_submit",
+                    "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
+                    "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
+                    "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
                     "rlu_status_string", "rlu_version"]
 
 
@@ -59,6 +63,20 @@ class Buffers(ctypes.Structure):
                 ("ipiv", ctypes.c_void_p), ("qpiv", ctypes.c_void_p)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("max_inflight", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("info", ctypes.c_int32 * 3),
+                ("t_submit_us", ctypes.c_double), ("t_start_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -78,6 +96,18 @@ def lib() -> ctypes.CDLL:
         L.rlu_factor_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                          ctypes.POINTER(Buffers), ctypes.c_void_p]
         L.rlu_check_info.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        L.rlu_serve_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
+        L.rlu_serve_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
+        L.rlu_serve_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result)]
+        L.rlu_serve_copy.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Buffers),
+                                     ctypes.c_void_p]
+        L.rlu_serve_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+        L.rlu_serve_footprint.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
+        L.rlu_serve_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(ctypes.c_int32)]
+        L.rlu_serve_destroy.argtypes = [ctypes.c_void_p]
         L.rlu_status_string.argtypes = [ctypes.c_int]
         L.rlu_status_string.restype = ctypes.c_char_p
         L.rlu_version.restype = ctypes.c_char_p
@@ -88,7 +118,9 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_int)]
         for name in ("rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
                      "rlu_factor_batched", "rlu_check_info", "rlu_set_timing",
-                     "rlu_phase_times"):
+                     "rlu_phase_times", "rlu_serve_create", "rlu_serve_submit",
+                     "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
+                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -294,6 +326,115 @@ def factor_batched(problems, *, precision: int | None = None, handle: Handle | N
     batched call.  Returns a list of Factors (device tensors, not
     synchronized)."""
     return Batch(problems, precision=precision, outs=outs).run(handle, stream)
+
+
+def serve_footprint(m, n, k, l, dtype=F64, precision=PREC_FP64) -> int:
+    """HBM bytes the server charges for a request of this shape."""
+    pb = Problem(m, n, k, l, dtype, precision, 0, None, 0, 0)
+    out = ctypes.c_size_t()
+    _check(lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)), "rlu_serve_footprint")
+    return out.value
+
+
+class Server:
+    """Continuous-batching request loop of the library (rlu_serve_*).  Keeps a
+    reference to each request's A (and G) until the ticket is released."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, max_inflight: int = 0,
+                 max_queue: int = 0):
+        cfg = ServerConfig(device, budget_bytes, max_inflight, max_queue)
+        self._s = ctypes.c_void_p()
+        _check(lib().rlu_serve_create(ctypes.byref(cfg), ctypes.byref(self._s)),
+               "rlu_serve_create")
+        self.device = device
+        self._keep = {}
+
+    def submit(self, A, k: int, l: int, *, seed: int = 0, precision: int | None = None,
+               G=None) -> int:
+        """Queue A (column-major device tensor); returns the ticket.  Raises
+        RluError on rejection (e.g. RLU_ERR_TOO_LARGE, RLU_ERR_QUEUE_FULL)."""
+        import torch
+
+        if A.dim() != 2 or not A.is_cuda or A.stride(0) != 1:
+            raise ValueError("A must be a column-major 2-D device tensor")
+        m, n = A.shape
+        lda = max(A.stride(1), m) if n > 1 else m
+        if A.dtype == torch.float64:
+            dtype, prec = F64, (PREC_FP64 if precision is None else precision)
+        elif A.dtype == torch.float32:
+            dtype, prec = F32, (PREC_FP32 if precision is None else precision)
+        else:
+            raise ValueError("A must be float64 or float32")
+        pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, 0)
+        if G is not None:
+            pb.G = G.data_ptr()
+            pb.ldg = max(G.stride(1), n) if l > 1 else n
+        t = ctypes.c_uint64()
+        _check(lib().rlu_serve_submit(self._s, ctypes.byref(pb), ctypes.c_void_p(A.data_ptr()),
+                                      lda, ctypes.byref(t)), "rlu_serve_submit")
+        self._keep[t.value] = (A, G, m, n, k, A.dtype)
+        return t.value
+
+    def poll(self, ticket: int):
+        r = Result()
+        st = lib().rlu_serve_poll(self._s, ticket, ctypes.byref(r))
+        return st, r
+
+    def wait(self, ticket: int, timeout: float = 120.0) -> int:
+        import time
+        t0 = time.perf_counter()
+        while True:
+            st, _ = self.poll(ticket)
+            if st != 1:  # RLU_PENDING
+                return st
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} still pending after {timeout} s")
+            time.sleep(50e-6)
+
+    def result(self, ticket: int, stream=None) -> Factors:
+        """Copy a finished request's factors into new device tensors."""
+        import torch
+
+        A, G, m, n, k, dt = self._keep[ticket]
+        dev = A.device
+        L = torch.empty((k, m), dtype=dt, device=dev).t()
+        U = torch.empty((n, k), dtype=dt, device=dev).t()
+        p = torch.empty(m, dtype=torch.int64, device=dev)
+        q = torch.empty(n, dtype=torch.int64, device=dev)
+        info = torch.empty(3, dtype=torch.int32, device=dev)
+        io = Buffers(None, 0, L.data_ptr(), m, U.data_ptr(), k, p.data_ptr(), q.data_ptr(),
+                     info.data_ptr(), None, 0, None, 0, None, None)
+        s = stream if stream is not None else torch.cuda.current_stream(dev)
+        _check(lib().rlu_serve_copy(self._s, ticket, ctypes.byref(io),
+                                    ctypes.c_void_p(s.cuda_stream)), "rlu_serve_copy")
+        s.synchronize()
+        return Factors(L, U, p, q, info)
+
+    def release(self, ticket: int) -> int:
+        st = lib().rlu_serve_release(self._s, ticket)
+        if st == 0:
+            self._keep.pop(ticket, None)
+        return st
+
+    def stats(self):
+        used = ctypes.c_size_t()
+        qd = ctypes.c_int32()
+        fl = ctypes.c_int32()
+        _check(lib().rlu_serve_stats(self._s, ctypes.byref(used), ctypes.byref(qd),
+                                     ctypes.byref(fl)), "rlu_serve_stats")
+        return used.value, qd.value, fl.value
+
+    def close(self):
+        if self._s:
+            lib().rlu_serve_destroy(self._s)
+            self._s = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def check_info(info) -> int:

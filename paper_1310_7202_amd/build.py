@@ -29,7 +29,7 @@ HIP_FLAGS = [
 ]
 
 SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
-           "rlu_api.cpp", "rlu_batch.cpp"]
+           "rlu_api.cpp", "rlu_batch.cpp", "rlu_serve.cpp"]
 
 
 def _hipcc() -> str:

@@ -352,7 +352,8 @@ rlu_status_t rlu_create(rlu_handle_t* out, int device) {
       hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess) {
     hipSetDevice(prev);
     delete h;
     return RLU_ERR_DEVICE;
@@ -381,6 +382,7 @@ rlu_status_t rlu_destroy(rlu_handle_t h) {
   if (h->bws) hipFree(h->bws);
   if (h->stage) hipHostFree(h->stage);
   if (h->ev_stage) hipEventDestroy(h->ev_stage);
+  if (h->ev_panel) hipEventDestroy(h->ev_panel);
   if (h->cap) hipStreamDestroy(h->cap);
   hipSetDevice(prev);
   delete h;

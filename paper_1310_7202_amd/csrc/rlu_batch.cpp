@@ -233,8 +233,13 @@ rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableW
   const int R = panel_rows_for(maxcols);
   if (R == 0) return RLU_ERR_UNSUPPORTED;
   const size_t lds = panel_lds_bytes(R, maxcols);
-  int slots = panel_batched_slots(R, lds, cus);
+  // Sizing pass (no base): no device query; at least one workgroup per CU
+  // is resident and at most four (512-thread workgroups), which bounds the
+  // schedule's size from above.
+  const bool sizing = base == nullptr;
+  int slots = sizing ? cus : panel_batched_slots(R, lds, cus);
   if (slots <= 0) return RLU_ERR_DEVICE;
+  if (slots > 4 * cus) slots = 4 * cus;
   std::vector<PanelTaskDev> tasks;
   std::vector<int> nwg, ncols;
   for (const Item& it : P.items) {
@@ -264,8 +269,14 @@ rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableW
     ncols.push_back(t.ncols);
   }
   std::vector<int> sched;
-  L.rounds = schedule_gangs(nwg, ncols, slots, sched);
-  L.nslots = slots;
+  if (sizing) {
+    L.rounds = (int)tasks.size();
+    L.nslots = 4 * cus;
+    sched.assign((size_t)L.rounds * L.nslots, -1);
+  } else {
+    L.rounds = schedule_gangs(nwg, ncols, slots, sched);
+    L.nslots = slots;
+  }
   L.maxR = R;
   L.lds = lds;
   L.tasks = tw.put(tasks);
@@ -501,9 +512,23 @@ rlu_status_t enqueue_gemms(const std::vector<GemmLaunch>& ls, char* tab, OpA opa
 }
 
 // The launch sequence of a batch on stream s.
+// Panel launches keep every workgroup of the device busy; two of them must
+// never run at once (their gangs could hold each other's workgroups), so an
+// optional gate event orders each panel launch after the previous one.
+hipError_t gated_panel(const PanelLaunch& L, char* tab, hipEvent_t gate, hipStream_t s) {
+  if (gate) {
+    hipError_t e = hipStreamWaitEvent(s, gate, 0);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_panel_lu_batched((const PanelTaskDev*)(tab + L.tasks),
+                                         (const int*)(tab + L.sched), L.rounds, L.nslots, L.maxR,
+                                         L.lds, kTimeoutTicks, s);
+  if (e == hipSuccess && gate) e = hipEventRecord(gate, s);
+  return e;
+}
+
 template <typename T>
-rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, hipStream_t s) {
-  char* base = (char*)h->bws;
+rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate, hipStream_t s) {
   char* tab = base + P.tab_off;
   const int count = (int)P.items.size();
   HIP_TRY(launch_fill_u32((uint32_t*)base, P.zero_bytes / 4, 0u, s));
@@ -519,9 +544,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, hipStream_t s) {
   }
   {
     PhaseScope ph(h, PH_PANEL_Y, s);
-    HIP_TRY(launch_panel_lu_batched((const PanelTaskDev*)(tab + P.py.tasks),
-                                    (const int*)(tab + P.py.sched), P.py.rounds, P.py.nslots,
-                                    P.py.maxR, P.py.lds, kTimeoutTicks, s));
+    HIP_TRY(gated_panel(P.py, tab, gate, s));
   }
   {
     PhaseScope ph(h, PH_GRAM, s);
@@ -547,9 +570,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, hipStream_t s) {
   }
   {
     PhaseScope ph(h, PH_PANEL_B, s);
-    HIP_TRY(launch_panel_lu_batched((const PanelTaskDev*)(tab + P.pbt.tasks),
-                                    (const int*)(tab + P.pbt.sched), P.pbt.rounds, P.pbt.nslots,
-                                    P.pbt.maxR, P.pbt.lds, kTimeoutTicks, s));
+    HIP_TRY(gated_panel(P.pbt, tab, gate, s));
   }
   {
     PhaseScope ph(h, PH_ASSEMBLE, s);
@@ -582,7 +603,7 @@ rlu_status_t ensure_bws(rlu_handle_s* h, size_t bytes) {
   return RLU_OK;
 }
 
-rlu_status_t upload_tables(rlu_handle_s* h, const Plan& P, hipStream_t s) {
+rlu_status_t upload_tables(rlu_handle_s* h, const Plan& P, char* base, hipStream_t s) {
   const size_t bytes = P.tab.size();
   if (bytes == 0) return RLU_OK;
   HIP_TRY(hipEventSynchronize(h->ev_stage));  // the previous upload has left the stage
@@ -597,7 +618,7 @@ rlu_status_t upload_tables(rlu_handle_s* h, const Plan& P, hipStream_t s) {
     h->stage_bytes = bytes;
   }
   std::memcpy(h->stage, P.tab.data(), bytes);
-  HIP_TRY(hipMemcpyAsync((char*)h->bws + P.tab_off, h->stage, bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + P.tab_off, h->stage, bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(h->ev_stage, s));
   return RLU_OK;
 }
@@ -613,7 +634,7 @@ void drop_graph(rlu_handle_s* h) {
 template <typename T>
 rlu_status_t capture(rlu_handle_s* h, const Plan& P) {
   HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-  rlu_status_t st = enqueue<T>(h, P, h->cap);
+  rlu_status_t st = enqueue<T>(h, P, (char*)h->bws, nullptr, h->cap);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap, &g);
   if (st != RLU_OK || e != hipSuccess || !g) {
@@ -650,14 +671,9 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
                                            rlu_stream_t stream) {
   if (!h || count < 0 || (count > 0 && (!pbs || !ios))) return RLU_ERR_INVALID_ARG;
   if (count == 0) return RLU_OK;
-  for (int i = 0; i < count; ++i) {
-    rlu_status_t st = validate(&pbs[i]);
+  {
+    rlu_status_t st = batched_validate(count, pbs, ios);
     if (st != RLU_OK) return st;
-    st = validate_io(&pbs[i], &ios[i]);
-    if (st != RLU_OK) return st;
-    if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
-    if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
-      return RLU_ERR_INVALID_ARG;
   }
   DeviceScope dev(h->device);
   if (!dev.ok) return RLU_ERR_DEVICE;
@@ -681,7 +697,8 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
     drop_graph(h);
     st = build_tables(P, (char*)h->bws, h->cus);
     if (st != RLU_OK) return st;
-    st = upload_tables(h, P, s);
+    if (P.total > h->bws_bytes) return RLU_ERR_DEVICE;  // the sizing pass bounds it
+    st = upload_tables(h, P, (char*)h->bws, s);
     if (st != RLU_OK) return st;
     st = f32 ? capture<float>(h, P) : capture<double>(h, P);
     if (st != RLU_OK) return st;
@@ -693,9 +710,81 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
   drop_graph(h);
   st = build_tables(P, (char*)h->bws, h->cus);
   if (st != RLU_OK) return st;
-  st = upload_tables(h, P, s);
+  if (P.total > h->bws_bytes) return RLU_ERR_DEVICE;  // the sizing pass bounds it
+  st = upload_tables(h, P, (char*)h->bws, s);
   if (st != RLU_OK) return st;
   st = begin_timing(h);
   if (st != RLU_OK) return st;
-  return f32 ? enqueue<float>(h, P, s) : enqueue<double>(h, P, s);
+  return f32 ? enqueue<float>(h, P, (char*)h->bws, h->ev_panel, s)
+             : enqueue<double>(h, P, (char*)h->bws, h->ev_panel, s);
 }
+
+namespace rlu_detail {
+
+// Validation shared with the server: every problem valid, one dtype and
+// precision, no diagnostics.
+rlu_status_t batched_validate(int count, const rlu_problem_t* pbs, const rlu_buffers_t* ios) {
+  for (int i = 0; i < count; ++i) {
+    rlu_status_t st = validate(&pbs[i]);
+    if (st != RLU_OK) return st;
+    if (ios) {
+      st = validate_io(&pbs[i], &ios[i]);
+      if (st != RLU_OK) return st;
+    }
+    if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
+    if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
+      return RLU_ERR_INVALID_ARG;
+  }
+  return RLU_OK;
+}
+
+// Upper bound of the batch workspace one problem adds (its data, exchange
+// areas and its share of the task tables), independent of the rest of the
+// batch.  Also checks that the problem fits the batched kernels.
+rlu_status_t batched_item_bytes(const rlu_problem_t& pb, int cus, size_t* bytes) {
+  rlu_buffers_t io{};
+  io.lda = pb.m; io.ldl = pb.m; io.ldu = pb.k;
+  Plan P;
+  rlu_status_t st = plan_layout(P, 1, &pb, &io);
+  if (st != RLU_OK) return st;
+  st = build_tables(P, nullptr, cus);
+  if (st != RLU_OK) return st;
+  // in a larger batch the same entries, plus alignment and the XCD padding of
+  // each tile map (< 8 entries per launch); the sizing pass already reserves
+  // a full schedule row of 4 x cus slots per problem and panel
+  const size_t slack = 8 * 8 * 8 + 16 * 64;
+  *bytes = P.total + slack;
+  return RLU_OK;
+}
+
+// Workspace a batch needs (for a caller-provided workspace).
+rlu_status_t batched_ws_bytes(int count, const rlu_problem_t* pbs, const rlu_buffers_t* ios,
+                              int cus, size_t* bytes) {
+  Plan P;
+  rlu_status_t st = plan_layout(P, count, pbs, ios);
+  if (st != RLU_OK) return st;
+  st = build_tables(P, nullptr, cus);
+  if (st != RLU_OK) return st;
+  *bytes = P.total;
+  return RLU_OK;
+}
+
+// Enqueue a batch on stream s in the caller's workspace (no graph), panel
+// launches ordered by `gate`.
+rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t* pbs,
+                                const rlu_buffers_t* ios, hipStream_t s, void* ws,
+                                size_t ws_bytes, hipEvent_t gate) {
+  Plan P;
+  rlu_status_t st = plan_layout(P, count, pbs, ios);
+  if (st != RLU_OK) return st;
+  st = build_tables(P, (char*)ws, h->cus);
+  if (st != RLU_OK) return st;
+  if (P.total > ws_bytes) return RLU_ERR_INVALID_ARG;
+  st = upload_tables(h, P, (char*)ws, s);
+  if (st != RLU_OK) return st;
+  h->cur = nullptr;
+  return pbs[0].dtype == RLU_F32 ? enqueue<float>(h, P, (char*)ws, gate, s)
+                                 : enqueue<double>(h, P, (char*)ws, gate, s);
+}
+
+}  // namespace rlu_detail

@@ -51,6 +51,7 @@ struct rlu_handle_s {
   size_t stage_bytes = 0;
   hipEvent_t ev_stage = nullptr; // last upload from `stage` done
   hipStream_t cap = nullptr;     // capture stream
+  hipEvent_t ev_panel = nullptr; // last batched panel launch (eager calls)
   BatchGraph bgraph;
 };
 
@@ -76,6 +77,15 @@ P* at(void* base, size_t off) { return (P*)((char*)base + off); }
 rlu_status_t validate(const rlu_problem_t* pb);
 rlu_status_t validate_io(const rlu_problem_t* pb, const rlu_buffers_t* io);
 rlu_status_t begin_timing(rlu_handle_s* h);
+
+// Batched path (rlu_batch.cpp), also used by the server.
+rlu_status_t batched_validate(int count, const rlu_problem_t* pbs, const rlu_buffers_t* ios);
+rlu_status_t batched_item_bytes(const rlu_problem_t& pb, int cus, size_t* bytes);
+rlu_status_t batched_ws_bytes(int count, const rlu_problem_t* pbs, const rlu_buffers_t* ios,
+                              int cus, size_t* bytes);
+rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t* pbs,
+                                const rlu_buffers_t* ios, hipStream_t s, void* ws,
+                                size_t ws_bytes, hipEvent_t gate);
 
 // Event pair around a phase when timing is on (recorded on the phase's stream).
 struct PhaseScope {

@@ -95,3 +95,54 @@ def test_create_rejects_bad_device(rlu):
     h = ctypes.c_void_p()
     assert rlu.lib().rlu_create(ctypes.byref(h), -1) < 0
     assert rlu.lib().rlu_create(None, 0) == -1
+
+
+def test_serve_footprint_counts_workspace_and_outputs(rlu):
+    small = rlu.serve_footprint(512, 512, 10, 15)
+    big = rlu.serve_footprint(4096, 3000, 64, 72)
+    assert 0 < small < big
+    # at least the outputs (L, U, p, q) and the sketch Y, B, C it must hold
+    m, n, k, l = 4096, 3000, 64, 72
+    assert big >= 8 * (m * k + k * n) + 8 * (m + n) + 8 * (m * l + 2 * k * n)
+    # FP32 storage charges less than FP64 for the same shape
+    assert rlu.serve_footprint(m, n, k, l, rlu.F32, rlu.PREC_FP32) < big
+
+
+def test_serve_footprint_rejects_bad_problems(rlu):
+    lib = rlu.lib()
+    out = ctypes.c_size_t()
+    bad = rlu.Problem(10, 10, 3, 2, 0, 0, 0, None, 0, 0)
+    assert lib.rlu_serve_footprint(ctypes.byref(bad), ctypes.byref(out)) == -1
+    diag = rlu.Problem(100, 100, 5, 8, 0, 0, 0, None, 0, rlu.FLAG_DIAGNOSTICS)
+    assert lib.rlu_serve_footprint(ctypes.byref(diag), ctypes.byref(out)) == -1
+    assert lib.rlu_serve_footprint(None, ctypes.byref(out)) == -1
+
+
+def test_serve_entry_points_reject_null_server(rlu):
+    lib = rlu.lib()
+    pb = rlu.Problem(100, 100, 5, 8, 0, 0, 0, None, 0, 0)
+    t = ctypes.c_uint64()
+    assert lib.rlu_serve_submit(None, ctypes.byref(pb), ctypes.c_void_p(1), 100,
+                                ctypes.byref(t)) == -1
+    assert lib.rlu_serve_poll(None, 1, None) == -1
+    assert lib.rlu_serve_release(None, 1) == -1
+    assert lib.rlu_serve_copy(None, 1, None, None) == -1
+    assert lib.rlu_serve_stats(None, None, None, None) == -1
+    assert lib.rlu_serve_destroy(None) == -1
+    assert lib.rlu_serve_create(None, None) == -1
+
+
+def test_batched_rejects_bad_arguments_before_any_device_work(rlu):
+    lib = rlu.lib()
+    assert lib.rlu_factor_batched(ctypes.c_void_p(1), 0, None, None, None) == 0
+    assert lib.rlu_factor_batched(None, 1, None, None, None) == -1
+    assert lib.rlu_factor_batched(ctypes.c_void_p(1), 2, None, None, None) == -1
+    pbs = (rlu.Problem * 2)(rlu.Problem(100, 100, 5, 8, 0, 0, 0, None, 0, 0),
+                            rlu.Problem(100, 100, 5, 8, 1, 1, 0, None, 0, 0))
+    ios = (rlu.Buffers * 2)()
+    for i in range(2):
+        ios[i].A = ios[i].L = ios[i].U = ios[i].p = ios[i].q = ios[i].info = 1
+        ios[i].lda = ios[i].ldl = 100
+        ios[i].ldu = 5
+    # mixed dtypes in one call
+    assert lib.rlu_factor_batched(ctypes.c_void_p(1), 2, pbs, ios, None) == -1
