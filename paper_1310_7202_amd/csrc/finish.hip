@@ -153,6 +153,24 @@ __global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev*
   }
 }
 
+// dst (cols x rows) = src (rows x cols)^T through 32 x 32 LDS tiles.
+__global__ void __launch_bounds__(256) transpose_kernel(const double* __restrict__ src,
+                                                        int64_t lds, double* __restrict__ dst,
+                                                        int64_t ldd, int64_t rows, int64_t cols) {
+  __shared__ double t[32][33];
+  const int64_t r0 = 32 * (int64_t)blockIdx.x, c0 = 32 * (int64_t)blockIdx.y;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + tx, c = c0 + y;
+    t[y][tx] = (r < rows && c < cols) ? src[r + c * lds] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t c = c0 + tx, r = r0 + y;  // dst(c, r) = src(r, c)
+    if (r < rows && c < cols) dst[c + r * ldd] = t[tx][y];
+  }
+}
+
 inline unsigned grid_for(int64_t n, int64_t cap = 8192) {
   int64_t b = (n + 255) / 256;
   if (b < 1) b = 1;
@@ -251,5 +269,13 @@ hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t m
 }
 template hipError_t launch_assemble_batched<double>(const AsmTaskDev*, int, int64_t, hipStream_t);
 template hipError_t launch_assemble_batched<float>(const AsmTaskDev*, int, int64_t, hipStream_t);
+
+hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd,
+                            int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)((rows + 31) / 32), (unsigned)((cols + 31) / 32)),
+                     dim3(256), 0, s, src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
 
 }  // namespace rlu

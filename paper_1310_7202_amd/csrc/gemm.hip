@@ -51,7 +51,7 @@ __device__ __forceinline__ void gemm_tile(
     const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
     const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
     const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int bx, int by,
-    int bz) {
+    int bz, int acol0 = 0, int csub = 0) {
   constexpr bool AK = (OA == OpA::LvT);  // A operand contiguous along K
   constexpr bool BKC = true;             // B operands are contiguous along K
   typedef Tile<BM, BN, BK, WM, WN, AK, BKC, NBUF> Tl;
@@ -84,8 +84,10 @@ __device__ __forceinline__ void gemm_tile(
           v = (TC)A[gi + gk * lda];
         } else if (OA == OpA::LvT) {
           v = (TC)lv_value<TA>(A[gk + gi * lda], (int)gi, astep[gk]);
-        } else {
+        } else if (OA == OpA::Lv) {
           v = (TC)lv_value<TA>(A[gi + gk * lda], (int)gk, astep[gi]);
+        } else {  // LvStrict: multipliers only, columns numbered from acol0
+          v = (int)(acol0 + gk) < astep[gi] ? (TC)A[gi + gk * lda] : TC(0);
         }
       }
       ra[q] = v;
@@ -180,7 +182,8 @@ __device__ __forceinline__ void gemm_tile(
             partial[(int64_t)bz * M * N + gi + gj * M] = val;
           } else {
             const int64_t oi = rowmap ? (int64_t)rowmap[gi] : gi;
-            C[oi + gj * ldc] = val;
+            if (csub) C[oi + gj * ldc] -= val;
+            else C[oi + gj * ldc] = val;
           }
         }
       }
@@ -206,7 +209,7 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
             const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
             const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
             const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int tm, int tn,
-            int nfast) {
+            int nfast, int acol0, int csub) {
   const int t = xcd_chunked((int)blockIdx.x, (int)gridDim.x);
   int bx, by, bz;
   if (nfast) {
@@ -215,7 +218,8 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
     bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
   }
   gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
-      M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, bx, by, bz);
+      M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, bx, by, bz, acol0,
+      csub);
 }
 
 // Many independent products in one launch: workgroup b computes the tile
@@ -326,7 +330,7 @@ hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>),
                      dim3((unsigned)nb), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A,
                      d.lda, d.astep, (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap,
-                     ksplit, (TO*)d.partial, tm, tn, nfast);
+                     ksplit, (TO*)d.partial, tm, tn, nfast, d.acol0, d.csub ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -335,7 +339,7 @@ hipError_t launch_ops(const GemmDesc& d, hipStream_t s) {
   GemmShape sh = choose_shape(d.M, d.N, d.K, OA == OpA::LvT);
   const int c = sh.cfg;
   // ksplit 0 = automatic (needs the partial workspace); 1 = no split
-  const int ks = d.ksplit == 0 ? (d.partial ? sh.ksplit : 1) : d.ksplit;
+  const int ks = d.csub ? 1 : (d.ksplit == 0 ? (d.partial ? sh.ksplit : 1) : d.ksplit);
   if (d.ksplit_out) *d.ksplit_out = ks;
   hipError_t e;
   switch (c) {
@@ -369,6 +373,8 @@ hipError_t dispatch(const GemmDesc& d, hipStream_t s) {
     return launch_ops<TA, TB, TC, TO, OpA::LvT, OpB::Lv>(d, s);
   if (d.opa == OpA::Lv && d.opb == OpB::Plain)
     return launch_ops<TA, TB, TC, TO, OpA::Lv, OpB::Plain>(d, s);
+  if (d.opa == OpA::LvStrict && d.opb == OpB::Plain)
+    return launch_ops<TA, TB, TC, TO, OpA::LvStrict, OpB::Plain>(d, s);
   return hipErrorInvalidValue;
 }
 

@@ -150,7 +150,8 @@ __device__ __forceinline__ void panel_body(
     int* __restrict__ pos_out, int* __restrict__ rstep_out, int* __restrict__ piv_row_out,
     int* __restrict__ ipiv_out, int* __restrict__ info_out, int* __restrict__ fail,
     char* __restrict__ xch, int64_t rec_stride, long long timeout_ticks, int w, double* smem,
-    long long t_start) {
+    long long t_start, int step0, int total_cols, const int* __restrict__ pos_in,
+    const int* __restrict__ rstep_in) {
   double* Ts = smem;                        // R x ncols, column-major (ld R)
   double* urow = Ts + (int64_t)R * ncols;   // 2 x ncols: U rows by step parity
   double* lbody = urow + 2 * ncols;         // 2 x ncols: single-workgroup "records"
@@ -179,7 +180,16 @@ __device__ __forceinline__ void panel_body(
       Ts[(int64_t)c * R + r] = r < nr ? X[(int64_t)(row0 + r) * rs + (int64_t)c * cs] : 0.0;
     }
   }
-  for (int r = tid; r < R; r += kThreads) step_s[r] = kNone;
+  // rows chosen by an earlier block of columns (global step < step0) stay
+  // inactive: they hold U rows
+  for (int r = tid; r < R; r += kThreads) {
+    int st = kNone;
+    if (rstep_in && r < nr) {
+      const int s0 = rstep_in[row0 + r];
+      if (s0 < step0) st = s0;
+    }
+    step_s[r] = st;
+  }
   if (tid == 0) {
     sh_stop = 0;
     for (int t = 0; t < 2; ++t) { sh_bw[t] = -1; sh_piv[t] = 0.0; sh_lm[t] = 0.0; sh_v1[t] = 0.0; }
@@ -191,8 +201,15 @@ __device__ __forceinline__ void panel_body(
 #pragma unroll
   for (int q = 0; q < RPL; ++q) {
     const int r = lane + 64 * q;
-    pos_q[q] = row0 + r;
-    st_q[q] = r < nr ? kNone : -1;  // -1: no such row
+    pos_q[q] = (pos_in && r < nr) ? pos_in[row0 + r] : row0 + r;
+    st_q[q] = -1;  // -1: no such row
+    if (r < nr) {
+      st_q[q] = kNone;
+      if (rstep_in) {
+        const int s0 = rstep_in[row0 + r];
+        if (s0 < step0) st_q[q] = s0;
+      }
+    }
     val_q[q] = 0.0;
     mlt_q[q] = 0.0;
   }
@@ -386,12 +403,12 @@ __device__ __forceinline__ void panel_body(
           const int r = lane + 64 * q;
           if (st_q[q] == -1) continue;
           if (r == wr) {
-            pos_q[q] = j;
-            st_q[q] = j;
-            step_s[r] = j;
+            pos_q[q] = step0 + j;
+            st_q[q] = step0 + j;
+            step_s[r] = step0 + j;
             mlt_q[q] = 0.0;
           } else {
-            if (pos_q[q] == j) pos_q[q] = win_pos;  // row at position j moves away
+            if (pos_q[q] == step0 + j) pos_q[q] = win_pos;  // row at position j moves away
             double m = 0.0;
             if (st_q[q] == kNone && piv != 0.0) {
               // multiply by the reciprocal pivot unless it would overflow
@@ -410,7 +427,7 @@ __device__ __forceinline__ void panel_body(
           pivrow_s[j] = win_row;
           ipiv_s[j] = win_pos;
         }
-        if (piv == 0.0 && info == 0) info = j + 1;
+        if (piv == 0.0 && info == 0) info = step0 + j + 1;
       }
     } else if (upd1) {
       // ---- (2b) waves 1-7: rank-one update of step j-1 on columns j+1.. --------
@@ -422,7 +439,7 @@ __device__ __forceinline__ void panel_body(
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         const int r = lane + 64 * q;
-        act[q] = r < nr && step_s[r] > j - 1;
+        act[q] = r < nr && step_s[r] > step0 + j - 1;
         m[q] = act[q] ? Ts[(int64_t)(j - 1) * R + r] : 0.0;
       }
       constexpr int kBulkWaves = kThreads / 64 - 1;
@@ -466,7 +483,9 @@ __device__ __forceinline__ void panel_body(
         step_s[r] = st_q[q];
       }
     }
-    if (lane == 0 && w == 0) *info_out = info;
+    // the first zero pivot of the whole factorization: keep an earlier
+    // block's report (the word starts at zero)
+    if (lane == 0 && w == 0 && info != 0 && *info_out == 0) *info_out = info;
   }
   __syncthreads();
   if (rs == 1) {
@@ -482,7 +501,7 @@ __device__ __forceinline__ void panel_body(
   }
   for (int r = tid; r < nr; r += kThreads) {
     pos_out[row0 + r] = pos_s[r];
-    rstep_out[row0 + r] = step_s[r] == kNone ? ncols : step_s[r];
+    rstep_out[row0 + r] = step_s[r] == kNone ? total_cols : step_s[r];
   }
   if (w == 0)
     for (int c = tid; c < ncols; c += kThreads) {
@@ -497,11 +516,12 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
                 int nwg, int* __restrict__ pos_out, int* __restrict__ rstep_out,
                 int* __restrict__ piv_row_out, int* __restrict__ ipiv_out,
                 int* __restrict__ info_out, int* __restrict__ fail, char* __restrict__ xch,
-                int64_t rec_stride, long long timeout_ticks) {
+                int64_t rec_stride, long long timeout_ticks, int step0, int total_cols,
+                const int* __restrict__ pos_in, const int* __restrict__ rstep_in) {
   extern __shared__ double smem[];
   panel_body<RPL>(X, rs, cs, nrows, ncols, R, nwg, pos_out, rstep_out, piv_row_out, ipiv_out,
                   info_out, fail, xch, rec_stride, timeout_ticks, (int)blockIdx.x, smem,
-                  now_ticks());
+                  now_ticks(), step0, total_cols, pos_in, rstep_in);
 }
 
 // Many panels in one persistent launch.  Workgroup b runs, round by round,
@@ -520,7 +540,8 @@ panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __res
     if (e < 0) continue;
     const PanelTaskDev t = tasks[e >> 8];
     panel_body<RPL>(t.X, t.rs, t.cs, t.nrows, t.ncols, t.R, t.nwg, t.pos, t.rstep, t.piv_row,
-                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem, t0);
+                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem, t0,
+                    0, t.ncols, nullptr, nullptr);
     __syncthreads();
   }
 }
@@ -577,8 +598,11 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
   int* info = d.info; int* fail = d.fail; char* xch = (char*)d.xch;
   long long tmo = d.timeout_ticks;
   int64_t rec_stride = rec_stride_for(d.ncols);
+  int step0 = d.step0, total = d.total_cols > 0 ? d.total_cols : d.ncols;
+  const int* pos_in = d.pos_in;
+  const int* rstep_in = d.rstep_in;
   void* args[] = {&X, &rs, &cs, &nrows, &ncols, &R, &nwg, &pos, &rstep, &piv_row, &ipiv,
-                  &info, &fail, &xch, &rec_stride, &tmo};
+                  &info, &fail, &xch, &rec_stride, &tmo, &step0, &total, &pos_in, &rstep_in};
   const void* fn = R <= 64 ? (const void*)panel_lu_kernel<1>
                  : R <= 128 ? (const void*)panel_lu_kernel<2>
                  : R <= 256 ? (const void*)panel_lu_kernel<4>
@@ -628,5 +652,75 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
   void* args[] = {&tasks, &sched, &rounds, &nslots, &timeout_ticks};
   return hipLaunchKernel(fn, dim3(nslots), dim3(kThreads), args, lds_bytes, s);
 }
+
+// ---------------------------------------------------------------------------
+// Between two column blocks of a blocked factorization (rows never move):
+// the U rows of the block's pivots for the columns to its right,
+//   L11 U12 = X(pr, c1:),   L11(j, i) = X(pr_j, c0 + i) for i < j (unit lower),
+// with pr_j = piv_row[j] the row chosen at step c0 + j.  Workgroup b solves
+// 64 right-hand-side columns with U12 in LDS, 16 rows at a time: the
+// product with the rows already solved by all 256 threads, then the 16 x 16
+// triangle by one wave.  Output U (w x nrhs, leading dimension w).
+// ---------------------------------------------------------------------------
+constexpr int kTrsmMaxW = 288;
+
+__global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restrict__ X, int64_t ldx,
+                                                         const int* __restrict__ piv_row, int c0,
+                                                         int w, int64_t c1, int nrhs,
+                                                         double* __restrict__ U) {
+  extern __shared__ double Us[];  // w x 64, row-major
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cc0 = 64 * blockIdx.x;
+  const int jj = tid >> 4, cg = tid & 15;
+  for (int J0 = 0; J0 < w; J0 += 16) {
+    const int h = min(16, w - J0);
+    if (jj < h) {
+      const int64_t prow = piv_row[J0 + jj];
+      double acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = cc0 + cg + 16 * q;
+        acc[q] = c < nrhs ? X[prow + (c1 + c) * ldx] : 0.0;
+      }
+      for (int i = 0; i < J0; ++i) {
+        const double l = X[prow + (int64_t)(c0 + i) * ldx];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __fma_rn(-l, Us[i * 64 + cg + 16 * q], acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) Us[(J0 + jj) * 64 + cg + 16 * q] = acc[q];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int r = 1; r < h; ++r) {
+        const int64_t prow = piv_row[J0 + r];
+        double u = Us[(J0 + r) * 64 + lane];
+        for (int i = 0; i < r; ++i)
+          u = __fma_rn(-X[prow + (int64_t)(c0 + J0 + i) * ldx], Us[(J0 + i) * 64 + lane], u);
+        Us[(J0 + r) * 64 + lane] = u;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < w * 64; e += 256) {
+    const int j = e / 64, c = e % 64;
+    if (cc0 + c < nrhs) U[j + (int64_t)(cc0 + c) * w] = Us[j * 64 + c];
+  }
+}
+
+hipError_t launch_block_trsm(const double* X, int64_t ldx, const int* piv_row, int c0, int w,
+                             int64_t c1, int nrhs, double* U, hipStream_t s) {
+  if (w <= 0 || nrhs <= 0) return hipSuccess;
+  if (w > kTrsmMaxW) return hipErrorInvalidValue;
+  const size_t lds = (size_t)w * 64 * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)block_trsm_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(block_trsm_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), lds, s, X,
+                     ldx, piv_row, c0, w, c1, nrhs, U);
+  return hipGetLastError();
+}
+
+int panel_block_max_width() { return kTrsmMaxW; }
 
 }  // namespace rlu

@@ -6,8 +6,8 @@
 //   Step 2  gemm                Y = A G
 //   Step 3  panel_lu(Y)         packed LU of Y in place, rows never moved
 //   Step 5  gemm (split-K)      S = Lv^T Lv        (Gram matrix)
-//           spd_inverse         S <- S^{-1}        on a second stream, while
-//           gemm                C = Lv^T A         runs on the caller's stream
+//           spd_inverse         S <- S^{-1}        (k <= 64: on a second stream,
+//           gemm                C = Lv^T A          while this product runs)
 //           gemm                B = S^{-1} C
 //   Step 6  panel_lu(B^T)       packed LU of B^T in the storage of B
 //   Step 8  build_u             U = U_b  (k x n, positions)
@@ -35,12 +35,47 @@ namespace rlu_detail {
 
 using namespace rlu;
 
+// A pivoted LU of a tall panel, in one launch when its rows fit the
+// workgroups the device holds at once, else in column blocks: each block is
+// one launch that continues from the positions the earlier blocks left,
+// followed by the block's U rows for the columns to its right (triangular
+// solve) and the update of those columns (GEMM with the block's
+// multipliers).  Rows never move.
+struct BlockedPanel {
+  int nblocks = 0, width = 0;   // every block but the last is `width` wide
+  PanelPlan main{}, last{};
+  size_t u12_elems = 0;
+  bool ok = false;
+};
+
+BlockedPanel plan_blocked(int nrows, int ncols, int cus) {
+  BlockedPanel b;
+  PanelPlan p = panel_plan(nrows, ncols, cus, 1);
+  if (p.ok) {
+    b.nblocks = 1; b.width = ncols; b.main = p; b.last = p; b.ok = true;
+    return b;
+  }
+  const int wmax = panel_block_max_width();
+  for (int nb = 2; nb <= 64; ++nb) {
+    const int w = (ncols + nb - 1) / nb;
+    const int wl = ncols - (nb - 1) * w;
+    if (w > wmax || wl <= 0) continue;
+    PanelPlan pm = panel_plan(nrows, w, cus, 1), pl = panel_plan(nrows, wl, cus, 1);
+    if (!pm.ok || !pl.ok) continue;
+    b.nblocks = nb; b.width = w; b.main = pm; b.last = pl; b.ok = true;
+    b.u12_elems = (size_t)w * (size_t)(ncols - w);
+    return b;
+  }
+  return b;
+}
+
 struct Layout {
-  size_t G = 0, Y = 0, part = 0, S = 0, C = 0, Bst = 0, Lb = 0;
+  size_t G = 0, Y = 0, part = 0, S = 0, gj = 0, C = 0, Bst = 0, Lb = 0;
   size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
   size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0, flags = 0, xch = 0;
   size_t total = 0;
-  PanelPlan py{}, pb{};
+  size_t u12 = 0, bt = 0;
+  BlockedPanel py{}, pb{};
 };
 
 bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
@@ -66,6 +101,7 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   }
   take(L.part, part * d);
   take(L.S, (size_t)k * k * d);
+  take(L.gj, spd_inverse_scratch_elems(k) * d);
   take(L.C, (size_t)k * n * d);
   take(L.Bst, (size_t)k * n * d);
   take(L.Lb, (size_t)k * k * d);
@@ -78,10 +114,13 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   take(L.piv_b, (size_t)k * 4);
   take(L.ipiv_b, (size_t)k * 4);
   take(L.flags, 64);
-  L.py = panel_plan((int)m, (int)l, cus, 1);
-  L.pb = panel_plan((int)n, (int)k, cus, 1);
+  L.py = plan_blocked((int)m, (int)l, cus);
+  L.pb = plan_blocked((int)n, (int)k, cus);
   if (!L.py.ok || !L.pb.ok) return false;
-  take(L.xch, std::max(L.py.xch_bytes, L.pb.xch_bytes));
+  take(L.xch, std::max(std::max(L.py.main.xch_bytes, L.py.last.xch_bytes),
+                       std::max(L.pb.main.xch_bytes, L.pb.last.xch_bytes)));
+  take(L.u12, std::max(L.py.u12_elems, L.pb.u12_elems) * d);
+  take(L.bt, L.pb.nblocks > 1 ? (size_t)n * k * d : 0);
   L.total = off;
   return true;
 }
@@ -162,6 +201,40 @@ namespace {
 using namespace rlu;
 using namespace rlu_detail;
 
+// Pivoted LU of the column-major panel X (nrows x ncols, leading dimension
+// ld), in one launch or in column blocks (BlockedPanel).
+rlu_status_t run_panel(double* X, int64_t ld, int nrows, int ncols, const BlockedPanel& bp,
+                       int* pos, int* rstep, int* piv, int* ipiv, int* info, int* fail,
+                       void* xch, double* u12, hipStream_t s) {
+  for (int b = 0; b < bp.nblocks; ++b) {
+    const int c0 = b * bp.width;
+    const int wb = b == bp.nblocks - 1 ? ncols - c0 : bp.width;
+    PanelDesc d{};
+    d.X = X + (int64_t)c0 * ld; d.rs = 1; d.cs = ld; d.nrows = nrows; d.ncols = wb;
+    d.pos = pos; d.rstep = rstep; d.piv_row = piv + c0; d.ipiv = ipiv + c0;
+    d.info = info; d.fail = fail; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    d.step0 = c0; d.total_cols = ncols;
+    d.pos_in = b ? pos : nullptr;
+    d.rstep_in = b ? rstep : nullptr;
+    HIP_TRY(launch_panel_lu(d, b == bp.nblocks - 1 ? bp.last : bp.main, s));
+    const int c1 = c0 + wb;
+    if (c1 < ncols) {
+      // U rows of this block's pivots for the columns to its right ...
+      HIP_TRY(launch_block_trsm(X, ld, piv + c0, c0, wb, c1, ncols - c1, u12, s));
+      // ... and the update of those columns by the block's multipliers
+      GemmDesc g{};
+      g.M = nrows; g.N = ncols - c1; g.K = wb;
+      g.A = X + (int64_t)c0 * ld; g.lda = ld; g.opa = OpA::LvStrict; g.astep = rstep;
+      g.acol0 = c0;
+      g.B = u12; g.ldb = wb; g.opb = OpB::Plain;
+      g.C = X + (int64_t)c1 * ld; g.ldc = ld;
+      g.ksplit = 1; g.csub = true;
+      HIP_TRY(launch_gemm<double>(g, s));
+    }
+  }
+  return RLU_OK;
+}
+
 // The FP64 path (T = double) and the FP32 path (T = float: FP32 storage of
 // A, G, L, U and FP32 MFMA for the two products with A).  The pivoted LUs,
 // the Gram matrix, its inverse and B are FP64 in both.
@@ -231,12 +304,10 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   }
   // Step 3 (+ Step 4: only the first k columns of the unit-lower factor are used)
   {
-    PanelDesc d{};
-    d.X = Y; d.rs = 1; d.cs = m; d.nrows = (int)m; d.ncols = (int)l;
-    d.pos = pos_y; d.rstep = rstep_y; d.piv_row = piv_y; d.ipiv = ipiv_y;
-    d.info = flags + 0; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
     PhaseScope ph(h, PH_PANEL_Y, s);
-    HIP_TRY(launch_panel_lu(d, Ly.py, s));
+    rlu_status_t st = run_panel(Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
+                                flags + 0, flags + 2, xch, at<double>(ws, Ly.u12), s);
+    if (st != RLU_OK) return st;
   }
   if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
   // Step 5: S = Lv^T Lv, S <- S^{-1} (side stream) while C = Lv^T A
@@ -250,13 +321,20 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     PhaseScope ph(h, PH_GRAM, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
-  HIP_TRY(hipEventRecord(h->ev_fork, s));
-  HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  {
-    PhaseScope ph(h, PH_GRAM_INV, h->side);
-    HIP_TRY(launch_spd_inverse(S, k, h->side));
+  // The one-workgroup inverse (k <= 64) overlaps the projection on the side
+  // stream; the blocked form is a chain of small launches that the
+  // projection would starve of CUs, so it runs first on the caller's stream.
+  const bool overlap = k <= 64;
+  hipStream_t sinv = overlap ? h->side : s;
+  if (overlap) {
+    HIP_TRY(hipEventRecord(h->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
   }
-  HIP_TRY(hipEventRecord(h->ev_join, h->side));
+  {
+    PhaseScope ph(h, PH_GRAM_INV, sinv);
+    HIP_TRY(launch_spd_inverse_scratch(S, k, at<double>(ws, Ly.gj), sinv));
+  }
+  if (overlap) HIP_TRY(hipEventRecord(h->ev_join, h->side));
   {
     GemmDesc d{};
     d.M = k; d.N = n; d.K = m;
@@ -276,7 +354,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
       HIP_TRY(launch_splitk_sum_f64(k, n, ks, (const double*)d.partial, C, k, nullptr, s));
     }
   }
-  HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
+  if (overlap) HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {
     GemmDesc d{};
     d.M = k; d.N = n; d.K = k;
@@ -293,12 +371,22 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   }
   // Step 6 through the LU of B^T
   {
-    PanelDesc d{};
-    d.X = Bst; d.rs = k; d.cs = 1; d.nrows = (int)n; d.ncols = (int)k;
-    d.pos = pos_b; d.rstep = rstep_b; d.piv_row = piv_b; d.ipiv = ipiv_b;
-    d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
     PhaseScope ph(h, PH_PANEL_B, s);
-    HIP_TRY(launch_panel_lu(d, Ly.pb, s));
+    if (Ly.pb.nblocks == 1) {
+      PanelDesc d{};
+      d.X = Bst; d.rs = k; d.cs = 1; d.nrows = (int)n; d.ncols = (int)k;
+      d.pos = pos_b; d.rstep = rstep_b; d.piv_row = piv_b; d.ipiv = ipiv_b;
+      d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+      HIP_TRY(launch_panel_lu(d, Ly.pb.main, s));
+    } else {
+      // blocked: on a column-major copy of B^T, then back into B's storage
+      double* Bt = at<double>(ws, Ly.bt);
+      HIP_TRY(launch_transpose(Bst, k, Bt, n, k, n, s));
+      rlu_status_t st = run_panel(Bt, n, (int)n, (int)k, Ly.pb, pos_b, rstep_b, piv_b, ipiv_b,
+                                  flags + 1, flags + 2, xch, at<double>(ws, Ly.u12), s);
+      if (st != RLU_OK) return st;
+      HIP_TRY(launch_transpose(Bt, n, Bst, k, n, k, s));
+    }
   }
   if (diag && io.qpiv) HIP_TRY(launch_copy_i32(ipiv_b, io.qpiv, k, s));
   {

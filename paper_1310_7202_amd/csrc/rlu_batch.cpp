@@ -36,7 +36,7 @@ using namespace rlu_detail;
 struct Item {
   rlu_problem_t pb;
   rlu_buffers_t io;
-  size_t G = 0, Y = 0, S = 0, part = 0, C = 0, Bst = 0, Lb = 0;
+  size_t G = 0, Y = 0, S = 0, gj = 0, part = 0, C = 0, Bst = 0, Lb = 0;
   size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
   size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0;
   size_t flags = 0, xy = 0, xb = 0;  // cleared before each run
@@ -328,6 +328,7 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     it.gram_ks = gram_split_for(m);
     take(it.part, it.gram_ks > 1 ? (size_t)it.gram_ks * k * k * d : 0);
     take(it.S, (size_t)k * k * d);
+    take(it.gj, spd_inverse_scratch_elems(k) * d);
     take(it.C, (size_t)k * n * d);
     take(it.Bst, (size_t)k * n * d);
     take(it.Lb, (size_t)k * k * d);
@@ -411,7 +412,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
     std::vector<SpdTaskDev> spd;
     P.kmax = 0;
     for (const Item& it : P.items) {
-      spd.push_back(SpdTaskDev{(double*)(base + it.S), (int)it.pb.k});
+      spd.push_back(SpdTaskDev{(double*)(base + it.S), (int)it.pb.k, (double*)(base + it.gj)});
       P.kmax = std::max<int64_t>(P.kmax, it.pb.k);
     }
     P.spd = tw.put(spd);

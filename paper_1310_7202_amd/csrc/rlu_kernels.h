@@ -23,7 +23,9 @@ hipError_t launch_gaussian_batched(const GaussTaskDev* tasks, int count, int64_t
 enum class OpA {
   Plain,      // A(i, kk) = A[i + kk*lda]                      (M contiguous)
   LvT,        // A(i, kk) = Lv(kk, i), Lv stored as Y[kk + i*lda]
-  Lv          // A(i, kk) = Lv(i, kk), Lv stored as Y[i + kk*lda]
+  Lv,         // A(i, kk) = Lv(i, kk), Lv stored as Y[i + kk*lda]
+  LvStrict    // A(i, kk) = Y[i + kk*lda] if acol0 + kk < astep[i], else 0 (the
+              // multipliers of a block of columns starting at acol0)
 };
 enum class OpB {
   Plain,      // B(kk, j) = B[kk + j*ldb]                      (K contiguous)
@@ -40,6 +42,8 @@ struct GemmDesc {
   void* partial;       // partial-sum workspace (gemm_auto_partial_elems elements)
   bool no_sum;         // with a split: leave the partial sums (launch_splitk_sum_f64 adds them)
   int* ksplit_out;     // optional: receives the split used (1 = none)
+  int acol0;           // LvStrict: global index of the first column of A
+  bool csub;           // C -= op(A) op(B) instead of C = ... (requires ksplit 1)
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
@@ -97,10 +101,22 @@ struct PanelDesc {
   int* fail;                 // out: set to 1 if the exchange timed out
   void* xch;                 // exchange area, panel_xch_bytes()
   long long timeout_ticks;   // bound on every wait (100 MHz ticks)
+  // Continuing a factorization whose first step0 columns were factored by
+  // earlier launches (X, piv_row and ipiv then point at column step0):
+  int step0;                 // global index of the first column (0: fresh)
+  int total_cols;            // columns of the whole factorization (0: ncols)
+  const int* pos_in;         // positions after the earlier columns (nullable)
+  const int* rstep_in;       // choosing steps so far (nullable: none chosen)
 };
 struct PanelPlan { int rows_per_wg; int nwg; size_t lds_bytes; size_t xch_bytes; bool ok; };
 PanelPlan panel_plan(int nrows, int ncols, int device_cus, int max_wg_per_cu_hint);
 hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s);
+// Between column blocks of a blocked factorization of a column-major X:
+// U (w x nrhs, ld w) = L11^{-1} X(pr, c1 : c1 + nrhs), L11 the unit-lower
+// multipliers of the block's pivot rows pr = piv_row[0..w) (columns c0..).
+hipError_t launch_block_trsm(const double* X, int64_t ldx, const int* piv_row, int c0, int w,
+                             int64_t c1, int nrhs, double* U, hipStream_t s);
+int panel_block_max_width();
 // One panel of a batched launch, as the device reads it.
 struct PanelTaskDev {
   double* X; int64_t rs, cs;
@@ -120,12 +136,22 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
                                    long long timeout_ticks, hipStream_t s);
 
 // ----- Inverse of the k x k Gram matrix (spd_inverse.hip) ------------------
+// Single workgroup, S in registers (k <= 208).
 hipError_t launch_spd_inverse(double* S, int64_t k, hipStream_t s);  // in place
+constexpr int64_t kSpdMaxK = 1024;
 bool spd_inverse_supported(int64_t k);
-struct SpdTaskDev { double* S; int k; };
-// One workgroup per matrix; the register tiling is chosen by the largest k.
+// scratch of the blocked form: spd_inverse_scratch_elems(k) doubles
+struct SpdTaskDev { double* S; int k; double* scratch; };
+size_t spd_inverse_scratch_elems(int64_t k);
+// Batch (one entry per matrix, tasks in device memory): one workgroup per
+// matrix when every k <= 64, else the blocked form (3 launches per 64 pivots).
 hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_t kmax,
                                      hipStream_t s);
+hipError_t launch_spd_inverse_blocked(const SpdTaskDev* tasks, int count, int64_t kmax,
+                                      hipStream_t s);
+// One matrix: the register kernel for k <= 64, else the blocked form with
+// `scratch` (spd_inverse_scratch_elems(k) doubles).
+hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
 
 // ----- Permutations and factor assembly (finish.hip) ------------------------
 hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
@@ -152,6 +178,9 @@ hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s)
 hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
                              int32_t* info_out, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);
+// dst (cols x rows, ld ldd) = src (rows x cols, ld lds)^T
+hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd,
+                            int64_t rows, int64_t cols, hipStream_t s);
 // Batched assembly of p, q, U (TO), L_b and info (max_elems = largest
 // m + n + k n + k k of the batch).
 struct AsmTaskDev {

@@ -261,3 +261,21 @@ def test_batched_full_size_sampled(rlu):
         A32 = to_host(As[i])
         G = philox.gaussian_matrix(n, r + 8, 7204 + i).astype(np.float32)
         _check_reduced(A32, r, r + 8, G, outs[i], f"#{i} {m}x{n} r={r}")
+
+
+def test_batched_blocked_gram_inverse(rlu):
+    """A batch whose largest k exceeds 64 (blocked Gram inverse for every
+    problem, ragged block counts)."""
+    shapes = [(900, 700, 130, 138), (500, 400, 20, 28), (1200, 1000, 70, 78), (300, 300, 64, 72)]
+    probs = []
+    for i, (m, n, k, l) in enumerate(shapes):
+        A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 1500 + i)
+        G = workloads.gaussian((n, l), 1550 + i)
+        probs.append((A, k, l, G))
+    print("[batched] blocked Gram inverse", flush=True)
+    items = [(to_dev_colmajor(A), k, l, 0, to_dev_colmajor(G)) for A, k, l, G in probs]
+    outs = rlu.factor_batched(items)
+    torch.cuda.synchronize()
+    for (A, k, l, G), f in zip(probs, outs):
+        _check_f64(A, k, l, G, to_host(f.L), to_host(f.U), to_host(f.p), to_host(f.q),
+                   to_host(f.info), label=f"{A.shape} k={k}")

@@ -187,3 +187,28 @@ def test_leading_dimensions(rlu):
     o = orl.randomized_lu(A, k, l, G)
     assert rel_maxdiff(unpermute_rows(to_host(out.L), to_host(out.p)),
                        unpermute_rows(o["L"], o["p"])) < TOL
+
+
+@pytest.mark.parametrize("m,n,k,l", [
+    (1500, 1200, 65, 70),      # one full block and a 1-wide block
+    (3000, 2600, 200, 210),    # the 8192^2 configuration's rank
+    (4000, 3000, 300, 310),    # five blocks, ragged last one
+])
+def test_large_rank_blocked_gram_inverse(rlu, m, n, k, l):
+    """k > 64: the Gram inverse of Step 5 runs as blocked Gauss-Jordan."""
+    A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 610 + k)
+    G = workloads.gaussian((n, l), 620 + k)
+    run_and_compare(rlu, A, k, l, G, f"k={k}")
+
+
+@pytest.mark.parametrize("m,n,k,l", [
+    (16384, 2000, 290, 300),   # Y (16384 x 300) factored in column blocks
+    (2000, 16384, 290, 300),   # B^T (16384 x 290) factored in column blocks
+])
+def test_blocked_panels(rlu, m, n, k, l):
+    """Panels too tall and wide for one resident launch: column blocks, each
+    continuing from the row positions of the ones before, with a triangular
+    solve and a GEMM update in between."""
+    A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 640 + m)
+    G = workloads.gaussian((n, l), 650 + n)
+    run_and_compare(rlu, A, k, l, G, f"blocked {m}x{n}")
