@@ -9,8 +9,10 @@ sketch GEMM, pivoted LU of Y, Gram matrix and its inverse, projection GEMM,
 pivoted LU of B^T, assembly of L and U) on a device-resident input; for the
 batched workload a step is one rlu_factor_batched call over 256 problems.
 Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
-under "forms", the same matrix through the FP32 path and the 256-problem
-batch (disable with --forms none).  Only one GPU is used; --gpus N with
+under "forms", the same matrix through the FP32 path, the 16384 x 16384
+mixed-precision configuration beside the FP64 path on the same matrix, the
+256-problem batch, and the served request stream (throughput with p50/p99
+latency; disable the extra measurements with --forms none).  Only one GPU is used; --gpus N with
 N > 1 exits with a message.
 """
 from __future__ import annotations
@@ -40,6 +42,10 @@ WORKLOADS = {
     "small512": (512, 512, 10, 15, "lowrank10", 101, 7203, "fp64",
                  "512x512, X Y^T + 1e-9 N(0,1), X, Y 512x10, k=10, l=15, FP64"),
 }
+MIXED = ("mixed16384", 16384, 16384, 500, 520, 103, 7205,
+         "16384x16384, U and V Haar, sigma_i = i^-2, k=500, l=520; A stored FP32, BF16 MFMA "
+         "products with FP32 accumulation, FP64 pivoted LUs and Gram inverse; the same matrix "
+         "in FP64 through the FP64 path for the equal-error comparison")
 BATCH = ("batch256", 256, 104, 7204,
          "256 FP32 problems per call, m, n ~ U[256, 4096], A = X Y^T + 1e-6 N(0,1) with "
          "rank r ~ U[8, 64], k = r, l = r + 8")
@@ -248,6 +254,184 @@ def run_single(rlu, torch, np, name, steps, warmup, input_kind="spectral", check
     return res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works)
 
 
+def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup):
+    h = rlu.Handle(0)
+    h.set_timing(True)
+    st = torch.cuda.current_stream()
+    out = None
+    for _ in range(warmup):
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        evs[i][0].record(st)
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st)
+        evs[i][1].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    ph = [h.phase_times(b) for b in range(steps)]
+    ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0]}
+    return out, steps / wall, wall * 1e3 / steps, lat, ph
+
+
+def run_mixed(rlu, torch, np, steps):
+    import workloads
+
+    name, m, n, k, l, dseed, sseed, desc = MIXED
+    log(f"generating {name}")
+    A64 = workloads.spectral_matrix_torch(m, n, workloads.inv_square(min(m, n)), dseed,
+                                          device="cuda", dtype=torch.float64)
+    A64 = A64.t().contiguous().t()
+    A32 = A64.float().t().contiguous().t()
+    torch.cuda.synchronize()
+    o16, v16, ms16, lat16, ph16 = timed_calls(rlu, torch, np, A32, k, l, sseed,
+                                              rlu.PREC_MIXED_BF16, steps, 2)
+    r16 = power_residual(A64, o16.L.double(), o16.U.double(), o16.p, o16.q)
+    log(f"mixed bf16: {v16:.1f}/s residual {r16:.3e}")
+    del o16
+    o64, v64, ms64, lat64, ph64 = timed_calls(rlu, torch, np, A64, k, l, sseed,
+                                              rlu.PREC_FP64, max(3, steps // 2), 1)
+    r64 = power_residual(A64, o64.L, o64.U, o64.p, o64.q)
+    log(f"fp64 path: {v64:.1f}/s residual {r64:.3e}")
+    info64 = o64.info.cpu().tolist()
+    del o64
+    works16 = phase_work(m, n, k, l, 4.0, 4.0)
+    works64 = phase_work(m, n, k, l, 8.0, 8.0)
+    f_sk, b_sk = works16["sketch_gemm"]
+    t_sk = ph16["sketch_gemm"] * 1e-3
+    hbm_bound = b_sk / PEAK["hbm"] >= f_sk / PEAK["bf16"]
+    roof = ({"bound": "hbm", "achieved": b_sk / t_sk / 1e9, "peak": PEAK["hbm"] / 1e9,
+             "unit": "GB/s", "frac": b_sk / t_sk / PEAK["hbm"]} if hbm_bound else
+            {"bound": "mfma", "achieved": f_sk / t_sk / 1e12, "peak": PEAK["bf16"] / 1e12,
+             "unit": "TFLOP/s", "frac": f_sk / t_sk / PEAK["bf16"]})
+    roof.update({"traffic": None, "kernel": "sketch GEMM (Step 2), BF16 MFMA 16x16x32, FP32 A",
+                 "algorithmic_flops_per_launch": f_sk, "algorithmic_bytes_per_launch": b_sk})
+    del A32, A64
+    torch.cuda.empty_cache()
+    return {
+        "workload": desc, "value": v16, "unit": "factorizations/s", "ms_per_step": ms16,
+        "latency_ms": {"p50": float(np.percentile(lat16, 50)),
+                       "p99": float(np.percentile(lat16, 99))},
+        "phase_ms": ph16,
+        "kernels": kernel_table(ph16, works16, PEAK["bf16"]),
+        "step_roofline": step_roofline(works16, PEAK["bf16"], ms16),
+        "roofline": roof,
+        "rel_residual": r16,
+        "fp64_path": {"value": v64, "ms_per_step": ms64, "rel_residual": r64, "phase_ms": ph64,
+                      "kernels": kernel_table(ph64, works64, PEAK["f64"]), "info": info64},
+        "speedup_vs_fp64": v16 / v64,
+        "residual_excess_vs_fp64": r16 - r64,
+        "equal_error": bool(r16 <= r64 + 1e-3),
+    }
+
+
+SERVE = ("serve", 64, 105, 7206,
+         "request stream: m log-uniform [512, 32768], n log-uniform [512, 8192], "
+         "k ~ U{16..256}, l = k + 10, A = U_R diag(exp(-i/k)) V_R^T with R = min(m, n, 24 k), "
+         "FP32 storage, BF16 products with FP32 accumulation; Poisson arrivals at 0.7 x the "
+         "closed-loop saturation rate")
+
+
+def make_serve_pool(torch, count, seed):
+    """Device-resident request matrices of the serving workload (Haar-like
+    thin factors from an FP32 QR of Gaussian matrices)."""
+    import workloads
+
+    shapes = workloads.serve_stream(count, seed=seed)
+    pool = []
+    gen = torch.Generator(device="cuda")
+    for i, (m, n, k, l, s) in enumerate(shapes):
+        gen.manual_seed(s % (2 ** 63))
+        R = min(m, n, 24 * k)
+        U, _ = torch.linalg.qr(torch.randn(m, R, generator=gen, device="cuda"))
+        V, _ = torch.linalg.qr(torch.randn(n, R, generator=gen, device="cuda"))
+        sig = torch.exp(-torch.arange(1, R + 1, device="cuda", dtype=torch.float32) / k)
+        At = (V * sig) @ U.t()          # n x m = A^T, so A is column-major
+        pool.append((At.t(), k, l))
+        del U, V
+    torch.cuda.synchronize()
+    return pool
+
+
+def run_serve(rlu, torch, np, n_req=2048, warm=256):
+    name, pool_n, dseed, sseed, desc = SERVE
+    log(f"generating serving pool of {pool_n} matrices")
+    pool = make_serve_pool(torch, pool_n, dseed)
+    srv = rlu.Server(0)
+    order = np.random.default_rng(dseed).integers(0, pool_n, size=warm + n_req + 512)
+
+    def submit(i):
+        A, k, l = pool[order[i]]
+        return srv.submit(A, k, l, seed=sseed + i, precision=rlu.PREC_MIXED_BF16)
+
+    # closed loop: everything submitted at once
+    t0 = time.perf_counter()
+    ts = [submit(i) for i in range(512)]
+    sat_status = {}
+    for i, t in enumerate(ts):
+        st = srv.wait(t)
+        sat_status[st] = sat_status.get(st, 0) + 1
+        if st != 0 and sat_status[st] == 1:
+            A, k, l = pool[order[i]]
+            _, r = srv.poll(t)
+            log(f"serve: request {i} ({A.shape[0]}x{A.shape[1]}, k={k}, l={l}) status {st} "
+                f"info {list(r.info)}")
+    sat = 512 / (time.perf_counter() - t0)
+    for t in ts:
+        srv.release(t)
+    log(f"serve: closed-loop saturation {sat:.0f} requests/s")
+    # open loop, Poisson arrivals at 0.7 x saturation
+    lam = 0.7 * sat
+    gaps = np.random.default_rng(dseed + 1).exponential(1.0 / lam, size=warm + n_req)
+    arrive = np.cumsum(gaps)
+    outstanding = {}
+    lat = []
+    done_t = []
+    statuses = {}
+    start = time.perf_counter()
+    i = 0
+    total = warm + n_req
+    while i < total or outstanding:
+        now = time.perf_counter() - start
+        while i < total and arrive[i] <= now:
+            outstanding[submit(512 + i)] = i
+            i += 1
+        for t in list(outstanding):
+            st, r = srv.poll(t)
+            if st == 1:
+                continue
+            idx = outstanding.pop(t)
+            statuses[st] = statuses.get(st, 0) + 1
+            if idx >= warm:
+                lat.append((r.t_done_us - r.t_submit_us) * 1e-3)
+                done_t.append(time.perf_counter() - start)
+            srv.release(t)
+        if i < total:
+            wait = arrive[i] - (time.perf_counter() - start)
+            if wait > 2e-4:
+                time.sleep(min(wait, 1e-3))
+    span = max(done_t) - arrive[warm] if done_t else float("nan")
+    srv.close()
+    lat = np.array(lat)
+    fp = [rlu.serve_footprint(A.shape[0], A.shape[1], k, l, rlu.F32, rlu.PREC_MIXED_BF16)
+          for A, k, l in pool]
+    del pool
+    torch.cuda.empty_cache()
+    return {
+        "workload": desc, "value": len(lat) / span, "unit": "requests/s",
+        "offered_rate": lam, "closed_loop_saturation": sat,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "mean": float(lat.mean()), "max": float(lat.max())},
+        "requests": {"measured": int(len(lat)), "warmup": warm, "pool": pool_n,
+                     "statuses": {str(k): v for k, v in statuses.items()},
+                     "closed_loop_statuses": {str(k): v for k, v in sat_status.items()}},
+        "footprint_mb": {"mean": float(np.mean(fp) / 1e6), "max": float(np.max(fp) / 1e6)},
+    }
+
+
 def run_batch(rlu, torch, np, steps, warmup):
     import workloads
 
@@ -324,8 +508,9 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp32,batch",
-                    help="extra measurements in the same line: comma list of fp32, batch, or none")
+    ap.add_argument("--forms", default="fp32,batch,mixed,serve",
+                    help="extra measurements in the same line: comma list of fp32, batch, "
+                         "mixed, serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
     ap.add_argument("--no-check", action="store_true",
@@ -433,9 +618,16 @@ def main():
             "speedup_vs_fp64": (n32 / w32) / res["value"]}
         log(f"fp32 form: {n32 / w32:.1f}/s residual {r32:.3e}")
         del A32, o32
+    if "mixed" in forms:
+        result["forms"]["mixed16384"] = run_mixed(rlu, torch, np, 8)
     if "batch" in forms:
         result["forms"]["batch256"] = run_batch(rlu, torch, np, max(5, args.steps // 2), 2)
         log(f"batch form: {result['forms']['batch256']['value']:.0f} factorizations/s")
+    if "serve" in forms:
+        result["forms"]["serve"] = run_serve(rlu, torch, np)
+        sv = result["forms"]["serve"]
+        log(f"serve form: {sv['value']:.0f} requests/s, p50 {sv['latency_ms']['p50']:.2f} ms, "
+            f"p99 {sv['latency_ms']['p99']:.2f} ms")
 
     if not args.no_cpu_baseline:
         A_host = A.double().cpu().numpy() if prec == "fp32" else A.cpu().numpy()

@@ -74,13 +74,13 @@ struct Plan {
   size_t asmb = 0; int64_t asm_max = 0;
 };
 
-// Panel shape of a batch: the largest rows-per-workgroup (a multiple of 64,
-// at most 512) whose LDS image fits for the widest panel.
+// Rows per workgroup of a panel: the largest multiple of 64 (at most 512)
+// whose LDS image fits for a panel of that width.
 constexpr size_t kPanelLdsBudget = 159 * 1024;
 
-int panel_rows_for(int maxcols) {
+int panel_rows_for(int ncols) {
   for (int rpl = 8; rpl >= 1; rpl >>= 1)
-    if (panel_lds_bytes(64 * rpl, maxcols) <= kPanelLdsBudget) return 64 * rpl;
+    if (panel_lds_bytes(64 * rpl, ncols) <= kPanelLdsBudget) return 64 * rpl;
   return 0;
 }
 
@@ -228,11 +228,22 @@ int schedule_gangs(const std::vector<int>& nwg, const std::vector<int>& ncols, i
 
 rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableWriter& tw,
                          PanelLaunch& L) {
-  int maxcols = 0;
-  for (const Item& it : P.items) maxcols = std::max<int>(maxcols, (int)(second ? it.pb.k : it.pb.l));
-  const int R = panel_rows_for(maxcols);
+  // every problem keeps its own rows per workgroup (the most its width
+  // allows); the launch is compiled for the largest and sized for the
+  // largest LDS image, including the bulk update's read of a full 64 * RPL
+  // rows past the last column of a shorter block
+  int R = 0;
+  size_t lds = 0;
+  for (const Item& it : P.items) R = std::max(R, second ? it.R_b : it.R_y);
   if (R == 0) return RLU_ERR_UNSUPPORTED;
-  const size_t lds = panel_lds_bytes(R, maxcols);
+  const int rmax = R <= 64 ? 64 : R <= 128 ? 128 : R <= 256 ? 256 : 512;
+  for (const Item& it : P.items) {
+    const int r = second ? it.R_b : it.R_y;
+    const int c = (int)(second ? it.pb.k : it.pb.l);
+    lds = std::max(lds, panel_lds_bytes(r, c));
+    lds = std::max(lds, (size_t)8 * ((size_t)(c - 1) * r + rmax));
+  }
+  if (lds > kPanelLdsBudget) return RLU_ERR_UNSUPPORTED;
   // Sizing pass (no base): no device query; at least one workgroup per CU
   // is resident and at most four (512-thread workgroups), which bounds the
   // schedule's size from above.
@@ -291,13 +302,6 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
   P.lp = prec == RLU_PREC_MIXED_BF16 || prec == RLU_PREC_MIXED_FP16;
   P.fp16 = prec == RLU_PREC_MIXED_FP16;
   P.f32 = pbs[0].dtype == RLU_F32;
-  int maxl = 0, maxk = 0;
-  for (int i = 0; i < count; ++i) {
-    maxl = std::max<int>(maxl, (int)pbs[i].l);
-    maxk = std::max<int>(maxk, (int)pbs[i].k);
-  }
-  const int Ry = panel_rows_for(maxl), Rb = panel_rows_for(maxk);
-  if (Ry == 0 || Rb == 0) return RLU_ERR_UNSUPPORTED;
   size_t off = 0;
   auto take = [&](size_t& slot, size_t bytes) {
     slot = off;
@@ -309,6 +313,8 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     it.pb = pbs[i];
     it.io = ios[i];
     const rlu_problem_t& pb = it.pb;
+    const int Ry = panel_rows_for((int)pb.l), Rb = panel_rows_for((int)pb.k);
+    if (Ry == 0 || Rb == 0) return RLU_ERR_UNSUPPORTED;
     it.nwg_y = (int)((pb.m + Ry - 1) / Ry);
     it.R_y = (int)((pb.m + it.nwg_y - 1) / it.nwg_y);
     it.nwg_b = (int)((pb.n + Rb - 1) / Rb);

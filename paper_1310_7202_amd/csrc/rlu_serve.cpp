@@ -51,6 +51,7 @@ struct Req {
   rlu_status_t status = RLU_PENDING;
   int32_t info[3] = {0, 0, 0};
   double t_submit = 0, t_start = 0, t_done = 0;
+  bool solo = false;    // too large for the batched kernels: runs alone (rlu_factor)
 };
 
 struct Flight {
@@ -78,6 +79,18 @@ size_t output_layout(const rlu_problem_t& pb, size_t* offU, size_t* offp, size_t
   return align_up(off + 16);
 }
 
+// Workspace a request needs: its share of a batch, or, for a shape the
+// batched kernels cannot run, the single-problem workspace (it then runs
+// alone through rlu_factor).
+rlu_status_t request_ws_bytes(const rlu_problem_t& pb, int cus, size_t* bytes, bool* solo) {
+  rlu_status_t st = batched_item_bytes(pb, cus, bytes);
+  *solo = false;
+  if (st != RLU_ERR_UNSUPPORTED) return st;
+  st = rlu_workspace_size(&pb, bytes);
+  if (st == RLU_OK) *solo = true;
+  return st;
+}
+
 double now_us(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
 }
@@ -86,7 +99,8 @@ double now_us(std::chrono::steady_clock::time_point t0) {
 
 struct rlu_server_s {
   rlu_server_config_t cfg{};
-  rlu_handle_s* h = nullptr;
+  rlu_handle_s* h = nullptr;                 // batched launches (task-table staging)
+  std::vector<rlu_handle_s*> solo_h;          // per stream: requests that run alone
   std::vector<hipStream_t> streams;
   std::vector<bool> busy;
   std::vector<hipEvent_t> done;      // per stream: completion of its batch
@@ -161,8 +175,10 @@ bool rlu_server_s::launch_one(std::unique_lock<std::mutex>& lk) {
   const size_t budget = cfg.hbm_budget_bytes;
   // strict FIFO: stop at the first request that does not fit or differs in
   // precision from the head
-  while (!queue.empty() && (int)batch.size() < kMaxBatch) {
+  const bool solo = queue.front()->solo;
+  while (!queue.empty() && (int)batch.size() < (solo ? 1 : kMaxBatch)) {
     Req* r = queue.front();
+    if (r->solo != solo) break;
     if (r->pb.dtype != head.dtype || r->pb.precision != head.precision) break;
     if (cfg.max_inflight > 0 && inflight >= cfg.max_inflight) break;
     const size_t fp = r->ws_bytes + r->out_bytes;
@@ -204,13 +220,22 @@ bool rlu_server_s::launch_one(std::unique_lock<std::mutex>& lk) {
     io.q = (int64_t*)((char*)r->out + r->offq);
     io.info = (int32_t*)((char*)r->out + r->offinfo);
   }
-  size_t wsb = 0;
-  if (st == RLU_OK) st = batched_ws_bytes(n, pbs.data(), ios.data(), h->cus, &wsb);
-  if (st == RLU_OK && hipMallocAsync(&f.ws, wsb, s) != hipSuccess) {
-    f.ws = nullptr;
-    st = RLU_ERR_OUT_OF_MEMORY;
+  if (solo) {
+    // the single-problem path keeps every workgroup busy in its pivoted LUs
+    // and uses cooperative launches: order it after the last panel launch
+    // and make the next one wait for all of it
+    if (st == RLU_OK && hipStreamWaitEvent(s, gate, 0) != hipSuccess) st = RLU_ERR_DEVICE;
+    if (st == RLU_OK) st = rlu_factor(solo_h[sidx], &pbs[0], &ios[0], s);
+    if (st == RLU_OK && hipEventRecord(gate, s) != hipSuccess) st = RLU_ERR_DEVICE;
+  } else {
+    size_t wsb = 0;
+    if (st == RLU_OK) st = batched_ws_bytes(n, pbs.data(), ios.data(), h->cus, &wsb);
+    if (st == RLU_OK && hipMallocAsync(&f.ws, wsb, s) != hipSuccess) {
+      f.ws = nullptr;
+      st = RLU_ERR_OUT_OF_MEMORY;
+    }
+    if (st == RLU_OK) st = batched_enqueue_ws(h, n, pbs.data(), ios.data(), s, f.ws, wsb, gate);
   }
-  if (st == RLU_OK) st = batched_enqueue_ws(h, n, pbs.data(), ios.data(), s, f.ws, wsb, gate);
   for (int i = 0; i < n && st == RLU_OK; ++i)
     if (hipMemcpyAsync(info_host[sidx] + 3 * i, ios[i].info, 12, hipMemcpyDeviceToHost, s) !=
         hipSuccess)
@@ -246,7 +271,8 @@ rlu_status_t rlu_serve_footprint(const rlu_problem_t* pb, size_t* bytes) {
   rlu_status_t st = batched_validate(1, pb, nullptr);
   if (st != RLU_OK) return st;
   size_t ws = 0, oU, op, oq, oi;
-  st = batched_item_bytes(*pb, 256, &ws);
+  bool solo = false;
+  st = request_ws_bytes(*pb, 256, &ws, &solo);
   if (st != RLU_OK) return st;
   *bytes = ws + output_layout(*pb, &oU, &op, &oq, &oi);
   return RLU_OK;
@@ -259,47 +285,43 @@ rlu_status_t rlu_serve_create(const rlu_server_config_t* cfg, rlu_server_t* out)
   rlu_server_s* srv = new (std::nothrow) rlu_server_s();
   if (!srv) return RLU_ERR_OUT_OF_MEMORY;
   srv->cfg = *cfg;
+  auto fail = [srv](rlu_status_t st) {
+    for (hipEvent_t x : srv->done) hipEventDestroy(x);
+    for (int32_t* x : srv->info_host) hipHostFree(x);
+    for (hipStream_t x : srv->streams) hipStreamDestroy(x);
+    for (rlu_handle_s* x : srv->solo_h) rlu_destroy(x);
+    if (srv->gate) hipEventDestroy(srv->gate);
+    if (srv->h) rlu_destroy(srv->h);
+    delete srv;
+    return st;
+  };
   rlu_status_t st = rlu_create(&srv->h, cfg->device);
-  if (st != RLU_OK) { delete srv; return st; }
+  if (st != RLU_OK) { srv->h = nullptr; return fail(st); }
   DeviceScope dev(cfg->device);
   if (srv->cfg.hbm_budget_bytes == 0) {
     size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) != hipSuccess) { rlu_destroy(srv->h); delete srv; return RLU_ERR_DEVICE; }
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(RLU_ERR_DEVICE);
     srv->cfg.hbm_budget_bytes = fr / 10 * 9;
   }
   for (int i = 0; i < kStreams; ++i) {
     hipStream_t s = nullptr;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : srv->streams) hipStreamDestroy(x);
-      rlu_destroy(srv->h);
-      delete srv;
-      return RLU_ERR_DEVICE;
-    }
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(RLU_ERR_DEVICE);
     srv->streams.push_back(s);
     srv->busy.push_back(false);
     hipEvent_t e = nullptr;
-    int32_t* ih = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess ||
-        hipHostMalloc((void**)&ih, 12 * (size_t)kMaxBatch, hipHostMallocDefault) != hipSuccess) {
-      if (e) hipEventDestroy(e);
-      for (hipEvent_t x : srv->done) hipEventDestroy(x);
-      for (int32_t* x : srv->info_host) hipHostFree(x);
-      for (hipStream_t x : srv->streams) hipStreamDestroy(x);
-      rlu_destroy(srv->h);
-      delete srv;
-      return RLU_ERR_DEVICE;
-    }
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RLU_ERR_DEVICE);
     srv->done.push_back(e);
+    int32_t* ih = nullptr;
+    if (hipHostMalloc((void**)&ih, 12 * (size_t)kMaxBatch, hipHostMallocDefault) != hipSuccess)
+      return fail(RLU_ERR_OUT_OF_MEMORY);
     srv->info_host.push_back(ih);
+    rlu_handle_s* hs = nullptr;
+    st = rlu_create(&hs, cfg->device);
+    if (st != RLU_OK) return fail(st);
+    srv->solo_h.push_back(hs);
   }
-  if (hipEventCreateWithFlags(&srv->gate, hipEventDisableTiming) != hipSuccess) {
-    for (hipEvent_t x : srv->done) hipEventDestroy(x);
-    for (int32_t* x : srv->info_host) hipHostFree(x);
-    for (hipStream_t x : srv->streams) hipStreamDestroy(x);
-    rlu_destroy(srv->h);
-    delete srv;
-    return RLU_ERR_DEVICE;
-  }
+  if (hipEventCreateWithFlags(&srv->gate, hipEventDisableTiming) != hipSuccess)
+    return fail(RLU_ERR_DEVICE);
   srv->t0 = std::chrono::steady_clock::now();
   srv->thr = std::thread([srv]() { srv->loop(); });
   *out = srv;
@@ -317,7 +339,7 @@ rlu_status_t rlu_serve_submit(rlu_server_t srv, const rlu_problem_t* pb, const v
   r->pb = *pb;
   r->A = A;
   r->lda = lda;
-  st = batched_item_bytes(*pb, srv->h->cus, &r->ws_bytes);
+  st = request_ws_bytes(*pb, srv->h->cus, &r->ws_bytes, &r->solo);
   if (st != RLU_OK) { delete r; return st; }
   r->out_bytes = output_layout(*pb, &r->offU, &r->offp, &r->offq, &r->offinfo);
   if (r->ws_bytes + r->out_bytes > srv->cfg.hbm_budget_bytes) { delete r; return RLU_ERR_TOO_LARGE; }
@@ -449,6 +471,7 @@ rlu_status_t rlu_serve_destroy(rlu_server_t srv) {
   for (hipEvent_t x : srv->done) hipEventDestroy(x);
   for (int32_t* x : srv->info_host) hipHostFree(x);
   for (hipStream_t s : srv->streams) hipStreamDestroy(s);
+  for (rlu_handle_s* x : srv->solo_h) rlu_destroy(x);
   rlu_destroy(srv->h);
   delete srv;
   return RLU_OK;

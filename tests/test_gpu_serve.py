@@ -203,3 +203,30 @@ def test_serve_mixed_precision_stream(rlu):
         assert r_gpu <= r_ora + 1e-3
         srv.release(t)
     srv.close()
+
+
+def test_oversize_request_runs_alone_in_the_mix(rlu):
+    """A request whose panel does not fit the batched kernels (20000 rows,
+    l = 210) runs through the single-problem path, interleaved with batched
+    requests; its factors equal a direct rlu_factor call."""
+    srv = rlu.Server(0)
+    m, n, k, l = 20000, 1500, 200, 210
+    A = workloads.low_rank_plus_noise_torch(m, n, k, 1e-6, 31, dtype=torch.float64)
+    ref = rlu.factor(A, k, l, seed=9)
+    small = _inputs(1600)
+    devs = [(to_dev_colmajor(X), to_dev_colmajor(G)) for X, kk, ll, G in small]
+    print("[serve] oversize request in a mix", flush=True)
+    ts = [srv.submit(Xd, kk, ll, G=Gd) for (Xd, Gd), (X, kk, ll, G) in zip(devs[:3], small[:3])]
+    tb = srv.submit(A, k, l, seed=9)
+    ts += [srv.submit(Xd, kk, ll, G=Gd) for (Xd, Gd), (X, kk, ll, G) in zip(devs[3:], small[3:])]
+    assert srv.wait(tb) == 0
+    f = srv.result(tb)
+    torch.cuda.synchronize()
+    for a, b in zip((f.L, f.U, f.p, f.q), (ref.L, ref.U, ref.p, ref.q)):
+        np.testing.assert_array_equal(to_host(a), to_host(b))
+    for t, (X, kk, ll, G) in zip(ts, small):
+        assert srv.wait(t) == 0
+        _check(X, kk, ll, G, srv.result(t))
+        srv.release(t)
+    srv.release(tb)
+    srv.close()
