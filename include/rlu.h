@@ -162,6 +162,14 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
 rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count, const rlu_problem_t* pbs,
                                 const rlu_buffers_t* ios, rlu_stream_t stream);
 
+/* Tile shapes of the grouped products of rlu_factor_batched, for tuning
+ * tools.  product: 0 sketch (Step 2), 1 Gram matrix, 2 projection (Step 5),
+ * 3 S^{-1} C, 4 L = Lv L_b (Step 7).  cfg: an index for which rlu_tile_name
+ * returns a name ("BMxBNxBK"), or -1 for the library's tuned table.  The
+ * setting applies to later calls on this handle. */
+rlu_status_t rlu_set_tile(rlu_handle_t h, int32_t product, int32_t cfg);
+const char* rlu_tile_name(int32_t cfg);  /* NULL if cfg is not a grouped tile */
+
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.
  *

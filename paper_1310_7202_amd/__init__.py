@@ -33,7 +33,7 @@ STATUS = {
 
 # every function include/rlu.h declares
 EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                    "rlu_factor_batched", "rlu_serve_create", "rlu_serve_submit",
+                    "rlu_factor_batched", "rlu_set_tile", "rlu_tile_name", "rlu_serve_create", "rlu_serve_submit",
                     "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
                     "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
@@ -96,6 +96,9 @@ def lib() -> ctypes.CDLL:
         L.rlu_factor_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                          ctypes.POINTER(Buffers), ctypes.c_void_p]
         L.rlu_check_info.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+        L.rlu_set_tile.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+        L.rlu_tile_name.argtypes = [ctypes.c_int32]
+        L.rlu_tile_name.restype = ctypes.c_char_p
         L.rlu_serve_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
         L.rlu_serve_submit.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64)]
@@ -117,7 +120,7 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_char_p), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]
         for name in ("rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_factor",
-                     "rlu_factor_batched", "rlu_check_info", "rlu_set_timing",
+                     "rlu_factor_batched", "rlu_set_tile", "rlu_check_info", "rlu_set_timing",
                      "rlu_phase_times", "rlu_serve_create", "rlu_serve_submit",
                      "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
                      "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy"):
@@ -161,6 +164,10 @@ class Handle:
     @property
     def ptr(self):
         return self._h
+
+    def set_tile(self, product: int, cfg: int):
+        """Tile shape of a grouped product of the batched form (-1: tuned table)."""
+        _check(lib().rlu_set_tile(self._h, product, cfg), "rlu_set_tile")
 
     def set_timing(self, enable: bool = True):
         _check(lib().rlu_set_timing(self._h, 1 if enable else 0), "rlu_set_timing")
@@ -326,6 +333,16 @@ def factor_batched(problems, *, precision: int | None = None, handle: Handle | N
     batched call.  Returns a list of Factors (device tensors, not
     synchronized)."""
     return Batch(problems, precision=precision, outs=outs).run(handle, stream)
+
+
+def tile_names() -> dict:
+    """{cfg: "BMxBNxBK"} of the tiles the grouped products can use."""
+    out = {}
+    for c in range(64):
+        n = lib().rlu_tile_name(c)
+        if n:
+            out[c] = n.decode()
+    return out
 
 
 def serve_footprint(m, n, k, l, dtype=F64, precision=PREC_FP64) -> int:

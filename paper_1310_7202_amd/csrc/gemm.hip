@@ -275,18 +275,20 @@ __global__ void __launch_bounds__(256) splitk_sum_kernel(int64_t M, int64_t N, i
 
 // Tile shapes compiled in (BM, BN, BK, waves M x N, LDS buffers).
 enum CfgId { C64x64x16, C64x112x16, C112x64x16, C64x112x32, C112x64x32, C112x64x64,
-             C64x64x32, C128x64x16, C64x128x16, CFG_COUNT };
+             C64x64x32, C128x64x16, C64x128x16, C128x224x16, C224x128x16, CFG_COUNT };
 struct CfgInfo { int bm, bn, bk; };
 struct GemmShape { int cfg; int ksplit; };
 constexpr CfgInfo kCfg[CFG_COUNT] = {{64, 64, 16}, {64, 112, 16}, {112, 64, 16},
                                      {64, 112, 32}, {112, 64, 32}, {112, 64, 64},
-                                     {64, 64, 32}, {128, 64, 16}, {64, 128, 16}};
+                                     {64, 64, 32}, {128, 64, 16}, {64, 128, 16},
+                                     {128, 224, 16}, {224, 128, 16}};
 
 int g_force_cfg = -1;  // tuning override (-1: automatic)
 
 // Tile shape and split-K for a product (the tuning table of this library,
-// from sweeps of the FP64 products of the 8192 x 8192 configuration on
-// MI355X):
+// from sweeps of the FP64 and FP32 products of the 8192 x 8192
+// configuration on MI355X: 128 x 224 tiles with split-K 4 took the sketch
+// from 0.75 to 0.56 ms in FP64, 224 x 128 the projection from 1.31 to 0.84 ms):
 //   * the tile shape minimizes (rounds of 256 tiles) x (tile area), ties to
 //     more tiles; an A operand streamed along K (Lv^T) uses 64 x 64 tiles,
 //     which measured fastest for it;
@@ -295,6 +297,18 @@ int g_force_cfg = -1;  // tuning override (-1: automatic)
 //     keeping at least 512 of K per split.
 GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
   GemmShape sh{C64x64x16, 1};
+  // Long products with one short side (the two products with A): one
+  // 8-wave tile spans the whole short side, so the long operand is read once,
+  // and split-K brings the grid to one workgroup per CU.
+  if (g_force_cfg < 0 && K >= 4096 && ((N <= 224 && M >= 1024) || (M <= 224 && N >= 1024))) {
+    sh.cfg = N <= 224 && M >= 1024 ? C128x224x16 : C224x128x16;
+    const CfgInfo& c = kCfg[sh.cfg];
+    const int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
+    int ks = 1;
+    while (tiles * ks < 256 && K / (ks * 2) >= 1024 && ks < 32) ks *= 2;
+    sh.ksplit = ks;
+    return sh;
+  }
   if (g_force_cfg >= 0) {
     sh.cfg = g_force_cfg;
   } else if (kcontig_a) {
@@ -351,6 +365,8 @@ hipError_t launch_ops(const GemmDesc& d, hipStream_t s) {
     case C112x64x64: e = launch_cfg<TA, TB, TC, TO, 112, 64, 64, 1, 4, 1, OA, OB>(d, ks, s); break;
     case C64x64x32: e = launch_cfg<TA, TB, TC, TO, 64, 64, 32, 2, 2, 2, OA, OB>(d, ks, s); break;
     case C128x64x16: e = launch_cfg<TA, TB, TC, TO, 128, 64, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
+    case C128x224x16: e = launch_cfg<TA, TB, TC, TO, 128, 224, 16, 4, 2, 2, OA, OB>(d, ks, s); break;
+    case C224x128x16: e = launch_cfg<TA, TB, TC, TO, 224, 128, 16, 2, 4, 2, OA, OB>(d, ks, s); break;
     default: e = launch_cfg<TA, TB, TC, TO, 64, 128, 16, 2, 2, 2, OA, OB>(d, ks, s); break;
   }
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;
@@ -381,6 +397,7 @@ hipError_t dispatch(const GemmDesc& d, hipStream_t s) {
 template <typename TA, typename TB, typename TC, typename TO, OpA OA, OpB OB>
 hipError_t launch_grouped_ops(int cfg, const GemmTaskDev* tasks, const int2* map, int nwg,
                               hipStream_t s) {
+  if (nwg <= 0) return hipSuccess;
 #define RLU_GG(BM, BN, BK, WM, WN, NB)                                                       \
   hipLaunchKernelGGL((gemm_grouped_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NB, OA, OB>), \
                      dim3((unsigned)nwg), dim3(64 * WM * WN), 0, s, tasks, map)
@@ -388,25 +405,15 @@ hipError_t launch_grouped_ops(int cfg, const GemmTaskDev* tasks, const int2* map
     case C64x64x16: RLU_GG(64, 64, 16, 2, 2, 2); break;
     case C64x112x16: RLU_GG(64, 112, 16, 4, 1, 2); break;
     case C112x64x16: RLU_GG(112, 64, 16, 1, 4, 2); break;
+    case C64x112x32: RLU_GG(64, 112, 32, 4, 1, 2); break;
+    case C112x64x32: RLU_GG(112, 64, 32, 1, 4, 2); break;
+    case C64x64x32: RLU_GG(64, 64, 32, 2, 2, 2); break;
+    case C128x64x16: RLU_GG(128, 64, 16, 2, 2, 2); break;
+    case C64x128x16: RLU_GG(64, 128, 16, 2, 2, 2); break;
     default: return hipErrorInvalidValue;
   }
 #undef RLU_GG
   return hipGetLastError();
-}
-
-template <typename TA, typename TB, typename TC, typename TO>
-hipError_t dispatch_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks, const int2* map,
-                            int nwg, hipStream_t s) {
-  if (nwg <= 0) return hipSuccess;
-  if (opa == OpA::Plain && opb == OpB::Plain)
-    return launch_grouped_ops<TA, TB, TC, TO, OpA::Plain, OpB::Plain>(cfg, tasks, map, nwg, s);
-  if (opa == OpA::LvT && opb == OpB::Plain)
-    return launch_grouped_ops<TA, TB, TC, TO, OpA::LvT, OpB::Plain>(cfg, tasks, map, nwg, s);
-  if (opa == OpA::LvT && opb == OpB::Lv)
-    return launch_grouped_ops<TA, TB, TC, TO, OpA::LvT, OpB::Lv>(cfg, tasks, map, nwg, s);
-  if (opa == OpA::Lv && opb == OpB::Plain)
-    return launch_grouped_ops<TA, TB, TC, TO, OpA::Lv, OpB::Plain>(cfg, tasks, map, nwg, s);
-  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -417,19 +424,45 @@ void gemm_group_tile(int cfg, int* bm, int* bn) {
   *bn = kCfg[c].bn;
 }
 
-template <typename TA, typename TB, typename TC, typename TO>
-hipError_t launch_gemm_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks,
-                               const int2* map, int nwg, hipStream_t s) {
-  return dispatch_grouped<TA, TB, TC, TO>(opa, opb, cfg, tasks, map, nwg, s);
+bool gemm_group_cfg_valid(int cfg) {
+  switch (cfg) {
+    case C64x64x16: case C64x112x16: case C112x64x16: case C64x112x32: case C112x64x32:
+    case C64x64x32: case C128x64x16: case C64x128x16:
+      return true;
+    default:
+      return false;
+  }
 }
-template hipError_t launch_gemm_grouped<double, double, double, double>(
-    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
-template hipError_t launch_gemm_grouped<float, float, float, double>(
-    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
-template hipError_t launch_gemm_grouped<double, float, float, double>(
-    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
-template hipError_t launch_gemm_grouped<double, double, double, float>(
-    OpA, OpB, int, const GemmTaskDev*, const int2*, int, hipStream_t);
+
+const char* gemm_cfg_name(int cfg) {
+  static const char* const names[CFG_COUNT] = {
+      "64x64x16", "64x112x16", "112x64x16", "64x112x32", "112x64x32", "112x64x64",
+      "64x64x32", "128x64x16", "64x128x16", "128x224x16", "224x128x16"};
+  return (cfg >= 0 && cfg < CFG_COUNT) ? names[cfg] : nullptr;
+}
+
+// The grouped products of the batched form, by role (operand forms and
+// types fixed by the role; f32: FP32 storage of A, G and L).
+hipError_t launch_gemm_grouped_role(GemmRole role, bool f32, int cfg, const GemmTaskDev* tasks,
+                                    const int2* map, int nwg, hipStream_t s) {
+  if (!gemm_group_cfg_valid(cfg)) return hipErrorInvalidValue;
+  switch (role) {
+    case GemmRole::Sketch:
+      return f32 ? launch_grouped_ops<float, float, float, double, OpA::Plain, OpB::Plain>(cfg, tasks, map, nwg, s)
+                 : launch_grouped_ops<double, double, double, double, OpA::Plain, OpB::Plain>(cfg, tasks, map, nwg, s);
+    case GemmRole::Gram:
+      return launch_grouped_ops<double, double, double, double, OpA::LvT, OpB::Lv>(cfg, tasks, map, nwg, s);
+    case GemmRole::Project:
+      return f32 ? launch_grouped_ops<double, float, float, double, OpA::LvT, OpB::Plain>(cfg, tasks, map, nwg, s)
+                 : launch_grouped_ops<double, double, double, double, OpA::LvT, OpB::Plain>(cfg, tasks, map, nwg, s);
+    case GemmRole::Solve:
+      return launch_grouped_ops<double, double, double, double, OpA::Plain, OpB::Plain>(cfg, tasks, map, nwg, s);
+    case GemmRole::FormL:
+      return f32 ? launch_grouped_ops<double, double, double, float, OpA::Lv, OpB::Plain>(cfg, tasks, map, nwg, s)
+                 : launch_grouped_ops<double, double, double, double, OpA::Lv, OpB::Plain>(cfg, tasks, map, nwg, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_splitk_sum_grouped(const GemmTaskDev* tasks, int count, int64_t max_elems,
                                      hipStream_t s) {

@@ -21,6 +21,7 @@
 // the same problems and buffers come back; the task tables live in the
 // handle's batch workspace and are uploaded only when the batch changes.
 #include "rlu_internal.h"
+#include "tuned_tiles.h"
 
 #include <algorithm>
 #include <array>
@@ -59,6 +60,7 @@ struct PanelLaunch {
 
 struct Plan {
   std::vector<Item> items;
+  int tile[5] = {-1, -1, -1, -1, -1};  // per-product overrides of the tile table
   bool lp = false, fp16 = false, f32 = false;
   size_t zero_bytes = 0;  // [0, zero_bytes) of the workspace: flags and exchange areas
   size_t data_end = 0;
@@ -84,12 +86,18 @@ int panel_rows_for(int ncols) {
   return 0;
 }
 
-// Tuning table of the grouped products (tile shape by output width N of
-// Step 2; every other product uses 64 x 64): a tile at least as wide as
-// the sketch reads each tile row of A once.
-int sketch_cfg(int64_t N) {
-  if (N <= 64) return GEMM_CFG_64x64;
-  if (N <= 112) return GEMM_CFG_64x112;
+// Tile shape of a grouped product: a handle override, else the tuned table,
+// else the built-in rule (the sketch takes a tile at least as wide as its
+// output, so each tile row of A is read once; the others 64 x 64).
+int pick_cfg(const Plan& P, GemmRole role, int64_t N) {
+  const int r = (int)role;
+  if (P.tile[r] >= 0) return P.tile[r];
+  const int t = tuned::kGroupedTile[r][P.f32 ? 1 : 0];
+  if (t >= 0 && gemm_group_cfg_valid(t)) return t;
+  if (role == GemmRole::Sketch) {
+    if (N <= 64) return GEMM_CFG_64x64;
+    if (N <= 112) return GEMM_CFG_64x112;
+  }
   return GEMM_CFG_64x64;
 }
 
@@ -380,7 +388,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       g.C = base + it.Y; g.ldc = it.pb.m;
       g.ksplit = 1;
       t.push_back(g);
-      cfg.push_back(P.lp ? GEMM_CFG_64x64 : sketch_cfg(g.N));
+      cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Sketch, g.N));
     }
     add_gemm_launches(tw, t, cfg, P.lp, P.sketch);
   }
@@ -404,7 +412,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       if (it.gram_ks > 1) P.gram_split = true;
       P.gram_max = std::max<int64_t>(P.gram_max, it.pb.k * it.pb.k);
       t.push_back(g);
-      cfg.push_back(GEMM_CFG_64x64);
+      cfg.push_back(pick_cfg(P, GemmRole::Gram, g.N));
     }
     add_gemm_launches(tw, t, cfg, false, P.gram);
     // all tasks again, in problem order, for the split-K sums
@@ -434,7 +442,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       g.C = base + it.C; g.ldc = it.pb.k;
       g.ksplit = 1;
       t.push_back(g);
-      cfg.push_back(GEMM_CFG_64x64);
+      cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Project, g.N));
     }
     add_gemm_launches(tw, t, cfg, P.lp, P.project);
   }
@@ -449,7 +457,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       g.C = base + it.Bst; g.ldc = it.pb.k;
       g.ksplit = 1;
       t.push_back(g);
-      cfg.push_back(GEMM_CFG_64x64);
+      cfg.push_back(pick_cfg(P, GemmRole::Solve, g.N));
     }
     add_gemm_launches(tw, t, cfg, false, P.solve);
   }
@@ -490,7 +498,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       g.rowmap = (const int*)(base + it.pos_y);
       g.ksplit = 1;
       t.push_back(g);
-      cfg.push_back(GEMM_CFG_64x64);
+      cfg.push_back(pick_cfg(P, GemmRole::FormL, g.N));
     }
     add_gemm_launches(tw, t, cfg, false, P.forml);
   }
@@ -498,22 +506,13 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
   return RLU_OK;
 }
 
-template <typename T>
-rlu_status_t enqueue_gemms(const std::vector<GemmLaunch>& ls, char* tab, OpA opa, OpB opb,
-                           int which, bool fp16, hipStream_t s) {
+rlu_status_t enqueue_gemms(const std::vector<GemmLaunch>& ls, char* tab, GemmRole role, OpA opa,
+                           bool f32, bool fp16, hipStream_t s) {
   for (const GemmLaunch& L : ls) {
     const GemmTaskDev* t = (const GemmTaskDev*)(tab + L.tasks);
     const int2* map = (const int2*)(tab + L.map);
-    if (L.lp) {
-      HIP_TRY(launch_gemm_lp_grouped(opa, fp16, t, map, L.nwg, s));
-      continue;
-    }
-    switch (which) {
-      case 0: HIP_TRY((launch_gemm_grouped<T, T, T, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
-      case 1: HIP_TRY((launch_gemm_grouped<double, T, T, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
-      case 2: HIP_TRY((launch_gemm_grouped<double, double, double, T>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
-      default: HIP_TRY((launch_gemm_grouped<double, double, double, double>(opa, opb, L.cfg, t, map, L.nwg, s))); break;
-    }
+    if (L.lp) HIP_TRY(launch_gemm_lp_grouped(opa, fp16, t, map, L.nwg, s));
+    else HIP_TRY(launch_gemm_grouped_role(role, f32, L.cfg, t, map, L.nwg, s));
   }
   return RLU_OK;
 }
@@ -546,7 +545,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_SKETCH, s);
-    rlu_status_t st = enqueue_gemms<T>(P.sketch, tab, OpA::Plain, OpB::Plain, 0, P.fp16, s);
+    rlu_status_t st = enqueue_gemms(P.sketch, tab, GemmRole::Sketch, OpA::Plain, P.f32, P.fp16, s);
     if (st != RLU_OK) return st;
   }
   {
@@ -555,7 +554,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_GRAM, s);
-    rlu_status_t st = enqueue_gemms<T>(P.gram, tab, OpA::LvT, OpB::Lv, 3, false, s);
+    rlu_status_t st = enqueue_gemms(P.gram, tab, GemmRole::Gram, OpA::LvT, P.f32, false, s);
     if (st != RLU_OK) return st;
     if (P.gram_split)
       HIP_TRY(launch_splitk_sum_grouped((const GemmTaskDev*)(tab + P.gram_all), P.gram_count,
@@ -567,12 +566,12 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_PROJECT, s);
-    rlu_status_t st = enqueue_gemms<T>(P.project, tab, OpA::LvT, OpB::Plain, 1, P.fp16, s);
+    rlu_status_t st = enqueue_gemms(P.project, tab, GemmRole::Project, OpA::LvT, P.f32, P.fp16, s);
     if (st != RLU_OK) return st;
   }
   {
     PhaseScope ph(h, PH_SOLVE, s);
-    rlu_status_t st = enqueue_gemms<T>(P.solve, tab, OpA::Plain, OpB::Plain, 3, false, s);
+    rlu_status_t st = enqueue_gemms(P.solve, tab, GemmRole::Solve, OpA::Plain, P.f32, false, s);
     if (st != RLU_OK) return st;
   }
   {
@@ -585,7 +584,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_FORM_L, s);
-    rlu_status_t st = enqueue_gemms<T>(P.forml, tab, OpA::Lv, OpB::Plain, 2, false, s);
+    rlu_status_t st = enqueue_gemms(P.forml, tab, GemmRole::FormL, OpA::Lv, P.f32, false, s);
     if (st != RLU_OK) return st;
   }
   return RLU_OK;
@@ -660,9 +659,10 @@ rlu_status_t capture(rlu_handle_s* h, const Plan& P) {
 
 std::vector<char> signature(rlu_handle_s* h, int count, const rlu_problem_t* pbs,
                             const rlu_buffers_t* ios) {
-  std::vector<char> sig(sizeof(int) + sizeof(void*) + sizeof(int) +
+  std::vector<char> sig(sizeof(int) + sizeof(void*) + sizeof(int) + sizeof(h->tile_override) +
                         count * (sizeof(rlu_problem_t) + sizeof(rlu_buffers_t)));
   char* p = sig.data();
+  std::memcpy(p, h->tile_override, sizeof(h->tile_override)); p += sizeof(h->tile_override);
   std::memcpy(p, &count, sizeof(int)); p += sizeof(int);
   std::memcpy(p, &h->bws, sizeof(void*)); p += sizeof(void*);
   std::memcpy(p, &h->cus, sizeof(int)); p += sizeof(int);
@@ -687,6 +687,7 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
   hipStream_t s = (hipStream_t)stream;
 
   Plan P;
+  for (int r = 0; r < 5; ++r) P.tile[r] = h->tile_override[r];
   rlu_status_t st = plan_layout(P, count, pbs, ios);
   if (st != RLU_OK) return st;
   st = build_tables(P, nullptr, h->cus);  // sizes only
@@ -795,3 +796,14 @@ rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t*
 }
 
 }  // namespace rlu_detail
+
+extern "C" rlu_status_t rlu_set_tile(rlu_handle_t h, int32_t product, int32_t cfg) {
+  if (!h || product < 0 || product >= 5) return RLU_ERR_INVALID_ARG;
+  if (cfg != -1 && !gemm_group_cfg_valid(cfg)) return RLU_ERR_INVALID_ARG;
+  h->tile_override[product] = cfg;
+  return RLU_OK;
+}
+
+extern "C" const char* rlu_tile_name(int32_t cfg) {
+  return gemm_group_cfg_valid(cfg) ? gemm_cfg_name(cfg) : nullptr;
+}

@@ -53,6 +53,7 @@ struct rlu_handle_s {
   hipStream_t cap = nullptr;     // capture stream
   hipEvent_t ev_panel = nullptr; // last batched panel launch (eager calls)
   BatchGraph bgraph;
+  int tile_override[5] = {-1, -1, -1, -1, -1};  // rlu_set_tile
 };
 
 namespace rlu_detail {

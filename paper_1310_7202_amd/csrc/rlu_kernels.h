@@ -76,12 +76,17 @@ struct GemmTaskDev {
   void* C; int64_t ldc; const int* rowmap;
   void* partial; int ksplit; int tiles_m, tiles_n;
 };
-// Compiled shapes usable in grouped launches: 0 = 64 x 64, 1 = 64 x 112, 2 = 112 x 64.
-enum { GEMM_CFG_64x64 = 0, GEMM_CFG_64x112 = 1, GEMM_CFG_112x64 = 2 };
+// Compiled tile shapes (index = cfg; gemm_cfg_name gives "BMxBNxBK").
+enum { GEMM_CFG_64x64 = 0, GEMM_CFG_64x112 = 1, GEMM_CFG_112x64 = 2, GEMM_CFG_64x112x32 = 3,
+       GEMM_CFG_112x64x32 = 4, GEMM_CFG_64x64x32 = 6, GEMM_CFG_128x64 = 7,
+       GEMM_CFG_64x128 = 8, GEMM_CFG_COUNT = 11 };
 void gemm_group_tile(int cfg, int* bm, int* bn);
-template <typename TA, typename TB, typename TC, typename TO>
-hipError_t launch_gemm_grouped(OpA opa, OpB opb, int cfg, const GemmTaskDev* tasks,
-                               const int2* map, int nwg, hipStream_t s);
+bool gemm_group_cfg_valid(int cfg);
+const char* gemm_cfg_name(int cfg);
+// The five products of the method as grouped launches.
+enum class GemmRole { Sketch = 0, Gram = 1, Project = 2, Solve = 3, FormL = 4 };
+hipError_t launch_gemm_grouped_role(GemmRole role, bool f32, int cfg, const GemmTaskDev* tasks,
+                                    const int2* map, int nwg, hipStream_t s);
 hipError_t launch_splitk_sum_grouped(const GemmTaskDev* tasks, int count, int64_t max_elems,
                                      hipStream_t s);
 // Grouped low-precision products (64 x 64 tiles, no split-K): opa Plain
@@ -152,6 +157,8 @@ hipError_t launch_spd_inverse_blocked(const SpdTaskDev* tasks, int count, int64_
 // One matrix: the register kernel for k <= 64, else the blocked form with
 // `scratch` (spd_inverse_scratch_elems(k) doubles).
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
+// Tuning override of the diagonal-block kernel shape (0: 1024 threads).
+void spd_force_diag_variant(int v);
 
 // ----- Permutations and factor assembly (finish.hip) ------------------------
 hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);

@@ -132,15 +132,18 @@ constexpr int GB = 64;
 
 __device__ __forceinline__ int blk_size(int k, int J) { return min(GB, k - GB * J); }
 
-// step 1: Di = (S_JJ)^{-1}
-__global__ void __launch_bounds__(1024) gj_diag_kernel(const SpdTaskDev* __restrict__ tasks,
-                                                        SpdTaskDev one, int J) {
+// step 1: Di = (S_JJ)^{-1}, one workgroup of 32 TY threads per matrix
+template <int TY, int NA, int NB>
+__global__ void __launch_bounds__(32 * TY) gj_diag_kernel(const SpdTaskDev* __restrict__ tasks,
+                                                          SpdTaskDev one, int J) {
   const SpdTaskDev t = tasks ? tasks[blockIdx.x] : one;
   if (GB * J >= t.k) return;
   const int bj = blk_size(t.k, J);
   const double* src = t.S + (int64_t)GB * J * (t.k + 1);
-  spd_inverse_body<32, 2, 2>(src, t.k, t.scratch, GB, bj);
+  spd_inverse_body<TY, NA, NB>(src, t.k, t.scratch, GB, bj);
 }
+
+int g_diag_variant = 0;
 
 // step 2: R = Di S_J. (64 x k) and C = S_.J (k x 64); blockIdx.x = column
 // tile of 64, blockIdx.y = matrix
@@ -240,7 +243,12 @@ hipError_t blocked_steps(const SpdTaskDev* tasks, SpdTaskDev one, int count, int
                          hipStream_t s) {
   const int nb = (int)((kmax + GB - 1) / GB);
   for (int J = 0; J < nb; ++J) {
-    hipLaunchKernelGGL(gj_diag_kernel, dim3((unsigned)count), dim3(1024), 0, s, tasks, one, J);
+    switch (g_diag_variant) {
+      case 1: hipLaunchKernelGGL((gj_diag_kernel<8, 8, 2>), dim3((unsigned)count), dim3(256), 0, s, tasks, one, J); break;
+      case 2: hipLaunchKernelGGL((gj_diag_kernel<4, 16, 2>), dim3((unsigned)count), dim3(128), 0, s, tasks, one, J); break;
+      case 3: hipLaunchKernelGGL((gj_diag_kernel<2, 32, 2>), dim3((unsigned)count), dim3(64), 0, s, tasks, one, J); break;
+      default: hipLaunchKernelGGL((gj_diag_kernel<32, 2, 2>), dim3((unsigned)count), dim3(1024), 0, s, tasks, one, J); break;
+    }
     hipLaunchKernelGGL(gj_panel_kernel, dim3((unsigned)nb, (unsigned)count), dim3(256), 0, s,
                        tasks, one, J);
     hipLaunchKernelGGL(gj_update_kernel, dim3((unsigned)(nb * nb), (unsigned)count), dim3(256),
@@ -249,6 +257,8 @@ hipError_t blocked_steps(const SpdTaskDev* tasks, SpdTaskDev one, int count, int
   return hipGetLastError();
 }
 }  // namespace
+
+void spd_force_diag_variant(int v) { g_diag_variant = v; }
 
 hipError_t launch_spd_inverse_blocked(const SpdTaskDev* tasks, int count, int64_t kmax,
                                       hipStream_t s) {
