@@ -21,6 +21,9 @@
 #include "rlu_device.h"
 #include "rlu_kernels.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace rlu {
 namespace {
 
@@ -212,6 +215,229 @@ gemm_lp_grouped_kernel(const GemmTaskDev* __restrict__ tasks, const int2* __rest
       nullptr, bx, by, 0);
 }
 
+// ---------------------------------------------------------------------------
+// Large-tile form for long products (K >= 1024, thousands of rows or
+// columns): 128-row tiles, vectorized global loads (4 consecutive elements
+// per load along the operand's contiguous dimension), the 16-bit values
+// written to LDS 4 at a time (8 bytes), so the per-element LDS stores and
+// scalar loads of the small-tile form no longer bound the kernel.
+//   * A of Step 2 (FP32, M contiguous): a thread loads a 4 x 4 block (4 rows
+//     at 4 consecutive k, four 16-byte loads) and writes each row's 4 k.
+//   * Lv^T of Step 5 (FP64 Y, K contiguous): 4 consecutive k of one output
+//     row (two 16-byte loads), masked by the rows' choosing steps, split
+//     into hi + lo.
+//   * B operands (FP32, K contiguous): 4 consecutive k of one column.
+// Vector loads need 16-byte aligned leading dimensions; the launcher falls
+// back to the small-tile form otherwise.
+// ---------------------------------------------------------------------------
+template <typename LP, typename TA, OpA OA, bool SPLIT, int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
+                const int* __restrict__ astep, const float* __restrict__ B, int64_t ldb,
+                double* __restrict__ C, int64_t ldc, int ksplit, double* __restrict__ partial,
+                int tm, int tn, int nfast) {
+  constexpr int NT = 64 * WM * WN;
+  constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
+  constexpr int NS = SPLIT ? 2 : 1;
+  // loads per thread per K slice
+  constexpr int ACH = (OA == OpA::Plain) ? (BM * LBK / 16) / NT : (BM * LBK / 4) / NT;
+  constexpr int BCH = (BN * LBK / 4) / NT;
+  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
+  static_assert(ACH * NT == ((OA == OpA::Plain) ? BM * LBK / 16 : BM * LBK / 4), "A chunks");
+  static_assert(BCH * NT == BN * LBK / 4, "B chunks");
+  typedef typename LpMfma<LP>::vec vec;
+  typedef LP lp4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) LP As[2][NS][BM * LLD];
+  __shared__ __attribute__((aligned(16))) LP Bs[2][BN * LLD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WM, wn = wave / WM;
+  const int t = xcd_chunked_lp((int)blockIdx.x, (int)gridDim.x);
+  int bx, by, bz;
+  if (nfast) {
+    by = t % tn; const int rest = t / tn; bx = rest % tm; bz = rest / tm;
+  } else {
+    bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
+  }
+  const int64_t m0 = (int64_t)bx * BM, n0 = (int64_t)by * BN;
+  const int64_t kchunk = ((K + ksplit - 1) / ksplit + LBK - 1) / LBK * LBK;
+  const int64_t kbeg = (int64_t)bz * kchunk;
+  const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+
+  // prefetch registers: A as FP32 values (Plain) or FP64 (LvT)
+  typedef typename std::conditional<OA == OpA::Plain, float, double>::type RA;
+  RA ra[ACH][(OA == OpA::Plain) ? 16 : 4];
+  float rb[BCH][4];
+
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q) {
+      const int e = tid + q * NT;
+      if (OA == OpA::Plain) {
+        // 4 x 4 block: rows 4 (e % (BM/4)) .., k 4 (e / (BM/4)) ..
+        const int i4 = 4 * (e % (BM / 4)), k4 = 4 * (e / (BM / 4));
+        const int64_t gi = m0 + i4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t gk = k0 + k4 + c;
+          if (gk < kend && gi + 3 < M) {
+            const float4 v = *(const float4*)&A[gi + gk * lda];
+            ra[q][4 * c + 0] = v.x; ra[q][4 * c + 1] = v.y;
+            ra[q][4 * c + 2] = v.z; ra[q][4 * c + 3] = v.w;
+          } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              ra[q][4 * c + r] = (gk < kend && gi + r < M) ? (float)A[gi + r + gk * lda] : 0.f;
+          }
+        }
+      } else {
+        // 4 consecutive k of output row i
+        const int kk4 = 4 * (e % (LBK / 4)), i = e / (LBK / 4);
+        const int64_t gi = m0 + i, gk = k0 + kk4;
+        if (gi < M && gk + 3 < kend) {
+          const double2 v0 = *(const double2*)&A[gk + gi * lda];
+          const double2 v1 = *(const double2*)&A[gk + 2 + gi * lda];
+          const int4 s4 = *(const int4*)&astep[gk];
+          ra[q][0] = lv_value<double>(v0.x, (int)gi, s4.x);
+          ra[q][1] = lv_value<double>(v0.y, (int)gi, s4.y);
+          ra[q][2] = lv_value<double>(v1.x, (int)gi, s4.z);
+          ra[q][3] = lv_value<double>(v1.y, (int)gi, s4.w);
+        } else {
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            ra[q][c] = (gi < M && gk + c < kend)
+                           ? lv_value<double>((double)A[gk + c + gi * lda], (int)gi, astep[gk + c])
+                           : 0.0;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q) {
+      const int e = tid + q * NT;
+      const int kk4 = 4 * (e % (LBK / 4)), j = e / (LBK / 4);
+      const int64_t gj = n0 + j, gk = k0 + kk4;
+      if (gj < N && gk + 3 < kend) {
+        const float4 v = *(const float4*)&B[gk + gj * ldb];
+        rb[q][0] = v.x; rb[q][1] = v.y; rb[q][2] = v.z; rb[q][3] = v.w;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) rb[q][c] = (gj < N && gk + c < kend) ? B[gk + c + gj * ldb] : 0.f;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < ACH; ++q) {
+      const int e = tid + q * NT;
+      if (OA == OpA::Plain) {
+        const int i4 = 4 * (e % (BM / 4)), k4 = 4 * (e / (BM / 4));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          lp4 h;
+          h.x = (LP)ra[q][r]; h.y = (LP)ra[q][4 + r]; h.z = (LP)ra[q][8 + r]; h.w = (LP)ra[q][12 + r];
+          *(lp4*)&As[buf][0][(i4 + r) * LLD + k4] = h;
+        }
+      } else {
+        const int kk4 = 4 * (e % (LBK / 4)), i = e / (LBK / 4);
+        lp4 h, l;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const float x = (float)ra[q][c];
+          const LP hi = (LP)x;
+          h[c] = hi;
+          l[c] = (LP)(float)(ra[q][c] - (double)(float)hi);
+        }
+        *(lp4*)&As[buf][0][i * LLD + kk4] = h;
+        if (SPLIT) *(lp4*)&As[buf][NS - 1][i * LLD + kk4] = l;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < BCH; ++q) {
+      const int e = tid + q * NT;
+      const int kk4 = 4 * (e % (LBK / 4)), j = e / (LBK / 4);
+      lp4 h;
+      h.x = (LP)rb[q][0]; h.y = (LP)rb[q][1]; h.z = (LP)rb[q][2]; h.w = (LP)rb[q][3];
+      *(lp4*)&Bs[buf][j * LLD + kk4] = h;
+    }
+  };
+
+  f4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+
+  int buf = 0;
+  if (kbeg < kend) {
+    load(kbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t kt = kbeg; kt < kend; kt += LBK) {
+    const bool more = kt + LBK < kend;
+    if (more) load(kt + LBK);
+    const int kof = 8 * (lane >> 4);
+    vec af[NS][TM], bf[TN];
+#pragma unroll
+    for (int a = 0; a < TM; ++a) {
+      const int row = wm * WTM + a * 16 + (lane & 15);
+#pragma unroll
+      for (int s2 = 0; s2 < NS; ++s2) af[s2][a] = *(const vec*)&As[buf][s2][row * LLD + kof];
+    }
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int col = wn * WTN + b * 16 + (lane & 15);
+      bf[b] = *(const vec*)&Bs[buf][col * LLD + kof];
+    }
+#pragma unroll
+    for (int a = 0; a < TM; ++a)
+#pragma unroll
+      for (int b = 0; b < TN; ++b) {
+        acc[a][b] = LpMfma<LP>::mma(af[0][a], bf[b], acc[a][b]);
+        if (SPLIT) acc[a][b] = LpMfma<LP>::mma(af[NS - 1][a], bf[b], acc[a][b]);
+      }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t gi = m0 + wm * WTM + a * 16 + 4 * (lane >> 4) + v;
+        const int64_t gj = n0 + wn * WTN + b * 16 + (lane & 15);
+        if (gi < M && gj < N) {
+          const double val = (double)acc[a][b][v];
+          if (ksplit > 1) partial[(int64_t)bz * M * N + gi + gj * M] = val;
+          else C[gi + gj * ldc] = val;
+        }
+      }
+}
+
+template <typename LP, typename TA, OpA OA, bool SPLIT, int BM, int BN, int WM, int WN>
+hipError_t launch_lp2(const GemmDesc& d, hipStream_t s) {
+  const int tm = (int)((d.M + BM - 1) / BM), tn = (int)((d.N + BN - 1) / BN);
+  const int64_t tiles = (int64_t)tm * tn;
+  int ks = 1;
+  if (d.partial)
+    while (tiles * ks < 512 && d.K / (ks * 2) >= 2048 && ks < 16) ks *= 2;
+  if (d.ksplit_out) *d.ksplit_out = ks;
+  const int nfast = d.M > d.N ? 1 : 0;
+  hipLaunchKernelGGL((gemm_lp2_kernel<LP, TA, OA, SPLIT, BM, BN, WM, WN>),
+                     dim3((unsigned)(tiles * ks)), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K,
+                     (const TA*)d.A, d.lda, d.astep, (const float*)d.B, d.ldb, (double*)d.C,
+                     d.ldc, ks, (double*)d.partial, tm, tn, nfast);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || ks == 1 || d.no_sum) return e;
+  return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
+                               nullptr, s);
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 template <typename LP, typename TA, typename TB, OpA OA, bool SPLIT>
 hipError_t launch_lp(const GemmDesc& d, hipStream_t s) {
   constexpr int BM = 64, BN = 64, WM = 2, WN = 2;
@@ -238,12 +464,29 @@ size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K) {
   const int64_t tiles = ((M + 63) / 64) * ((N + 63) / 64);
   int ks = 1;
   while (tiles * ks < 1024 && K / (ks * 2) >= 1024 && ks < 32) ks *= 2;
+  // the large-tile form: 128-row tiles, fewer tiles, its own split rule
+  const int64_t t2 = std::min(((M + 127) / 128) * ((N + 191) / 192),
+                              ((M + 127) / 128) * ((N + 127) / 128));
+  int ks2 = 1;
+  while (t2 * ks2 < 512 && K / (ks2 * 2) >= 2048 && ks2 < 16) ks2 *= 2;
+  ks = std::max(ks, ks2);
   return ks > 1 ? (size_t)ks * (size_t)M * (size_t)N : 0;
 }
 
 hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   if (d.opb != OpB::Plain) return hipErrorInvalidValue;
+  const bool bvec = d.ldb % 4 == 0 && aligned16(d.B);
+  if (d.opa == OpA::Plain && d.K >= 1024 && d.M >= 1024 && bvec && d.lda % 4 == 0 &&
+      aligned16(d.A)) {
+    return fp16 ? launch_lp2<_Float16, float, OpA::Plain, false, 128, 192, 4, 1>(d, s)
+                : launch_lp2<__bf16, float, OpA::Plain, false, 128, 192, 4, 1>(d, s);
+  }
+  if (d.opa == OpA::LvT && d.K >= 1024 && d.N >= 1024 && bvec && d.lda % 2 == 0 &&
+      aligned16(d.A) && aligned16(d.astep)) {
+    return fp16 ? launch_lp2<_Float16, double, OpA::LvT, true, 128, 128, 2, 2>(d, s)
+                : launch_lp2<__bf16, double, OpA::LvT, true, 128, 128, 2, 2>(d, s);
+  }
   if (d.opa == OpA::Plain) {  // Y = A G: FP32 A and G
     return fp16 ? launch_lp<_Float16, float, float, OpA::Plain, false>(d, s)
                 : launch_lp<__bf16, float, float, OpA::Plain, false>(d, s);
