@@ -14,26 +14,30 @@
 //     lowest-position tie break) and the step that chose it.
 //   * step j: wave 0 brings column j up to date, finds the workgroup's best
 //     candidate (largest magnitude, lowest current position on ties) and
-//     publishes it in an exchange record: its value in column j, its
-//     multiplier of step j-1 and its row from column j+1 on *one update
-//     behind* (through step j-2).  Every workgroup reads all records, selects
-//     the same winner and completes the winner's row itself,
+//     publishes its key (magnitude, position, row) and a short header: its
+//     value in column j, its multiplier of step j-1 and its value in column
+//     j+1 *one update behind* (through step j-2); the bulk waves publish the
+//     rest of the candidate's row, also one update behind.  Every workgroup
+//     polls the dense array of keys, selects the same winner, reads only the
+//     winner's header and completes the winner's row itself,
 //         U(j, c) = row(c) - l(j-1) U(j-1, c),
 //     with the same fused multiply-add the winner's own workgroup applies to
 //     its copy, so all copies agree bitwise.  Publishing the row one update
-//     behind lets waves 1-3 apply the bulk rank-one update of step j-1 while
+//     behind lets waves 1-7 apply the bulk rank-one update of step j-1 while
 //     wave 0 waits on the exchange: only the exchange latency and
-//     O(R/64 + ncols/64) work per lane sit on the critical path.
+//     O(R/64 + nwg/64) work per lane sit on the critical path.
 //   * exchange protocol: every 64-bit word of a record carries the step tag
 //     in its upper half and 32 bits of payload in its lower half (a double
 //     takes two words).  Words are written and read with device-coherent
 //     (agent-scope) relaxed atomic accesses, whose 64-bit single-copy
-//     atomicity is all the protocol relies on: a reader accepts a record only
-//     when every word it needs shows the current tag, so no store ordering,
-//     fence or cache maintenance is needed and the writer never waits.
-//     Records alternate between two buffers by step parity, which is enough
-//     because a workgroup cannot publish step j+2 before every workgroup has
-//     finished reading step j.
+//     atomicity is all the protocol relies on: a reader accepts a key, header
+//     or row entry only when every word it needs shows the current tag, so no
+//     store ordering, fence or cache maintenance is needed and the writer
+//     never waits.  Buffers rotate by step mod 3: a workgroup publishes step
+//     j+3 only after the exchange of step j+2, which needs every workgroup's
+//     step j+2 key, which each publishes only after it finished reading the
+//     buffers of step j (keys and header in its exchange, the winner's row in
+//     its bulk update of step j+1).
 //   * every wait is bounded by a wall-clock limit; on expiry the kernel sets
 //     a failure flag and all workgroups leave.
 #include "rlu_device.h"
@@ -47,12 +51,19 @@ namespace {
 constexpr int kThreads = 512;
 constexpr int kNone = INT_MAX;
 
-// Record: 10 header words, then 2 words per column (entries from column j+2
-// on are written at step j).  Header words: [0,1] candidate magnitude,
-// [2] current position, [3] original row (or -1), [4,5] value in column j,
-// [6,7] multiplier of step j-1, [8,9] value in column j+1 (one update
-// behind, like the row).
-constexpr int kHdrWords = 10;
+// Exchange buffer of a step: first a dense key area, 4 words per workgroup
+// ([0,1] candidate magnitude, [2] current position, [3] original row or -1),
+// which every workgroup polls; then one record per workgroup: 6 header
+// words ([0,1] value in column j, [2,3] multiplier of step j-1, [4,5] value
+// in column j+1, one update behind like the row), read for the winner only,
+// and 2 words per column of the candidate's row (entries from column j+2 on,
+// written at step j by the bulk waves).
+constexpr int kKeyWords = 4;
+constexpr int kHdrWords = 6;
+
+__host__ __device__ __forceinline__ int64_t key_area_bytes(int nwg) {
+  return (8 * (int64_t)kKeyWords * nwg + 127) / 128 * 128;
+}
 
 __device__ __forceinline__ void put32(unsigned long long* w, unsigned tag, unsigned v) {
   st_agent(w, ((unsigned long long)tag << 32) | v);
@@ -137,13 +148,15 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // Step j, with U(i, .) the U row of step i (the winner's row through step
 // i-1) kept in a two-slot ring urow[i & 1]:
 //   wave 0      U(j-1, j) from the step j-1 header; column j brought up to
-//               date; local candidate; header + row published        | B1 |
-//               wait for all headers, select the winner, bookkeeping,
-//               multipliers of step j                                 | B0 |
-//   waves 1-7   fetch the step j-1 winner's row, complete U(j-1, c)
-//               for c > j                                             | B1 |
-//               rank-one update of step j-1 on columns c > j          | B0 |
-// so the only device round trip on wave 0's path is the header exchange.
+//               date; local candidate; header and key published       | B1 |
+//               wait for all keys, select the winner, read its header,
+//               bookkeeping, multipliers of step j                    | B0 |
+//   waves 1-7   issue the loads of the step j-1 winner's row          | B1 |
+//               publish their columns of the local candidate's row,
+//               complete U(j-1, c) for their own columns c > j, then
+//               the rank-one update of step j-1 on those columns      | B0 |
+// so the only device round trips on wave 0's path are the key exchange and
+// one header read, and the row traffic overlaps them.
 template <int RPL>
 __device__ __forceinline__ void panel_body(
     double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R, int nwg,
@@ -216,6 +229,7 @@ __device__ __forceinline__ void panel_body(
   int info = 0;
   __syncthreads();
 
+  unsigned long long pre_lo = 0, pre_hi = 0;  // bulk waves: prefetched body words
   for (int j = 0; j < ncols; ++j) {
     const int sj = j & 1, sp = sj ^ 1;
     double* Uj = urow + sj * ncols;   // U(j, .); until overwritten it still holds U(j-2, .)
@@ -223,7 +237,12 @@ __device__ __forceinline__ void panel_body(
     const bool upd1 = j >= 1 && sh_piv[sp] != 0.0;  // step j-1 updated the trailing part
     const bool upd2 = j >= 2 && sh_piv[sj] != 0.0;  // step j-2 did
     const unsigned tag = (unsigned)(j + 1);
-    char* base = xch + (int64_t)sj * nwg * rec_stride;
+    // records of step j live in buffer j mod 3 (see the header comment)
+    const int bj = j % 3, bprev = (j + 2) % 3;
+    const int64_t keyb = key_area_bytes(nwg), bufb = keyb + (int64_t)nwg * rec_stride;
+    char* base = xch + (int64_t)bj * bufb;            // keys of step j
+    char* recs = base + keyb;                         // records of step j
+    const char* precs = xch + (int64_t)bprev * bufb + keyb;  // records of step j-1
 
     if (wave == 0) {
       // ---- (1) column j up to date, local candidate, publish -----------------
@@ -258,60 +277,39 @@ __device__ __forceinline__ void panel_body(
       const double lm = upd1 ? lane_bcast(lmr, r >= 0 ? (r & 63) : 0) : 0.0;
       const double cpiv = r >= 0 ? Ts[(int64_t)j * R + r] : 0.0;
       const double cv1 = (r >= 0 && j + 1 < ncols) ? Ts[(int64_t)(j + 1) * R + r] : 0.0;
+      // (the candidate's row from column j+2 on is published by the bulk
+      // waves after B1, before they update it)
+      if (lane == 0) sh_cr = r;
       if (nwg > 1) {
-        unsigned long long* rec = (unsigned long long*)(base + (int64_t)w * rec_stride);
-        unsigned long long* body = rec + kHdrWords;
-        if (r >= 0)
-          for (int c = j + 2 + lane; c < ncols; c += 64)
-            put64(body + 2 * c, tag, dbits(Ts[(int64_t)c * R + r]));
         if (lane == 0) {
-          put64(rec + 0, tag, dbits(a));
-          put32(rec + 2, tag, (unsigned)p);
-          put32(rec + 3, tag, (unsigned)(r >= 0 ? row0 + r : -1));
-          put64(rec + 4, tag, dbits(cpiv));
-          put64(rec + 6, tag, dbits(lm));
-          put64(rec + 8, tag, dbits(cv1));
+          unsigned long long* rec = (unsigned long long*)(recs + (int64_t)w * rec_stride);
+          unsigned long long* key = (unsigned long long*)base + kKeyWords * w;
+          put64(rec + 0, tag, dbits(cpiv));
+          put64(rec + 2, tag, dbits(lm));
+          put64(rec + 4, tag, dbits(cv1));
+          put64(key + 0, tag, dbits(a));
+          put32(key + 2, tag, (unsigned)p);
+          put32(key + 3, tag, (unsigned)(r >= 0 ? row0 + r : -1));
         }
       } else {
-        if (r >= 0)
-          for (int c = j + 2 + lane; c < ncols; c += 64) lbody[sj * ncols + c] = Ts[(int64_t)c * R + r];
         if (lane == 0) {
-          sh_cr = r; sh_cp = p; sh_cpiv = cpiv; sh_clm = lm; sh_cv1 = cv1;
+          sh_cp = p; sh_cpiv = cpiv; sh_clm = lm; sh_cv1 = cv1;
           if (r < 0) { st_agent_i(fail, 1); sh_stop = 1; }  // cannot happen for ncols <= nrows
         }
       }
-    } else if (upd1) {
-      // ---- (2a) waves 1-7: U(j-1, c) for c > j from the step j-1 winner's row --
-      const int t = tid - 64;
-      const double lmw = sh_lm[sp];
-      const unsigned long long* pbody = nullptr;
-      if (nwg > 1)
-        pbody = (const unsigned long long*)(xch + ((int64_t)sp * nwg + sh_bw[sp]) * rec_stride) +
-                kHdrWords;
-      bool stop = false;
-      for (int c = j + 1 + t; c < ncols; c += kThreads - 64) {
-        double b;
-        if (nwg > 1) {
-          unsigned long long lo, hi;
-          while (true) {
-            lo = ld_agent(pbody + 2 * c);
-            hi = ld_agent(pbody + 2 * c + 1);
-            if (tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j)) break;
-            if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
-              stop = true;
-              break;
-            }
-          }
-          if (stop) break;
-          b = bitsd(join64(lo, hi));
-        } else {
-          b = lbody[sp * ncols + c];
-        }
-        Up[c] = upd2 ? __fma_rn(-lmw, Uj[c], b) : b;
+    } else if (upd1 && nwg > 1) {
+      // ---- (2a) waves 1-7: start fetching the step j-1 winner's row ---------
+      // (columns c > j, one per lane; the loads complete while wave 0
+      // publishes, and are checked after B1)
+      const int c = j + 1 + (wave - 1) + (kThreads / 64 - 1) * lane;
+      if (c < ncols) {
+        const unsigned long long* pbody =
+            (const unsigned long long*)(precs + (int64_t)sh_bw[sp] * rec_stride) + kHdrWords;
+        pre_lo = ld_agent(pbody + 2 * c);
+        pre_hi = ld_agent(pbody + 2 * c + 1);
       }
-      if (stop) { st_agent_i(fail, 1); sh_stop = 1; }
     }
-    lds_barrier();  // B1: candidate published; U(j-1, .) complete
+    lds_barrier();  // B1: candidate published (the bulk update may now touch its row)
     if (sh_stop) break;
 
     if (wave == 0) {
@@ -320,37 +318,34 @@ __device__ __forceinline__ void panel_body(
       double piv = 0.0, wlm = 0.0, wv1 = 0.0;
       bool stop = false;
       if (nwg > 1) {
-        // every lane owns the records lane, lane + 64, ... (nwg <= 256) and
-        // reads whole headers, so the winner's fields need no second trip
+        // every lane polls the keys of workgroups lane, lane + 64, ...
+        // (nwg <= 256), then all read the winner's header words
         const int nq = (nwg + 63) / 64;
-        double qa[4], qpiv[4], qlm[4], qv1[4];
+        double qa[4];
         int qp[4], qrow[4];
         unsigned seen = 0, need = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          qa[q] = -1.0; qp[q] = INT_MAX; qrow[q] = -1; qpiv[q] = 0.0; qlm[q] = 0.0; qv1[q] = 0.0;
+          qa[q] = -1.0; qp[q] = INT_MAX; qrow[q] = -1;
           if (q < nq && lane + 64 * q < nwg) need |= 1u << q;
         }
         while (true) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             if ((need >> q & 1u) && !(seen >> q & 1u)) {
-              const unsigned long long* h =
-                  (const unsigned long long*)(base + (int64_t)(lane + 64 * q) * rec_stride);
-              unsigned long long x[kHdrWords];
+              const unsigned long long* k =
+                  (const unsigned long long*)base + kKeyWords * (lane + 64 * q);
+              unsigned long long x[kKeyWords];
 #pragma unroll
-              for (int t = 0; t < kHdrWords; ++t) x[t] = ld_agent(h + t);
+              for (int t = 0; t < kKeyWords; ++t) x[t] = ld_agent(k + t);
               bool ok = true;
 #pragma unroll
-              for (int t = 0; t < kHdrWords; ++t) ok = ok && tagged(x[t], tag);
+              for (int t = 0; t < kKeyWords; ++t) ok = ok && tagged(x[t], tag);
               if (ok) {
                 seen |= 1u << q;
                 qa[q] = bitsd(join64(x[0], x[1]));
                 qp[q] = (int)(unsigned)x[2];
                 qrow[q] = (int)(unsigned)x[3];
-                qpiv[q] = bitsd(join64(x[4], x[5]));
-                qlm[q] = bitsd(join64(x[6], x[7]));
-                qv1[q] = bitsd(join64(x[8], x[9]));
               }
             }
           }
@@ -371,18 +366,31 @@ __device__ __forceinline__ void panel_body(
           if (bw < 0 || ba < 0.0) {
             stop = true;  // no candidate anywhere: cannot happen for ncols <= nrows
           } else {
-            // the winner's header fields live in lane bw % 64, slot bw / 64
-            int hrow = -1; double hpiv = 0.0, hlm = 0.0, hv1 = 0.0;
+            int hrow = -1;
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              if (bw == lane + 64 * q) { hrow = qrow[q]; hpiv = qpiv[q]; hlm = qlm[q]; hv1 = qv1[q]; }
-            const int src = bw & 63;
-            win_row = __builtin_amdgcn_readlane(hrow, src);
-            piv = lane_bcast(hpiv, src);
-            wlm = lane_bcast(hlm, src);
-            wv1 = lane_bcast(hv1, src);
+              if (bw == lane + 64 * q) hrow = qrow[q];
+            win_row = __builtin_amdgcn_readlane(hrow, bw & 63);
             win_pos = bp;
             if (win_row < 0) stop = true;
+            // the winner's header (same words in every lane)
+            const unsigned long long* h =
+                (const unsigned long long*)(recs + (int64_t)bw * rec_stride);
+            unsigned long long x[kHdrWords];
+            while (!stop) {
+              bool ok = true;
+#pragma unroll
+              for (int t = 0; t < kHdrWords; ++t) x[t] = ld_agent(h + t);
+#pragma unroll
+              for (int t = 0; t < kHdrWords; ++t) ok = ok && tagged(x[t], tag);
+              if (__all(ok)) break;
+              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) stop = true;
+            }
+            if (!stop) {
+              piv = bitsd(join64(x[0], x[1]));
+              wlm = bitsd(join64(x[2], x[3]));
+              wv1 = bitsd(join64(x[4], x[5]));
+            }
           }
         }
       } else {
@@ -429,8 +437,71 @@ __device__ __forceinline__ void panel_body(
         }
         if (piv == 0.0 && info == 0) info = step0 + j + 1;
       }
-    } else if (upd1) {
-      // ---- (2b) waves 1-7: rank-one update of step j-1 on columns j+1.. --------
+    } else {
+      // ---- (2b) waves 1-7, first: publish this wave's columns c >= j+2 of
+      // the workgroup's candidate row (through step j-2: before the update
+      // of step j-1 below touches them)
+      const int rc = sh_cr;
+      if (rc >= 0) {
+        constexpr int kBWp = kThreads / 64 - 1;
+        unsigned long long* body =
+            (unsigned long long*)(recs + (int64_t)w * rec_stride) + kHdrWords;
+        for (int c = j + 1 + (wave - 1) + kBWp * lane; c < ncols; c += kBWp * 64) {
+          if (c < j + 2) continue;
+          const double v = Ts[(int64_t)c * R + rc];
+          if (nwg > 1) put64(body + 2 * c, tag, dbits(v));
+          else lbody[sj * ncols + c] = v;
+        }
+      }
+    }
+    if (wave != 0 && upd1) {
+      // ---- (2b) waves 1-7: U(j-1, c) for this wave's columns, then the
+      // rank-one update of step j-1 on them.  Wave w owns the columns
+      // c = j + w + 7 t (t = 0, 1, ...): it completes U(j-1, c) from the
+      // winner's row, one update behind, with the same fused multiply-add
+      // the winner's own workgroup applies, then updates those columns.
+      constexpr int kBW = kThreads / 64 - 1;
+      {
+        const double lmw = sh_lm[sp];
+        bool stop = false;
+        const unsigned long long* pbody =
+            nwg > 1 ? (const unsigned long long*)(precs + (int64_t)sh_bw[sp] * rec_stride) +
+                          kHdrWords
+                    : nullptr;
+        for (int c = j + 1 + (wave - 1) + kBW * lane, first = 1; c < ncols;
+             c += kBW * 64, first = 0) {
+          double b;
+          if (nwg > 1) {
+            unsigned long long lo = pre_lo, hi = pre_hi;
+            if (!first) {
+              lo = ld_agent(pbody + 2 * c);
+              hi = ld_agent(pbody + 2 * c + 1);
+            }
+            while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
+              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+                stop = true;
+                break;
+              }
+              lo = ld_agent(pbody + 2 * c);
+              hi = ld_agent(pbody + 2 * c + 1);
+            }
+            if (stop) break;
+            b = bitsd(join64(lo, hi));
+          } else {
+            b = lbody[sp * ncols + c];
+          }
+          Up[c] = upd2 ? __fma_rn(-lmw, Uj[c], b) : b;
+        }
+        if (__any(stop)) {
+          if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
+        }
+      }
+      // this wave's U values are read back by all its lanes: keep the LDS
+      // writes ahead of the reads
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      __builtin_amdgcn_s_waitcnt(0xC07F);
+      __builtin_amdgcn_wave_barrier();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       // Rows still active after step j-1 (step_s > j-1).  A row being chosen
       // at step j right now has step_s kNone or j: included either way, as it
       // must be (its U row is its values through step j-1).
@@ -578,7 +649,7 @@ PanelPlan panel_plan(int nrows, int ncols, int device_cus, int /*max_wg_per_cu_h
   p.rows_per_wg = R;
   p.nwg = nwg;
   p.lds_bytes = lds_for(R, ncols);
-  p.xch_bytes = (size_t)(2 * (int64_t)nwg * rec_stride_for(ncols));
+  p.xch_bytes = panel_xch_bytes(nwg, ncols);
   p.ok = true;
   return p;
 }
@@ -614,6 +685,10 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
 }
 
 int64_t panel_rec_stride(int ncols) { return rec_stride_for(ncols); }
+
+size_t panel_xch_bytes(int nwg, int ncols) {
+  return (size_t)(3 * (key_area_bytes(nwg) + (int64_t)nwg * rec_stride_for(ncols)));
+}
 
 size_t panel_lds_bytes(int R, int ncols) { return lds_for(R, ncols); }
 

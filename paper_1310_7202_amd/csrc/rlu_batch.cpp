@@ -328,8 +328,8 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     it.nwg_b = (int)((pb.n + Rb - 1) / Rb);
     it.R_b = (int)((pb.n + it.nwg_b - 1) / it.nwg_b);
     take(it.flags, 64);
-    take(it.xy, it.nwg_y > 1 ? 2 * (size_t)it.nwg_y * panel_rec_stride((int)pb.l) : 0);
-    take(it.xb, it.nwg_b > 1 ? 2 * (size_t)it.nwg_b * panel_rec_stride((int)pb.k) : 0);
+    take(it.xy, it.nwg_y > 1 ? panel_xch_bytes(it.nwg_y, (int)pb.l) : 0);
+    take(it.xb, it.nwg_b > 1 ? panel_xch_bytes(it.nwg_b, (int)pb.k) : 0);
   }
   P.zero_bytes = off;
   const size_t d = sizeof(double);

@@ -130,6 +130,8 @@ struct PanelTaskDev {
   char* xch; int64_t rec_stride;
 };
 int64_t panel_rec_stride(int ncols);
+// exchange area of a panel launch with nwg workgroups (three step buffers)
+size_t panel_xch_bytes(int nwg, int ncols);
 size_t panel_lds_bytes(int R, int ncols);
 // Workgroups of the batched panel kernel the device holds at once (0 on error).
 int panel_batched_slots(int max_R, size_t lds_bytes, int cus);
