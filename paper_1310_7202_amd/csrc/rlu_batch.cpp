@@ -15,8 +15,9 @@
 //     device holds at once (chains of equal length together, members of a
 //     gang on one XCD where it fits), and each workgroup runs its members of
 //     successive rounds back to back.
-//   * The Gram inverses take one workgroup per problem; the assembly of p,
-//     q, U, L_b and info is one launch.
+//   * The Gram inverses take one workgroup per 64 x 64 tile of every
+//     problem and one launch per 64 pivots; the assembly of p, q, U, L_b
+//     and info is one launch.
 // The launch sequence is captured once into a HIP graph and replayed while
 // the same problems and buffers come back; the task tables live in the
 // handle's batch workspace and are uploaded only when the batch changes.

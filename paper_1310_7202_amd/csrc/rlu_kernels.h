@@ -143,24 +143,18 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
                                    long long timeout_ticks, hipStream_t s);
 
 // ----- Inverse of the k x k Gram matrix (spd_inverse.hip) ------------------
-// Single workgroup, S in registers (k <= 208).
-hipError_t launch_spd_inverse(double* S, int64_t k, hipStream_t s);  // in place
+// The blocked symmetric sweep: one launch per 64 pivots (plus a copy when
+// the block count is odd, k > 64); the scratch of a matrix holds
+// spd_inverse_scratch_elems(k) doubles (unused for k <= 64).
 constexpr int64_t kSpdMaxK = 1024;
 bool spd_inverse_supported(int64_t k);
-// scratch of the blocked form: spd_inverse_scratch_elems(k) doubles
 struct SpdTaskDev { double* S; int k; double* scratch; };
 size_t spd_inverse_scratch_elems(int64_t k);
-// Batch (one entry per matrix, tasks in device memory): one workgroup per
-// matrix when every k <= 64, else the blocked form (3 launches per 64 pivots).
+// Batch: one entry per matrix, tasks in device memory.
 hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_t kmax,
                                      hipStream_t s);
-hipError_t launch_spd_inverse_blocked(const SpdTaskDev* tasks, int count, int64_t kmax,
-                                      hipStream_t s);
-// One matrix: the register kernel for k <= 64, else the blocked form with
-// `scratch` (spd_inverse_scratch_elems(k) doubles).
+// One matrix.
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
-// Tuning override of the diagonal-block kernel shape (0: 1024 threads).
-void spd_force_diag_variant(int v);
 
 // ----- Permutations and factor assembly (finish.hip) ------------------------
 hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
