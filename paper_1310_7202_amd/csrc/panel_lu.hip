@@ -102,37 +102,47 @@ __device__ __forceinline__ bool better(double a2, int p2, double a, int p) {
   return a2 > a || (a2 == a && p2 < p);
 }
 
-// One step of a wavefront reduction through DPP: every lane receives the
-// (magnitude, position, payload) triple of the lane selected by CTRL and
-// keeps the better of the two.  Lanes without a source keep their own value
-// (old operand = own value), which the comparison leaves unchanged.
+// max(v, v of the lane selected by CTRL) through DPP; lanes without a source
+// keep their own value (old operand = own value).
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ void dpp_pick(double& a, int& p, int& x) {
-  const int alo = __double2loint(a), ahi = __double2hiint(a);
-  const int lo2 = __builtin_amdgcn_update_dpp(alo, alo, CTRL, ROW_MASK, 0xF, false);
-  const int hi2 = __builtin_amdgcn_update_dpp(ahi, ahi, CTRL, ROW_MASK, 0xF, false);
-  const int p2 = __builtin_amdgcn_update_dpp(p, p, CTRL, ROW_MASK, 0xF, false);
-  const int x2 = __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xF, false);
-  const double a2 = __hiloint2double(hi2, lo2);
-  if (better(a2, p2, a, p)) { a = a2; p = p2; x = x2; }
+__device__ __forceinline__ double dpp_max(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+  return fmax(v, __hiloint2double(hi2, lo2));
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_min(int v) {
+  return min(v, __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xF, false));
 }
 
-// Best (largest magnitude, then lowest position) over the 64 lanes, returned
-// in every lane: an inclusive scan inside each row of 16 lanes (row_shr 1, 2,
-// 4, 8), then row_bcast 15 and 31 carry rows 0-1 and 0-3 into lane 63, whose
-// value is broadcast.
-__device__ __forceinline__ void wave_argbest(double& a, int& p, int& x) {
-  dpp_pick<0x111, 0xF>(a, p, x);  // row_shr:1
-  dpp_pick<0x112, 0xF>(a, p, x);  // row_shr:2
-  dpp_pick<0x114, 0xF>(a, p, x);  // row_shr:4
-  dpp_pick<0x118, 0xF>(a, p, x);  // row_shr:8
-  dpp_pick<0x142, 0xA>(a, p, x);  // row_bcast:15 into rows 1 and 3
-  dpp_pick<0x143, 0xC>(a, p, x);  // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(a), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(a), 63);
-  a = __hiloint2double(hi, lo);
-  p = __builtin_amdgcn_readlane(p, 63);
-  x = __builtin_amdgcn_readlane(x, 63);
+// The lane (uniform) holding the best (a, p) of the wave: largest key a, then
+// lowest position p.  Keys are never NaN, so max is exact: an inclusive max
+// scan inside each row of 16 lanes (row_shr 1, 2, 4, 8), then row_bcast 15
+// and 31 carry rows 0-1 and 0-3 into lane 63; a ballot finds the lanes that
+// hold the maximum, and only when there are several does a second scan take
+// the lowest position among them.
+__device__ __forceinline__ int wave_best_lane(double a, int p) {
+  double m = a;
+  m = dpp_max<0x111, 0xF>(m);  // row_shr:1
+  m = dpp_max<0x112, 0xF>(m);  // row_shr:2
+  m = dpp_max<0x114, 0xF>(m);  // row_shr:4
+  m = dpp_max<0x118, 0xF>(m);  // row_shr:8
+  m = dpp_max<0x142, 0xA>(m);  // row_bcast:15 into rows 1 and 3
+  m = dpp_max<0x143, 0xC>(m);  // row_bcast:31 into rows 2 and 3
+  const double mx = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(m), 63),
+                                     __builtin_amdgcn_readlane(__double2loint(m), 63));
+  const unsigned long long hit = __ballot(a == mx);
+  if (__popcll(hit) == 1) return __ffsll((long long)hit) - 1;
+  int q = a == mx ? p : INT_MAX;
+  q = dpp_min<0x111, 0xF>(q);
+  q = dpp_min<0x112, 0xF>(q);
+  q = dpp_min<0x114, 0xF>(q);
+  q = dpp_min<0x118, 0xF>(q);
+  q = dpp_min<0x142, 0xA>(q);
+  q = dpp_min<0x143, 0xC>(q);
+  const int qmin = __builtin_amdgcn_readlane(q, 63);
+  return __ffsll((long long)__ballot(a == mx && p == qmin)) - 1;
 }
 
 // Value of lane `src` (uniform) in every lane.
@@ -179,6 +189,9 @@ __device__ __forceinline__ void panel_body(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row0 = w * R;
+  // wave 0 carries the critical path and shares its SIMD with a bulk wave:
+  // let it issue first
+  if (wave == 0) __builtin_amdgcn_s_setprio(3);
   const int nr = min(R, nrows - row0);
 
   // ---- load the workgroup's rows into LDS ---------------------------------
@@ -251,12 +264,15 @@ __device__ __forceinline__ void panel_body(
         uj = upd2 ? __fma_rn(-sh_lm[sp], Uj[j], sh_v1[sp]) : sh_v1[sp];
         if (lane == 0) Up[j] = uj;
       }
-      double a = -1.0; int p = INT_MAX, r = -1;
+      // each lane's best row, with what the header needs from it
+      double a = -1.0, bv = 0.0, blm = 0.0, bn = 0.0;
+      int p = INT_MAX, r = -1;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
         if (st_q[q] == kNone) {
           const int rr = lane + 64 * q;
           double v = Ts[(int64_t)j * R + rr];
+          const double nx = j + 1 < ncols ? Ts[(int64_t)(j + 1) * R + rr] : 0.0;
           if (upd1) {
             v = __fma_rn(-mlt_q[q], uj, v);
             Ts[(int64_t)j * R + rr] = v;
@@ -265,18 +281,26 @@ __device__ __forceinline__ void panel_body(
           // NaN ranks above every number, so no step is ever left without
           // a candidate (and the NaN propagates)
           const double key = v != v ? __builtin_inf() : fabs(v);
-          if (better(key, pos_q[q], a, p)) { a = key; p = pos_q[q]; r = rr; }
+          if (better(key, pos_q[q], a, p)) {
+            a = key; p = pos_q[q]; r = rr; bv = v; blm = mlt_q[q]; bn = nx;
+          }
         }
       }
-      wave_argbest(a, p, r);
-      // the candidate's multiplier of step j-1 (row r's lane holds it)
-      double lmr = 0.0;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q)
-        if (r >= 0 && r == lane + 64 * q) lmr = mlt_q[q];
-      const double lm = upd1 ? lane_bcast(lmr, r >= 0 ? (r & 63) : 0) : 0.0;
-      const double cpiv = r >= 0 ? Ts[(int64_t)j * R + r] : 0.0;
-      const double cv1 = (r >= 0 && j + 1 < ncols) ? Ts[(int64_t)(j + 1) * R + r] : 0.0;
+      {
+        const int src = wave_best_lane(a, p);
+        a = lane_bcast(a, src);
+        p = __builtin_amdgcn_readlane(p, src);
+        r = __builtin_amdgcn_readlane(r, src);
+        bv = lane_bcast(bv, src);
+        blm = lane_bcast(blm, src);
+        bn = lane_bcast(bn, src);
+      }
+      // the candidate's multiplier of step j-1 and its values in columns j
+      // and j+1 (the latter through step j-2: the bulk update of step j-1
+      // comes after B1)
+      const double lm = upd1 ? blm : 0.0;
+      const double cpiv = r >= 0 ? bv : 0.0;
+      const double cv1 = r >= 0 ? bn : 0.0;
       // (the candidate's row from column j+2 on is published by the bulk
       // waves after B1, before they update it)
       if (lane == 0) sh_cr = r;
@@ -356,21 +380,24 @@ __device__ __forceinline__ void panel_body(
           }
         }
         if (!stop) {
-          double ba = -1.0; int bp = INT_MAX;
+          double ba = -1.0; int bp = INT_MAX, brow = -1;
 #pragma unroll
-          for (int q = 0; q < 4; ++q)
-            if ((need >> q & 1u) && (bw < 0 || better(qa[q], qp[q], ba, bp))) {
-              ba = qa[q]; bp = qp[q]; bw = lane + 64 * q;
-            }
-          wave_argbest(ba, bp, bw);
+          for (int q = 0; q < 4; ++q) {
+            const bool take = (need >> q & 1u) && (bw < 0 || better(qa[q], qp[q], ba, bp));
+            ba = take ? qa[q] : ba;
+            bp = take ? qp[q] : bp;
+            brow = take ? qrow[q] : brow;
+            bw = take ? lane + 64 * q : bw;
+          }
+          const int src = wave_best_lane(ba, bp);
+          ba = lane_bcast(ba, src);
+          bp = __builtin_amdgcn_readlane(bp, src);
+          bw = __builtin_amdgcn_readlane(bw, src);
+          brow = __builtin_amdgcn_readlane(brow, src);
           if (bw < 0 || ba < 0.0) {
             stop = true;  // no candidate anywhere: cannot happen for ncols <= nrows
           } else {
-            int hrow = -1;
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-              if (bw == lane + 64 * q) hrow = qrow[q];
-            win_row = __builtin_amdgcn_readlane(hrow, bw & 63);
+            win_row = brow;
             win_pos = bp;
             if (win_row < 0) stop = true;
             // the winner's header (same words in every lane)

@@ -212,3 +212,34 @@ def test_blocked_panels(rlu, m, n, k, l):
     A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 640 + m)
     G = workloads.gaussian((n, l), 650 + n)
     run_and_compare(rlu, A, k, l, G, f"blocked {m}x{n}")
+
+
+@pytest.mark.parametrize("m,seed", [(6000, 77), (20000, 78)])
+def test_exact_pivot_ties_go_to_lowest_position(rlu, m, seed):
+    """Pivot searches with many equal magnitudes, in exact arithmetic.
+
+    Entries are +-1 and G = [I; 0], so Y is the first l columns of A.  While
+    every pivot is a power of two, multipliers and updates are exact on both
+    sides, so each pivot choice up to and including the first other pivot is
+    made on identical values; every tie (the first step is an m-way one, and
+    ties span workgroups) must go to the lowest current position, as the
+    oracle's search does."""
+    n, k, l = 40, 12, 16
+    rng = np.random.default_rng(seed)
+    A = rng.choice([-1.0, 1.0], size=(m, n))
+    G = np.zeros((n, l))
+    G[:l, :l] = np.eye(l)
+    print(f"[parity] exact ties m={m} seed={seed}", flush=True)
+    out = rlu.factor(to_dev_colmajor(A), k, l, G=to_dev_colmajor(G), diagnostics=True)
+    torch.cuda.synchronize()
+    _, ipiv, _, _, diag = orl.lu_partial_pivot(A[:, :l])
+    exact = 0
+    for a in diag["piv_abs"]:
+        if a == 0.0 or np.frexp(a)[0] != 0.5:
+            break
+        exact += 1
+    assert exact >= 4, "the input no longer exercises exact ties"
+    upto = min(exact + 1, l)
+    assert to_host(out.info)[2] == 0
+    np.testing.assert_array_equal(to_host(out.Y), A[:, :l])
+    np.testing.assert_array_equal(to_host(out.ipiv)[:upto], ipiv[:upto])
