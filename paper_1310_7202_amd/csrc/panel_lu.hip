@@ -19,7 +19,8 @@
 //     j+1 *one update behind* (through step j-2); the bulk waves publish the
 //     rest of the candidate's row, also one update behind.  Every workgroup
 //     polls the dense array of keys, selects the same winner, reads only the
-//     winner's header and completes the winner's row itself,
+//     winner's header, fetches the winner's row into LDS by the next step
+//     and completes the winner's row itself,
 //         U(j, c) = row(c) - l(j-1) U(j-1, c),
 //     with the same fused multiply-add the winner's own workgroup applies to
 //     its copy, so all copies agree bitwise.  Publishing the row one update
@@ -158,15 +159,18 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // Step j, with U(i, .) the U row of step i (the winner's row through step
 // i-1) kept in a two-slot ring urow[i & 1]:
 //   wave 0      U(j-1, j) from the step j-1 header; column j brought up to
-//               date; local candidate; header and key published       | B1 |
+//               date; local candidate; header and key published; the
+//               step j-1 winner's row (loads issued at step j-1) into
+//               LDS                                                   | B1 |
 //               wait for all keys, select the winner, read its header,
-//               bookkeeping, multipliers of step j                    | B0 |
-//   waves 1-7   issue the loads of the step j-1 winner's row          | B1 |
-//               publish their columns of the local candidate's row,
-//               complete U(j-1, c) for their own columns c > j, then
-//               the rank-one update of step j-1 on those columns      | B0 |
+//               issue the loads of its row, bookkeeping, multipliers
+//               of step j                                             | B0 |
+//   waves 1-7   publish their columns of the local candidate's row,  | B1 |
+//               complete U(j-1, c) for their own columns c > j from
+//               LDS, then the rank-one update of step j-1 on them     | B0 |
 // so the only device round trips on wave 0's path are the key exchange and
-// one header read, and the row traffic overlaps them.
+// one header read; the row fetch spans a whole step, and the bulk waves
+// touch no device memory but their own publication.
 template <int RPL>
 __device__ __forceinline__ void panel_body(
     double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R, int nwg,
@@ -242,7 +246,12 @@ __device__ __forceinline__ void panel_body(
   int info = 0;
   __syncthreads();
 
-  unsigned long long pre_lo = 0, pre_hi = 0;  // bulk waves: prefetched body words
+  // wave 0: words of the last winner's row (columns from two past its
+  // step), loaded after its exchange and landed in LDS at the next step
+  constexpr int kPF = 4;
+  unsigned long long bl[kPF], bh[kPF];
+#pragma unroll
+  for (int t = 0; t < kPF; ++t) bl[t] = bh[t] = 0;
   for (int j = 0; j < ncols; ++j) {
     const int sj = j & 1, sp = sj ^ 1;
     double* Uj = urow + sj * ncols;   // U(j, .); until overwritten it still holds U(j-2, .)
@@ -321,16 +330,45 @@ __device__ __forceinline__ void panel_body(
           if (r < 0) { st_agent_i(fail, 1); sh_stop = 1; }  // cannot happen for ncols <= nrows
         }
       }
-    } else if (upd1 && nwg > 1) {
-      // ---- (2a) waves 1-7: start fetching the step j-1 winner's row ---------
-      // (columns c > j, one per lane; the loads complete while wave 0
-      // publishes, and are checked after B1)
-      const int c = j + 1 + (wave - 1) + (kThreads / 64 - 1) * lane;
-      if (c < ncols) {
+      if (nwg > 1 && upd1) {
+        // ---- (1b) the step j-1 winner's row, columns j+1 on, into LDS for
+        // the bulk waves (fetched after that step's exchange; one poll per
+        // word normally finds it there)
         const unsigned long long* pbody =
             (const unsigned long long*)(precs + (int64_t)sh_bw[sp] * rec_stride) + kHdrWords;
-        pre_lo = ld_agent(pbody + 2 * c);
-        pre_hi = ld_agent(pbody + 2 * c + 1);
+        bool stop = false;
+#pragma unroll
+        for (int t = 0; t < kPF; ++t) {
+          const int c = j + 1 + lane + 64 * t;
+          if (c < ncols && !stop) {
+            unsigned long long lo = bl[t], hi = bh[t];
+            while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
+              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+                stop = true;
+                break;
+              }
+              lo = ld_agent(pbody + 2 * c);
+              hi = ld_agent(pbody + 2 * c + 1);
+            }
+            lbody[sp * ncols + c] = bitsd(join64(lo, hi));
+          }
+        }
+        // columns past the prefetched ones (panels wider than 64 kPF)
+        for (int c = j + 1 + 64 * kPF + lane; c < ncols && !stop; c += 64) {
+          unsigned long long lo = ld_agent(pbody + 2 * c), hi = ld_agent(pbody + 2 * c + 1);
+          while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
+            if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+              stop = true;
+              break;
+            }
+            lo = ld_agent(pbody + 2 * c);
+            hi = ld_agent(pbody + 2 * c + 1);
+          }
+          lbody[sp * ncols + c] = bitsd(join64(lo, hi));
+        }
+        if (__any(stop)) {
+          if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
+        }
       }
     }
     lds_barrier();  // B1: candidate published (the bulk update may now touch its row)
@@ -417,6 +455,18 @@ __device__ __forceinline__ void panel_body(
               piv = bitsd(join64(x[0], x[1]));
               wlm = bitsd(join64(x[2], x[3]));
               wv1 = bitsd(join64(x[4], x[5]));
+              // start fetching the winner's row (columns j+2 on): the bulk
+              // waves need it at the next step
+              const unsigned long long* wb =
+                  (const unsigned long long*)(recs + (int64_t)bw * rec_stride) + kHdrWords;
+#pragma unroll
+              for (int t = 0; t < kPF; ++t) {
+                const int c = j + 2 + lane + 64 * t;
+                if (c < ncols) {
+                  bl[t] = ld_agent(wb + 2 * c);
+                  bh[t] = ld_agent(wb + 2 * c + 1);
+                }
+              }
             }
           }
         }
@@ -489,38 +539,12 @@ __device__ __forceinline__ void panel_body(
       // the winner's own workgroup applies, then updates those columns.
       constexpr int kBW = kThreads / 64 - 1;
       {
+        // the winner's row is in LDS (landed by wave 0 before B1, or
+        // written by this workgroup itself when it is alone)
         const double lmw = sh_lm[sp];
-        bool stop = false;
-        const unsigned long long* pbody =
-            nwg > 1 ? (const unsigned long long*)(precs + (int64_t)sh_bw[sp] * rec_stride) +
-                          kHdrWords
-                    : nullptr;
-        for (int c = j + 1 + (wave - 1) + kBW * lane, first = 1; c < ncols;
-             c += kBW * 64, first = 0) {
-          double b;
-          if (nwg > 1) {
-            unsigned long long lo = pre_lo, hi = pre_hi;
-            if (!first) {
-              lo = ld_agent(pbody + 2 * c);
-              hi = ld_agent(pbody + 2 * c + 1);
-            }
-            while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
-              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
-                stop = true;
-                break;
-              }
-              lo = ld_agent(pbody + 2 * c);
-              hi = ld_agent(pbody + 2 * c + 1);
-            }
-            if (stop) break;
-            b = bitsd(join64(lo, hi));
-          } else {
-            b = lbody[sp * ncols + c];
-          }
+        for (int c = j + 1 + (wave - 1) + kBW * lane; c < ncols; c += kBW * 64) {
+          const double b = lbody[sp * ncols + c];
           Up[c] = upd2 ? __fma_rn(-lmw, Uj[c], b) : b;
-        }
-        if (__any(stop)) {
-          if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
         }
       }
       // this wave's U values are read back by all its lanes: keep the LDS
