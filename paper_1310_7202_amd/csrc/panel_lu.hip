@@ -555,40 +555,48 @@ __device__ __forceinline__ void panel_body(
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       // Rows still active after step j-1 (step_s > j-1).  A row being chosen
       // at step j right now has step_s kNone or j: included either way, as it
-      // must be (its U row is its values through step j-1).
+      // must be (its U row is its values through step j-1).  Lanes past the
+      // last stored row (lane + 64 q >= R) mirror row R-1: they load, compute
+      // and store exactly what that row's own lane does, so that every load
+      // and store is unconditional and inactive rows store back what they
+      // read (only this wave writes its columns).
+      int ro[RPL];
       double m[RPL];
       bool act[RPL];
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        const int r = lane + 64 * q;
-        act[q] = r < nr && step_s[r] > step0 + j - 1;
-        m[q] = act[q] ? Ts[(int64_t)(j - 1) * R + r] : 0.0;
+        ro[q] = min(lane + 64 * q, R - 1);
+        act[q] = ro[q] < nr && step_s[ro[q]] > step0 + j - 1;
+        m[q] = Ts[(int64_t)(j - 1) * R + ro[q]];
       }
       constexpr int kBulkWaves = kThreads / 64 - 1;
-      constexpr int kU = 4;  // columns per iteration: all loads issued before any FMA
-      int c = j + 1 + (wave - 1);
+      // columns per iteration, all loads issued before any FMA (fewer for
+      // eight rows per lane, which would spill)
+      constexpr int kU = RPL >= 8 ? 2 : 4;
+      int c = j + __builtin_amdgcn_readfirstlane(wave);  // uniform: j + 1 + (wave - 1)
       for (; c + (kU - 1) * kBulkWaves < ncols; c += kU * kBulkWaves) {
         double u[kU], x[kU][RPL];
 #pragma unroll
         for (int t = 0; t < kU; ++t) {
           u[t] = Up[c + t * kBulkWaves];
 #pragma unroll
-          for (int q = 0; q < RPL; ++q)
-            x[t][q] = Ts[(int64_t)(c + t * kBulkWaves) * R + lane + 64 * q];
+          for (int q = 0; q < RPL; ++q) x[t][q] = Ts[(int64_t)(c + t * kBulkWaves) * R + ro[q]];
         }
 #pragma unroll
         for (int t = 0; t < kU; ++t)
 #pragma unroll
           for (int q = 0; q < RPL; ++q)
-            if (act[q])
-              Ts[(int64_t)(c + t * kBulkWaves) * R + lane + 64 * q] = __fma_rn(-m[q], u[t], x[t][q]);
+            Ts[(int64_t)(c + t * kBulkWaves) * R + ro[q]] =
+                act[q] ? __fma_rn(-m[q], u[t], x[t][q]) : x[t][q];
       }
       for (; c < ncols; c += kBulkWaves) {
         const double u = Up[c];
-        double* col = Ts + (int64_t)c * R + lane;
+        double x[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) x[q] = Ts[(int64_t)c * R + ro[q]];
 #pragma unroll
         for (int q = 0; q < RPL; ++q)
-          if (act[q]) col[64 * q] = __fma_rn(-m[q], u, col[64 * q]);
+          Ts[(int64_t)c * R + ro[q]] = act[q] ? __fma_rn(-m[q], u, x[q]) : x[q];
       }
     }
     lds_barrier();  // B0 of the next step
