@@ -41,6 +41,7 @@ struct Tile {
   static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be a multiple of 16");
   static_assert((BM * BK) % NT == 0 && (BN * BK) % NT == 0, "tile must divide threads");
   static_assert(BK % 4 == 0, "BK multiple of the MFMA depth");
+  static_assert(NT % BK == 0, "a thread's K row is the same for all its elements");
 };
 
 // One BM x BN output tile (bx, by) over K split bz of ksplit.
@@ -69,26 +70,40 @@ __device__ __forceinline__ void gemm_tile(
   const int64_t kbeg = (int64_t)bz * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
-  TC ra[Tl::AE], rb[Tl::BE];
+  // Prefetch registers hold the operands in their storage type: the
+  // conversion, and the Lv mapping of the K-contiguous operands (one step
+  // per thread), are applied when the slice is written to LDS, after the
+  // MFMAs of the current slice, so that no load of the next slice is waited
+  // for early.  (Lv and LvStrict operands, whose step varies per element,
+  // are mapped on load.)
+  TA ra[Tl::AE];
+  TB rb[Tl::BE];
+  int sa1 = 0, sb1 = 0;  // Lv^T A / Lv B: the step of this thread's K row
 
+  // element q of this thread in the A tile: (row i, k kk)
+  auto a_pos = [&](int q, int& i, int& kk) {
+    const int e = tid + q * Tl::NT;
+    if (AK) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+  };
   auto load = [&](int64_t k0) {
+    if (OA == OpA::LvT) {
+      const int64_t gk = k0 + tid % BK;  // the same K row for every element (NT % BK == 0)
+      sa1 = gk < kend ? astep[gk] : 0;
+    }
+    if (OB == OpB::Lv) {
+      const int64_t gk = k0 + tid % BK;
+      sb1 = gk < kend ? bstep[gk] : 0;
+    }
 #pragma unroll
     for (int q = 0; q < Tl::AE; ++q) {
-      const int e = tid + q * Tl::NT;
       int i, kk;
-      if (AK) { kk = e % BK; i = e / BK; } else { i = e % BM; kk = e / BM; }
+      a_pos(q, i, kk);
       const int64_t gi = m0 + i, gk = k0 + kk;
-      TC v = TC(0);
+      TA v = TA(0);
       if (gi < M && gk < kend) {
-        if (OA == OpA::Plain) {
-          v = (TC)A[gi + gk * lda];
-        } else if (OA == OpA::LvT) {
-          v = (TC)lv_value<TA>(A[gk + gi * lda], (int)gi, astep[gk]);
-        } else if (OA == OpA::Lv) {
-          v = (TC)lv_value<TA>(A[gi + gk * lda], (int)gk, astep[gi]);
-        } else {  // LvStrict: multipliers only, columns numbered from acol0
-          v = (int)(acol0 + gk) < astep[gi] ? (TC)A[gi + gk * lda] : TC(0);
-        }
+        if (OA == OpA::Plain || OA == OpA::LvT) v = AK ? A[gk + gi * lda] : A[gi + gk * lda];
+        else if (OA == OpA::Lv) v = lv_value<TA>(A[gi + gk * lda], (int)gk, astep[gi]);
+        else v = (int)(acol0 + gk) < astep[gi] ? A[gi + gk * lda] : TA(0);  // LvStrict
       }
       ra[q] = v;
     }
@@ -97,31 +112,35 @@ __device__ __forceinline__ void gemm_tile(
       const int e = tid + q * Tl::NT;
       const int kk = e % BK, j = e / BK;
       const int64_t gj = n0 + j, gk = k0 + kk;
-      TC v = TC(0);
-      if (gj < N && gk < kend) {
-        if (OB == OpB::Plain) v = (TC)B[gk + gj * ldb];
-        else v = (TC)lv_value<TB>(B[gk + gj * ldb], (int)gj, bstep[gk]);
-      }
-      rb[q] = v;
+      rb[q] = (gj < N && gk < kend) ? B[gk + gj * ldb] : TB(0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int64_t k0) {
 #pragma unroll
     for (int q = 0; q < Tl::AE; ++q) {
-      const int e = tid + q * Tl::NT;
-      if (AK) {
-        const int kk = e % BK, i = e / BK;
-        As[buf][i * Tl::A_LD + kk] = ra[q];
-      } else {
-        const int i = e % BM, kk = e / BM;
-        As[buf][kk * Tl::A_LD + i] = ra[q];
-      }
+      int i, kk;
+      a_pos(q, i, kk);
+      const int64_t gi = m0 + i, gk = k0 + kk;
+      TC v;
+      if (OA == OpA::LvT)
+        v = gi < M && gk < kend ? (TC)lv_value<TA>(ra[q], (int)gi, sa1) : TC(0);
+      else
+        v = (TC)ra[q];
+      if (AK) As[buf][i * Tl::A_LD + kk] = v;
+      else As[buf][kk * Tl::A_LD + i] = v;
     }
 #pragma unroll
     for (int q = 0; q < Tl::BE; ++q) {
       const int e = tid + q * Tl::NT;
       const int kk = e % BK, j = e / BK;
-      Bs[buf][j * Tl::B_LD + kk] = rb[q];
+      TC v;
+      if (OB == OpB::Plain) {
+        v = (TC)rb[q];
+      } else {
+        const int64_t gj = n0 + j, gk = k0 + kk;
+        v = (gj < N && gk < kend) ? (TC)lv_value<TB>(rb[q], (int)gj, sb1) : TC(0);
+      }
+      Bs[buf][j * Tl::B_LD + kk] = v;
     }
   };
 
@@ -134,7 +153,7 @@ __device__ __forceinline__ void gemm_tile(
   int buf = 0;
   if (kbeg < kend) {
     load(kbeg);
-    store(0);
+    store(0, kbeg);
   }
   __syncthreads();
   for (int64_t kt = kbeg; kt < kend; kt += BK) {
@@ -161,7 +180,7 @@ __device__ __forceinline__ void gemm_tile(
     }
     if (more) {
       if (NBUF == 1) __syncthreads();  // everyone is done reading the only buffer
-      store(NBUF == 1 ? 0 : buf ^ 1);
+      store(NBUF == 1 ? 0 : buf ^ 1, kt + BK);
     }
     __syncthreads();
     if (NBUF == 2) buf ^= 1;

@@ -21,6 +21,8 @@
 #include "rlu_device.h"
 #include "rlu_kernels.h"
 
+#include <climits>
+
 #include <algorithm>
 #include <type_traits>
 
@@ -73,22 +75,30 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
   const int64_t kbeg = (int64_t)bz * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
 
-  // raw (storage-type) prefetch registers
-  double ra[AE];
-  float rb[BE];
+  // raw (storage-type) prefetch registers: conversion and the Lv mapping
+  // are applied at the LDS store, after the MFMAs of the current slice, so
+  // that no load of the next slice is waited for early
+  static_assert(NT % LBK == 0, "a thread's K row is the same for all its elements");
+  TA ra[AE];
+  TB rb[BE];
+  int sa1 = 0;  // Lv^T A: the step of this thread's K row
 
+  auto a_pos = [&](int q, int& i, int& kk) {
+    const int e = tid + q * NT;
+    if (OA == OpA::LvT) { kk = e % LBK; i = e / LBK; } else { i = e % BM; kk = e / BM; }
+  };
   auto load = [&](int64_t k0) {
+    if (OA == OpA::LvT) {
+      const int64_t gk = k0 + tid % LBK;
+      sa1 = gk < kend ? astep[gk] : 0;
+    }
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
-      const int e = tid + q * NT;
       int i, kk;
-      if (OA == OpA::LvT) { kk = e % LBK; i = e / LBK; } else { i = e % BM; kk = e / BM; }
+      a_pos(q, i, kk);
       const int64_t gi = m0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < M && gk < kend) {
-        if (OA == OpA::Plain) v = (double)A[gi + gk * lda];
-        else v = (double)lv_value<TA>(A[gk + gi * lda], (int)gi, astep[gk]);
-      }
+      TA v = TA(0);
+      if (gi < M && gk < kend) v = OA == OpA::Plain ? A[gi + gk * lda] : A[gk + gi * lda];
       ra[q] = v;
     }
 #pragma unroll
@@ -96,25 +106,31 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
       const int e = tid + q * NT;
       const int kk = e % LBK, j = e / LBK;
       const int64_t gj = n0 + j, gk = k0 + kk;
-      rb[q] = (gj < N && gk < kend) ? (float)B[gk + gj * ldb] : 0.f;
+      rb[q] = (gj < N && gk < kend) ? B[gk + gj * ldb] : TB(0);
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int64_t k0) {
 #pragma unroll
     for (int q = 0; q < AE; ++q) {
-      const int e = tid + q * NT;
       int i, kk;
-      if (OA == OpA::LvT) { kk = e % LBK; i = e / LBK; } else { i = e % BM; kk = e / BM; }
-      const float x = (float)ra[q];
+      a_pos(q, i, kk);
+      double xd;
+      if (OA == OpA::Plain) {
+        xd = (double)ra[q];
+      } else {
+        const int64_t gi = m0 + i, gk = k0 + kk;
+        xd = (gi < M && gk < kend) ? (double)lv_value<TA>(ra[q], (int)gi, sa1) : 0.0;
+      }
+      const float x = (float)xd;
       const LP hi = (LP)x;
       As[buf][0][i * LLD + kk] = hi;
-      if (SPLIT) As[buf][NS - 1][i * LLD + kk] = (LP)(float)(ra[q] - (double)(float)hi);
+      if (SPLIT) As[buf][NS - 1][i * LLD + kk] = (LP)(float)(xd - (double)(float)hi);
     }
 #pragma unroll
     for (int q = 0; q < BE; ++q) {
       const int e = tid + q * NT;
       const int kk = e % LBK, j = e / LBK;
-      Bs[buf][j * LLD + kk] = (LP)rb[q];
+      Bs[buf][j * LLD + kk] = (LP)(float)rb[q];
     }
   };
 
@@ -127,7 +143,7 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
   int buf = 0;
   if (kbeg < kend) {
     load(kbeg);
-    store(0);
+    store(0, kbeg);
   }
   __syncthreads();
   for (int64_t kt = kbeg; kt < kend; kt += LBK) {
@@ -153,7 +169,7 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
         acc[a][b] = LpMfma<LP>::mma(af[0][a], bf[b], acc[a][b]);
         if (SPLIT) acc[a][b] = LpMfma<LP>::mma(af[NS - 1][a], bf[b], acc[a][b]);
       }
-    if (more) store(buf ^ 1);
+    if (more) store(buf ^ 1, kt + LBK);
     __syncthreads();
     buf ^= 1;
   }
@@ -267,6 +283,7 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
   // prefetch registers: A as FP32 values (Plain) or FP64 (LvT)
   typedef typename std::conditional<OA == OpA::Plain, float, double>::type RA;
   RA ra[ACH][(OA == OpA::Plain) ? 16 : 4];
+  int rs[(OA == OpA::Plain) ? 1 : ACH][4];  // Lv^T: the steps of the loaded K rows
   float rb[BCH][4];
 
   auto load = [&](int64_t k0) {
@@ -291,23 +308,23 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
           }
         }
       } else {
-        // 4 consecutive k of output row i
+        // 4 consecutive k of output row i, as stored, with their steps (the
+        // Lv mapping is applied at the LDS store)
         const int kk4 = 4 * (e % (LBK / 4)), i = e / (LBK / 4);
         const int64_t gi = m0 + i, gk = k0 + kk4;
         if (gi < M && gk + 3 < kend) {
           const double2 v0 = *(const double2*)&A[gk + gi * lda];
           const double2 v1 = *(const double2*)&A[gk + 2 + gi * lda];
           const int4 s4 = *(const int4*)&astep[gk];
-          ra[q][0] = lv_value<double>(v0.x, (int)gi, s4.x);
-          ra[q][1] = lv_value<double>(v0.y, (int)gi, s4.y);
-          ra[q][2] = lv_value<double>(v1.x, (int)gi, s4.z);
-          ra[q][3] = lv_value<double>(v1.y, (int)gi, s4.w);
+          ra[q][0] = v0.x; ra[q][1] = v0.y; ra[q][2] = v1.x; ra[q][3] = v1.y;
+          rs[q][0] = s4.x; rs[q][1] = s4.y; rs[q][2] = s4.z; rs[q][3] = s4.w;
         } else {
 #pragma unroll
-          for (int c = 0; c < 4; ++c)
-            ra[q][c] = (gi < M && gk + c < kend)
-                           ? lv_value<double>((double)A[gk + c + gi * lda], (int)gi, astep[gk + c])
-                           : 0.0;
+          for (int c = 0; c < 4; ++c) {
+            const bool in = gi < M && gk + c < kend;
+            ra[q][c] = in ? (double)A[gk + c + gi * lda] : 0.0;
+            rs[q][c] = in ? astep[gk + c] : INT_MIN;  // INT_MIN: outside, maps to 0
+          }
         }
       }
     }
@@ -339,13 +356,15 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
         }
       } else {
         const int kk4 = 4 * (e % (LBK / 4)), i = e / (LBK / 4);
+        const int gi = (int)(m0 + i);
         lp4 h, l;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const float x = (float)ra[q][c];
+          const double xd = lv_value<double>(ra[q][c], gi, rs[q][c]);
+          const float x = (float)xd;
           const LP hi = (LP)x;
           h[c] = hi;
-          l[c] = (LP)(float)(ra[q][c] - (double)(float)hi);
+          l[c] = (LP)(float)(xd - (double)(float)hi);
         }
         *(lp4*)&As[buf][0][i * LLD + kk4] = h;
         if (SPLIT) *(lp4*)&As[buf][NS - 1][i * LLD + kk4] = l;

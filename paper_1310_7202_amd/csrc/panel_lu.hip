@@ -276,25 +276,29 @@ __device__ __forceinline__ void panel_body(
       // each lane's best row, with what the header needs from it
       double a = -1.0, bv = 0.0, blm = 0.0, bn = 0.0;
       int p = INT_MAX, r = -1;
+      // (straight-line: loads for every lane, clamped to the stored rows,
+      // selects instead of branches; the updated column j is stored in (4))
+      const int jn = j + 1 < ncols ? j + 1 : j;
 #pragma unroll
       for (int q = 0; q < RPL; ++q) {
-        if (st_q[q] == kNone) {
-          const int rr = lane + 64 * q;
-          double v = Ts[(int64_t)j * R + rr];
-          const double nx = j + 1 < ncols ? Ts[(int64_t)(j + 1) * R + rr] : 0.0;
-          if (upd1) {
-            v = __fma_rn(-mlt_q[q], uj, v);
-            Ts[(int64_t)j * R + rr] = v;
-          }
-          val_q[q] = v;
-          // NaN ranks above every number, so no step is ever left without
-          // a candidate (and the NaN propagates)
-          const double key = v != v ? __builtin_inf() : fabs(v);
-          if (better(key, pos_q[q], a, p)) {
-            a = key; p = pos_q[q]; r = rr; bv = v; blm = mlt_q[q]; bn = nx;
-          }
-        }
+        const int rr = lane + 64 * q, rq = min(rr, R - 1);
+        const bool live = st_q[q] == kNone;
+        const double x = Ts[(int64_t)j * R + rq];
+        const double nx = Ts[(int64_t)jn * R + rq];
+        const double v = upd1 ? __fma_rn(-mlt_q[q], uj, x) : x;
+        val_q[q] = v;
+        // NaN ranks above every number, so no step is ever left without a
+        // candidate (and the NaN propagates)
+        const double key = v != v ? __builtin_inf() : fabs(v);
+        const bool take = live && better(key, pos_q[q], a, p);
+        a = take ? key : a;
+        p = take ? pos_q[q] : p;
+        r = take ? rr : r;
+        bv = take ? v : bv;
+        blm = take ? mlt_q[q] : blm;
+        bn = take ? nx : bn;
       }
+      if (j + 1 >= ncols) bn = 0.0;
       {
         const int src = wave_best_lane(a, p);
         a = lane_bcast(a, src);
@@ -486,23 +490,20 @@ __device__ __forceinline__ void panel_body(
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
           const int r = lane + 64 * q;
-          if (st_q[q] == -1) continue;
-          if (r == wr) {
-            pos_q[q] = step0 + j;
-            st_q[q] = step0 + j;
-            step_s[r] = step0 + j;
-            mlt_q[q] = 0.0;
-          } else {
-            if (pos_q[q] == step0 + j) pos_q[q] = win_pos;  // row at position j moves away
-            double m = 0.0;
-            if (st_q[q] == kNone && piv != 0.0) {
-              // multiply by the reciprocal pivot unless it would overflow
-              m = big_piv ? val_q[q] * rpiv : val_q[q] / piv;
-              Ts[(int64_t)j * R + r] = m;
-            }
-            mlt_q[q] = m;
-          }
+          const bool live = st_q[q] == kNone, isw = r == wr;
+          // multiply by the reciprocal pivot unless it would overflow
+          double mq = 0.0;
+          if (piv != 0.0) mq = big_piv ? val_q[q] * rpiv : val_q[q] / piv;
+          mq = live && !isw ? mq : 0.0;
+          // column j: the winner keeps its pivot, the other live rows take
+          // their multipliers (their values when the pivot is zero)
+          if (live) Ts[(int64_t)j * R + r] = isw || piv == 0.0 ? val_q[q] : mq;
+          // the winner takes position j, the row there moves to its place
+          pos_q[q] = isw ? step0 + j : (pos_q[q] == step0 + j ? win_pos : pos_q[q]);
+          st_q[q] = isw ? step0 + j : st_q[q];
+          mlt_q[q] = mq;
         }
+        if (lane == 0 && wr >= 0 && wr < R) step_s[wr] = step0 + j;
         if (lane == 0) {
           Uj[j] = piv;
           sh_piv[sj] = piv;
