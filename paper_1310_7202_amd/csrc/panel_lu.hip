@@ -24,7 +24,7 @@
 //         U(j, c) = row(c) - l(j-1) U(j-1, c),
 //     with the same fused multiply-add the winner's own workgroup applies to
 //     its copy, so all copies agree bitwise.  Publishing the row one update
-//     behind lets waves 1-7 apply the bulk rank-one update of step j-1 while
+//     behind lets the bulk waves apply the rank-one update of step j-1 while
 //     wave 0 waits on the exchange: only the exchange latency and
 //     O(R/64 + nwg/64) work per lane sit on the critical path.
 //   * exchange protocol: every 64-bit word of a record carries the step tag
@@ -49,7 +49,11 @@
 namespace rlu {
 namespace {
 
-constexpr int kThreads = 512;
+// Threads per workgroup: 16 waves (one pivot wave, 15 bulk waves) when a
+// lane holds at most two rows (four waves per SIMD fit the registers), else 8.
+template <int RPL>
+constexpr int threads_for() { return RPL <= 2 ? 1024 : 512; }
+inline int threads_for_rows(int R) { return R <= 128 ? 1024 : 512; }
 constexpr int kNone = INT_MAX;
 
 // Exchange buffer of a step: first a dense key area, 4 words per workgroup
@@ -165,7 +169,7 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 //               wait for all keys, select the winner, read its header,
 //               issue the loads of its row, bookkeeping, multipliers
 //               of step j                                             | B0 |
-//   waves 1-7   publish their columns of the local candidate's row,  | B1 |
+//   bulk waves  publish their columns of the local candidate's row,  | B1 |
 //               complete U(j-1, c) for their own columns c > j from
 //               LDS, then the rank-one update of step j-1 on them     | B0 |
 // so the only device round trips on wave 0's path are the key exchange and
@@ -179,6 +183,7 @@ __device__ __forceinline__ void panel_body(
     char* __restrict__ xch, int64_t rec_stride, long long timeout_ticks, int w, double* smem,
     long long t_start, int step0, int total_cols, const int* __restrict__ pos_in,
     const int* __restrict__ rstep_in) {
+  constexpr int kThreads = threads_for<RPL>();
   double* Ts = smem;                        // R x ncols, column-major (ld R)
   double* urow = Ts + (int64_t)R * ncols;   // 2 x ncols: U rows by step parity
   double* lbody = urow + 2 * ncols;         // 2 x ncols: single-workgroup "records"
@@ -516,7 +521,7 @@ __device__ __forceinline__ void panel_body(
         if (piv == 0.0 && info == 0) info = step0 + j + 1;
       }
     } else {
-      // ---- (2b) waves 1-7, first: publish this wave's columns c >= j+2 of
+      // ---- (2b) bulk waves, first: publish this wave's columns c >= j+2 of
       // the workgroup's candidate row (through step j-2: before the update
       // of step j-1 below touches them)
       const int rc = sh_cr;
@@ -533,9 +538,9 @@ __device__ __forceinline__ void panel_body(
       }
     }
     if (wave != 0 && upd1) {
-      // ---- (2b) waves 1-7: U(j-1, c) for this wave's columns, then the
+      // ---- (2b) bulk waves: U(j-1, c) for this wave's columns, then the
       // rank-one update of step j-1 on them.  Wave w owns the columns
-      // c = j + w + 7 t (t = 0, 1, ...): it completes U(j-1, c) from the
+      // c = j + w + (waves - 1) t: it completes U(j-1, c) from the
       // winner's row, one update behind, with the same fused multiply-add
       // the winner's own workgroup applies, then updates those columns.
       constexpr int kBW = kThreads / 64 - 1;
@@ -642,7 +647,7 @@ __device__ __forceinline__ void panel_body(
 }
 
 template <int RPL>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(threads_for<RPL>())
 panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R,
                 int nwg, int* __restrict__ pos_out, int* __restrict__ rstep_out,
                 int* __restrict__ piv_row_out, int* __restrict__ ipiv_out,
@@ -661,7 +666,7 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
 // same round, so a member waiting on its partners only waits for work of
 // the same or earlier rounds, which always completes.
 template <int RPL>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(threads_for<RPL>())
 panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __restrict__ sched,
                         int rounds, int nslots, long long timeout_ticks) {
   extern __shared__ double smem[];
@@ -740,8 +745,8 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
                             : (const void*)panel_lu_kernel<8>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
   if (e != hipSuccess) return e;
-  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kThreads), args, (unsigned)plan.lds_bytes,
-                                    s);
+  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(threads_for_rows(R)), args,
+                                    (unsigned)plan.lds_bytes, s);
 }
 
 int64_t panel_rec_stride(int ncols) { return rec_stride_for(ncols); }
@@ -767,7 +772,7 @@ int panel_batched_slots(int max_R, size_t lds_bytes, int cus) {
       hipSuccess)
     return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds_bytes) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_for_rows(max_R), lds_bytes) !=
       hipSuccess)
     return 0;
   return per_cu * cus;
@@ -785,7 +790,7 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   void* args[] = {&tasks, &sched, &rounds, &nslots, &timeout_ticks};
-  return hipLaunchKernel(fn, dim3(nslots), dim3(kThreads), args, lds_bytes, s);
+  return hipLaunchKernel(fn, dim3(nslots), dim3(threads_for_rows(max_R)), args, lds_bytes, s);
 }
 
 // ---------------------------------------------------------------------------
