@@ -245,10 +245,13 @@ rlu_status_t rlu_serve_stats(rlu_server_t srv, size_t* used_bytes, int32_t* queu
  * not released are freed too). */
 rlu_status_t rlu_serve_destroy(rlu_server_t srv);
 
-/* Phase timing for measurement tools.  When enabled, rlu_factor records a
- * HIP event pair around each phase on the stream that runs the phase (the
- * caller's stream, or the handle's side stream for the Gram inverse).  The
- * handle keeps the events of the last RLU_TIMING_RING calls. */
+/* Phase timing for measurement tools.  enable = 1: rlu_factor records a HIP
+ * event pair around each phase on the stream that runs the phase (the
+ * caller's stream, or the handle's side stream for the Gram inverse);
+ * enable = 2: around the sketch product (Step 2) only, so that timing the
+ * dominant kernel adds one event pair per call; 0: off.  The handle keeps
+ * the events of the last RLU_TIMING_RING calls.  Other values:
+ * RLU_ERR_INVALID_ARG. */
 #define RLU_TIMING_RING 64
 #define RLU_MAX_PHASES 16
 rlu_status_t rlu_set_timing(rlu_handle_t h, int enable);

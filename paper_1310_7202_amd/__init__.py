@@ -169,8 +169,10 @@ class Handle:
         """Tile shape of a grouped product of the batched form (-1: tuned table)."""
         _check(lib().rlu_set_tile(self._h, product, cfg), "rlu_set_tile")
 
-    def set_timing(self, enable: bool = True):
-        _check(lib().rlu_set_timing(self._h, 1 if enable else 0), "rlu_set_timing")
+    def set_timing(self, enable=True):
+        """True / 1: every phase; 2: the sketch product only; False / 0: off."""
+        mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        _check(lib().rlu_set_timing(self._h, mode), "rlu_set_timing")
 
     def phase_times(self, back: int = 0) -> dict:
         """{phase name: ms} of the call `back` calls before the latest."""

@@ -512,8 +512,9 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffe
 }
 
 rlu_status_t rlu_set_timing(rlu_handle_t h, int enable) {
-  if (!h) return RLU_ERR_INVALID_ARG;
+  if (!h || enable < 0 || enable > 2) return RLU_ERR_INVALID_ARG;
   h->timing = enable != 0;
+  h->timing_mode = enable;
   if (!h->timing) { h->ring_filled = 0; h->ring_next = 0; }
   return RLU_OK;
 }

@@ -35,6 +35,7 @@ struct BatchGraph {
 struct rlu_handle_s {
   int device = 0;
   bool timing = false;
+  int timing_mode = 0;      // 1: every phase, 2: the sketch product only
   int ring_next = 0;        // next slot to fill
   int ring_filled = 0;      // number of valid slots
   TimingSlot ring[RLU_TIMING_RING];
@@ -92,7 +93,8 @@ rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t*
 struct PhaseScope {
   rlu_handle_s* h; int id; hipStream_t s; bool on;
   PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
-      : h(h_), id(id_), s(s_), on(h_->timing && h_->cur) {
+      : h(h_), id(id_), s(s_),
+        on(h_->timing && h_->cur && (h_->timing_mode != 2 || id_ == PH_SKETCH)) {
     if (on) {
       h->cur->used[id] = true;
       hipEventRecord(h->cur->ev[id][0], s);

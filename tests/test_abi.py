@@ -146,3 +146,12 @@ def test_batched_rejects_bad_arguments_before_any_device_work(rlu):
         ios[i].ldu = 5
     # mixed dtypes in one call
     assert lib.rlu_factor_batched(ctypes.c_void_p(1), 2, pbs, ios, None) == -1
+
+
+def test_timing_rejects_null_handle_and_unknown_modes(rlu):
+    """rlu_set_timing: 0 off, 1 every phase, 2 the sketch product only;
+    a null handle or any other mode is an argument error (no device work)."""
+    lib = rlu.lib()
+    for mode in (0, 1, 2):
+        assert lib.rlu_set_timing(None, mode) == -1
+    assert lib.rlu_set_timing(None, 3) == -1
