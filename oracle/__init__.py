@@ -20,6 +20,11 @@ Pinned by (see ``tests/test_oracle_*.py``):
     block elimination, in exact rational arithmetic on tiny inputs.
   * ``rlu.lu_col_pivot``       -- LAPACK getrf of the transpose (pivots) and
     the closed-form Schur complement.
+  * ``rlu.power_sketch``       -- Section 5.2: the plain product
+    (A A^T)^q A G gives the same pivots and factors (the normalization is a
+    right triangular factor); q = 0 is Step 2; exact rank-k reconstruction;
+    the error falls with q on the paper's slowly decaying spectrum.
+  * ``rlu.lu_normalize``       -- LAPACK getrf: P L from scipy.linalg.lu.
   * ``bounds.xi``              -- Table 4.1 of the paper, 9 of 9 rows.
   * ``philox.philox4x32_10``   -- Random123 known-answer vectors.
   * ``philox.gaussian_matrix`` -- Box-Muller closed form on fixed uniforms and

@@ -150,11 +150,45 @@ def lu_col_pivot(B: np.ndarray):
     return Lb, Ub, qpiv, q, info, {"piv_abs": piv_abs, "gap": gap, "max_abs": bmax}
 
 
-def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray) -> dict:
+def lu_normalize(X: np.ndarray) -> np.ndarray:
+    """The normalization of the power scheme (Section 5.2): X (tall, w
+    columns) is replaced by the unit-lower factor of its partial-pivot LU
+    (the factorization of Step 3), put back in X's own row order, i.e.
+    P^T L where P X = L U.  When U is nonsingular this equals X U^{-1}: the
+    same column space, with every entry bounded by 1 in magnitude."""
+    LU, _, p, _, _ = lu_partial_pivot(X)
+    L = unit_lower(LU, X.shape[1])
+    out = np.empty_like(L)
+    out[p, :] = L
+    return out
+
+
+def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
+    """Step 2 with q power iterations (Section 5.2): Y = (A A^*)^q A G.
+
+    A G is followed by q rounds of one product with A^T and one with A.
+    Every product except the last is normalized by ``lu_normalize``, the
+    normalized scheme the paper points to for larger q.  Each normalization
+    multiplies the block on the right by an upper-triangular matrix, which
+    changes neither the pivots nor the unit-lower factor of Step 3, so
+    Steps 3-8 agree with the plain product in exact arithmetic.
+    """
+    if q < 0:
+        raise ValueError("q must be >= 0")
+    Y = sketch(A, G)
+    for _ in range(q):
+        Y = lu_normalize(Y)
+        Z = lu_normalize(A.T @ Y)
+        Y = A @ Z
+    return Y
+
+
+def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0) -> dict:
     """Algorithm 4.1 of the paper, Steps 2-8, for a given Gaussian G (Step 1).
 
     Inputs: A (m x n), k (target rank), l (number of sketch columns,
-    k <= l <= min(m, n)), G (n x l).  Returns a dict with the outputs
+    k <= l <= min(m, n)), G (n x l) and the number q of power iterations
+    of Section 5.2 (0: the plain Step 2).  Returns a dict with the outputs
     L (m x k unit lower trapezoidal), U (k x n upper trapezoidal), p, q and
     the intermediates (Y, packed LU of Y, ipiv, L_y, B, L_b, qpiv, info words
     and pivot diagnostics).
@@ -166,7 +200,17 @@ def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray) -> dict:
         raise ValueError("need 1 <= k <= l <= min(m, n)")
     if G.shape != (n, l):
         raise ValueError("G must be n x l")
-    Y = sketch(A, G)                                   # Step 2
+    Y = power_sketch(A, G, q)                          # Step 2 (Section 5.2)
+    return randomized_lu_from_sketch(A, k, Y)
+
+
+def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray) -> dict:
+    """Steps 3-8 of Algorithm 4.1 for a given sketch Y (m x l)."""
+    A = np.asarray(A, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    m, n = A.shape
+    if Y.shape[0] != m or not (1 <= k <= Y.shape[1] <= min(m, n)):
+        raise ValueError("need an m x l sketch with 1 <= k <= l <= min(m, n)")
     LUy, ipiv, p, info_y, diag_y = lu_partial_pivot(Y)  # Step 3
     Ly = unit_lower(LUy, k)                            # Step 4
     B = pinv_apply(Ly, A[p, :])                        # Step 5

@@ -382,6 +382,88 @@ def test_small_config_magnitude():
 
 
 # ---------------------------------------------------------------------------
+# Section 5.2: power iterations, Y = (A A^*)^q A G with LU normalization
+# ---------------------------------------------------------------------------
+
+
+def _plain_power_sketch(A, G, q):
+    """(A A^T)^q A G by plain products, with no normalization."""
+    Y = A @ G
+    for _ in range(q):
+        Y = A @ (A.T @ Y)
+    return Y
+
+
+def test_lu_normalize_equals_lapack_p_times_l():
+    # scipy.linalg.lu (LAPACK getrf) gives X = P L U; the normalized block
+    # is P L = X U^{-1}, in X's row order
+    for seed, shape in ((63, (50, 7)), (64, (31, 31)), (65, (200, 12))):
+        X = workloads.gaussian(shape, seed)
+        P, Lsc, Usc = scipy.linalg.lu(X)
+        N = rlu.lu_normalize(X)
+        np.testing.assert_allclose(N, P @ Lsc, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(N @ Usc, X, rtol=0, atol=1e-12 * np.abs(X).max())
+        assert np.abs(N).max() <= 1.0
+
+
+@pytest.mark.parametrize("q", [1, 2])
+@pytest.mark.parametrize("shape", [(70, 70), (90, 60), (60, 90)])
+def test_power_sketch_gives_the_factors_of_the_plain_product(q, shape):
+    # each normalization multiplies the block on the right by an upper
+    # triangular matrix, so Steps 3-8 on the normalized sketch and on the
+    # plain (A A^T)^q A G agree: same pivots, same factors up to rounding
+    m, n = shape
+    k, l = 6, 9
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), 12.0), 61)
+    G = workloads.gaussian((n, l), 62)
+    got = rlu.randomized_lu(A, k, l, G, q=q)
+    ref = rlu.randomized_lu_from_sketch(A, k, _plain_power_sketch(A, G, q))
+    np.testing.assert_array_equal(got["ipiv"], ref["ipiv"])
+    np.testing.assert_array_equal(got["p"], ref["p"])
+    np.testing.assert_array_equal(got["q"], ref["q"])
+    np.testing.assert_allclose(got["L"], ref["L"], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(got["U"], ref["U"], rtol=0, atol=1e-9 * np.abs(ref["U"]).max())
+    # and the sketch spans the same columns as the plain product
+    Yp = _plain_power_sketch(A, G, q)
+    Qp, _ = np.linalg.qr(Yp)
+    np.testing.assert_allclose(Qp @ (Qp.T @ got["Y"]), got["Y"], rtol=0,
+                               atol=1e-9 * np.abs(got["Y"]).max())
+
+
+def test_power_iterations_with_q_zero_are_step_2():
+    A = workloads.spectral_matrix(80, 70, workloads.exp_decay(70, 6.0), 66)
+    G = workloads.gaussian((70, 10), 67)
+    np.testing.assert_array_equal(rlu.power_sketch(A, G, 0), A @ G)
+    a, b = rlu.randomized_lu(A, 8, 10, G), rlu.randomized_lu(A, 8, 10, G, q=0)
+    np.testing.assert_array_equal(a["L"], b["L"])
+    np.testing.assert_array_equal(a["U"], b["U"])
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_power_iterations_exact_rank_reconstruction(q):
+    A = workloads.low_rank_plus_noise(150, 120, 9, 0.0, 68)
+    G = workloads.gaussian((120, 12), 69)
+    out = rlu.randomized_lu(A, 9, 12, G, q=q)
+    assert rlu.relative_residual(A, out) < 1e-12
+
+
+def test_power_iterations_lower_the_error_on_slow_decay():
+    # Section 5.2: on sigma_j = 100 / (9 + j)^2 the error falls with q and
+    # never drops below sigma_{k+1} (Eckart-Young)
+    m, n, k, l = 240, 200, 15, 20
+    sig = workloads.slow_decay(n)
+    sig = sig / sig[0]
+    A = workloads.spectral_matrix(m, n, sig, 70)
+    errs = []
+    for q in (0, 1, 2):
+        G = workloads.gaussian((n, l), 71)
+        errs.append(rlu.relative_residual(A, rlu.randomized_lu(A, k, l, G, q=q)))
+    assert errs[1] < 0.8 * errs[0]
+    assert errs[2] < errs[1]
+    assert min(errs) >= sig[k] * (1 - 1e-9)
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: each broken copy of a step must fail a pin above
 # ---------------------------------------------------------------------------
 
@@ -411,12 +493,33 @@ def _broken_variants():
         Q, R = np.linalg.qr(Ly)
         return scipy.linalg.solve_triangular(R, Q.T @ PA, lower=False, trans=1)
 
-    return {"wrong_sign_update": ("lu", wrong_sign_update),
+    def normalize_keeps_pivot_order(X):
+        LU, _, _, _, _ = rlu.lu_partial_pivot(X)
+        return rlu.unit_lower(LU, X.shape[1])
+
+    def power_without_transpose(A, G, q):
+        Y = rlu.sketch(A, G)
+        for _ in range(q):
+            Y = A @ rlu.lu_normalize(A @ rlu.lu_normalize(Y))
+        return Y
+
+    def power_one_round_short(A, G, q):
+        Y = rlu.sketch(A, G)
+        for _ in range(q - 1):
+            Y = A @ rlu.lu_normalize(A.T @ rlu.lu_normalize(Y))
+        return Y
+
+    return {"normalize_keeps_pivot_order": ("normalize", normalize_keeps_pivot_order),
+            "power_without_transpose": ("power", power_without_transpose),
+            "power_one_round_short": ("power", power_one_round_short),
+            "wrong_sign_update": ("lu", wrong_sign_update),
             "max_not_abs": ("lu", max_not_abs),
             "transposed_projection": ("pinv", transposed_projection)}
 
 
-@pytest.mark.parametrize("name", ["wrong_sign_update", "max_not_abs", "transposed_projection"])
+@pytest.mark.parametrize("name", ["wrong_sign_update", "max_not_abs", "transposed_projection",
+                                  "normalize_keeps_pivot_order", "power_without_transpose",
+                                  "power_one_round_short"])
 def test_planted_mistakes_are_caught(name, monkeypatch):
     kind, fn = _broken_variants()[name]
     if kind == "lu":
@@ -424,8 +527,19 @@ def test_planted_mistakes_are_caught(name, monkeypatch):
                             lambda Y: fn(Y)[:4] + ({"piv_abs": np.ones(Y.shape[1]),
                                                      "gap": np.ones(Y.shape[1]),
                                                      "max_abs": 1.0},))
-    else:
+    elif kind == "pinv":
         monkeypatch.setattr(rlu, "pinv_apply", fn)
+    else:
+        monkeypatch.setattr(rlu, "lu_normalize" if kind == "normalize" else "power_sketch", fn)
+    if kind in ("normalize", "power"):
+        failed = False
+        for q in (1, 2):
+            try:
+                test_power_sketch_gives_the_factors_of_the_plain_product(q, (70, 70))
+            except AssertionError:
+                failed = True
+        assert failed, name
+        return
     failed = False
     for t in (test_lu_partial_pivot_equals_lapack_getrf,
               test_projection_identity_of_the_proof,
