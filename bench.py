@@ -9,7 +9,8 @@ sketch GEMM, pivoted LU of Y, Gram matrix and its inverse, projection GEMM,
 pivoted LU of B^T, assembly of L and U) on a device-resident input; for the
 batched workload a step is one rlu_factor_batched call over 256 problems.
 Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
-under "forms", the same matrix through the FP32 path, the 16384 x 16384
+under "forms", the same matrix through the FP32 path and with one power
+iteration (Section 5.2), the 16384 x 16384
 mixed-precision configuration beside the FP64 path on the same matrix, the
 256-problem batch, and the served request stream (throughput with p50/p99
 latency; disable the extra measurements with --forms none).  Only one GPU is used; --gpus N with
@@ -265,20 +266,22 @@ def run_single(rlu, torch, np, name, steps, warmup, input_kind="spectral", check
     return res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works)
 
 
-def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup):
+def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_iters=0):
     h = rlu.Handle(0)
     h.set_timing(2)  # one event pair per call in the timed region (the sketch product)
     st = torch.cuda.current_stream()
     out = None
     for _ in range(warmup):
-        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st)
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st,
+                         power_iters=power_iters)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     t0 = time.perf_counter()
     for i in range(steps):
         evs[i][0].record(st)
-        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st)
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st,
+                         power_iters=power_iters)
         evs[i][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -287,7 +290,8 @@ def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup):
     h.set_timing(True)  # every phase, in a pass after the timed region
     nph = min(steps, 5)
     for _ in range(nph):
-        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out)
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
+                         power_iters=power_iters)
     torch.cuda.synchronize()
     ph = [h.phase_times(b) for b in range(nph)]
     ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0]}
@@ -526,8 +530,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp32,batch,mixed,serve",
-                    help="extra measurements in the same line: comma list of fp32, batch, "
+    ap.add_argument("--forms", default="fp32,power,batch,mixed,serve",
+                    help="extra measurements in the same line: comma list of fp32, power, batch, "
                          "mixed, serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
@@ -643,6 +647,23 @@ def main():
             "speedup_vs_fp64": (n32 / w32) / res["value"]}
         log(f"fp32 form: {n32 / w32:.1f}/s residual {r32:.3e}")
         del A32, o32
+    if "power" in forms and name == "exp8192":
+        # Section 5.2: one power iteration, Y = (A A^T) A G with the LU
+        # normalization, on the same matrix and sketch seed
+        outp, vp, msp, latp, php = timed_calls(rlu, torch, np, A, k, l, sseed, None,
+                                               max(5, args.steps // 3), 2, power_iters=1)
+        rp = power_residual(A, outp.L, outp.U, outp.p, outp.q)
+        r0 = res.get("rel_residual")
+        result["forms"]["power_q1"] = {
+            "workload": WORKLOADS["exp8192"][8] + ", q = 1 power iteration",
+            "value": vp, "unit": "factorizations/s", "ms_per_step": msp,
+            "latency_ms": {"p50": float(np.percentile(latp, 50)),
+                           "p99": float(np.percentile(latp, 99))},
+            "phase_ms": php, "rel_residual": rp, "rel_residual_q0": r0,
+            "error_ratio_vs_q0": rp / r0 if r0 else None,
+            "info": outp.info.cpu().tolist()}
+        log(f"power form: {vp:.1f}/s ({msp:.2f} ms), residual {rp:.3e} against {r0}")
+        del outp
     if "mixed" in forms:
         result["forms"]["mixed16384"] = run_mixed(rlu, torch, np, 8)
     if "batch" in forms:

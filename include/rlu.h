@@ -98,7 +98,15 @@ typedef struct {
   const void* G;      /* optional caller G (n x l, storage dtype, device);    */
   int64_t ldg;        /*   NULL => generated from seed                        */
   uint32_t flags;
+  int32_t power_iters; /* q of Section 5.2, 0..RLU_MAX_POWER_ITERS: Step 2
+                          becomes Y = (A A^T)^q A G, each product but the last
+                          replaced by the unit-lower factor of its pivoted LU
+                          (same column space; see rlu_factor).  0 = plain
+                          Step 2.  rlu_factor only: the batched form and the
+                          server return RLU_ERR_UNSUPPORTED for q != 0. */
 } rlu_problem_t;
+
+#define RLU_MAX_POWER_ITERS 16
 
 /* Step 1 generator: key = (seed mod 2^32, seed div 2^32); element (i, j) of G
  * has column-major index e = i + j*n and uses counter (e/2 mod 2^32,
@@ -137,6 +145,16 @@ rlu_status_t rlu_destroy(rlu_handle_t h);
 rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
 
 /* Algorithm 4.1, Steps 1-8, enqueued on `stream`.
+ *
+ * Power iterations (Section 5.2, pb->power_iters = q > 0): Step 2 computes
+ * A G and then q times one product with A^T and one with A.  Before each
+ * product after the first, the current block (m x l or n x l) is replaced
+ * by the unit-lower factor of its partial-pivot LU in its own row order
+ * (P^T L = X U^{-1}), so the entries stay bounded by 1; in exact arithmetic
+ * this changes neither the pivots nor the factors of Steps 3-8 relative to
+ * the plain (A A^T)^q A G.  A zero pivot inside such a normalization is not
+ * reported (Step 3 reports the rank of the final sketch).  The optional
+ * diagnostic Y is the final sketch.
  *
  * Zero pivots: in Step 3 the LAPACK getf2 convention holds (no scaling, no
  * update, info[0] = first such step); in Step 6, column j of L_b below the

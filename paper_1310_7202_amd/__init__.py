@@ -50,7 +50,10 @@ class Problem(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
                 ("l", ctypes.c_int64), ("dtype", ctypes.c_int), ("precision", ctypes.c_int),
                 ("seed", ctypes.c_uint64), ("G", ctypes.c_void_p), ("ldg", ctypes.c_int64),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("power_iters", ctypes.c_int32)]
+
+
+MAX_POWER_ITERS = 16
 
 
 class Buffers(ctypes.Structure):
@@ -195,8 +198,9 @@ def default_handle(device: int = 0) -> Handle:
     return h
 
 
-def workspace_size(m, n, k, l, dtype=F64, precision=PREC_FP64, with_g=False) -> int:
-    pb = Problem(m, n, k, l, dtype, precision, 0, None, 0, 0)
+def workspace_size(m, n, k, l, dtype=F64, precision=PREC_FP64, with_g=False,
+                   power_iters=0) -> int:
+    pb = Problem(m, n, k, l, dtype, precision, 0, None, 0, 0, power_iters)
     if with_g:
         pb.G = 1
         pb.ldg = n
@@ -222,7 +226,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _prepare(A, k, l, precision, seed, G, diagnostics, out):
+def _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters=0):
     """ctypes problem and buffer structs for one factorization (allocating
     the outputs that `out` does not provide)."""
     import torch
@@ -255,7 +259,8 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out):
             out.B = torch.empty((n, k), dtype=ytype, device=dev).t()
             out.ipiv = torch.empty(l, dtype=torch.int32, device=dev)
             out.qpiv = torch.empty(k, dtype=torch.int32, device=dev)
-    pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, FLAG_DIAGNOSTICS if diagnostics else 0)
+    pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, FLAG_DIAGNOSTICS if diagnostics else 0,
+                 power_iters)
     if G is not None:
         if G.shape != (n, l) or G.stride(0) != 1 or G.dtype != A.dtype:
             raise ValueError("G must be an n x l column-major tensor of A's dtype")
@@ -276,15 +281,16 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out):
 
 def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
            diagnostics: bool = False, handle: Handle | None = None, stream=None,
-           out: Factors | None = None) -> Factors:
+           out: Factors | None = None, power_iters: int = 0) -> Factors:
     """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
     float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
     tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
     p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
-    current torch stream by default) and not synchronized."""
+    current torch stream by default) and not synchronized.  ``power_iters``
+    is q of the power scheme, Y = (A A^T)^q A G (Section 5.2)."""
     import torch
 
-    pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out)
+    pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters)
     h = handle or default_handle(A.device.index or 0)
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),

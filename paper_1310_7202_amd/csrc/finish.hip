@@ -77,6 +77,21 @@ __global__ void __launch_bounds__(256) convert2d_kernel(const TI* __restrict__ s
   }
 }
 
+// Dense copy of the unit-lower factor that a pivoted LU left in place (rows
+// never moved): out(i, c) = Lv(i, c) for c < cols, converted to TO.
+template <typename TO>
+__global__ void __launch_bounds__(256) lv_dense_kernel(const double* __restrict__ X, int64_t ldx,
+                                                       const int* __restrict__ rstep,
+                                                       TO* __restrict__ out, int64_t ldo,
+                                                       int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, c = e / rows;
+    out[i + c * ldo] = (TO)lv_value<double>(X[i + c * ldx], (int)c, rstep[i]);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) copy2d_kernel(const T* __restrict__ src, int64_t lds,
                                                      T* __restrict__ dst, int64_t ldd,
@@ -225,6 +240,19 @@ template hipError_t launch_convert2d<double, float>(const double*, int64_t, floa
                                                     int64_t, int64_t, hipStream_t);
 template hipError_t launch_convert2d<float, double>(const float*, int64_t, double*, int64_t,
                                                     int64_t, int64_t, hipStream_t);
+
+template <typename TO>
+hipError_t launch_lv_dense(const double* X, int64_t ldx, const int* rstep, TO* out, int64_t ldo,
+                           int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((lv_dense_kernel<TO>), dim3(grid_for(rows * cols)), dim3(256), 0, s, X, ldx,
+                     rstep, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+template hipError_t launch_lv_dense<double>(const double*, int64_t, const int*, double*, int64_t,
+                                            int64_t, int64_t, hipStream_t);
+template hipError_t launch_lv_dense<float>(const double*, int64_t, const int*, float*, int64_t,
+                                           int64_t, int64_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,

@@ -4,6 +4,9 @@
 // Launch sequence of rlu_factor (FP64 path):
 //   Step 1  gaussian            G (n x l) from the seed, unless given
 //   Step 2  gemm                Y = A G
+//           q times (Section 5.2, power iterations):
+//             panel_lu(Y), gemm Z^T = Lv^T A, transpose, panel_lu(Z),
+//             lv_dense, gemm Y = A Lv(Z)
 //   Step 3  panel_lu(Y)         packed LU of Y in place, rows never moved
 //   Step 5  gemm (split-K)      S = Lv^T Lv        (Gram matrix)
 //           spd_inverse         S <- S^{-1}        (k <= 64: on a second stream,
@@ -29,7 +32,7 @@
 static const char* const kPhaseNames[PH_COUNT] = {
     "gaussian", "sketch_gemm", "panel_lu_y", "gram_gemm", "gram_inverse", "project_gemm",
     "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm", "sketch_splitk_sum",
-    "project_splitk_sum"};
+    "project_splitk_sum", "power_iterations"};
 
 namespace rlu_detail {
 
@@ -75,7 +78,8 @@ struct Layout {
   size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0, flags = 0, xch = 0;
   size_t total = 0;
   size_t u12 = 0, bt = 0;
-  BlockedPanel py{}, pb{};
+  size_t zt = 0, z = 0, piv_z = 0, ipiv_z = 0;  // power iterations (Section 5.2)
+  BlockedPanel py{}, pb{}, pz{};
 };
 
 bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
@@ -87,7 +91,9 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   };
   const size_t d = sizeof(double);
   const size_t sa = pb.dtype == RLU_F32 ? sizeof(float) : sizeof(double);
-  take(L.G, pb.G ? 0 : (size_t)n * l * sa);
+  const bool power = pb.power_iters > 0;
+  // G, or with power iterations the normalized n x l block that replaces it
+  take(L.G, pb.G && !power ? 0 : (size_t)n * l * sa);
   take(L.Y, (size_t)m * l * d);
   // one partial-sum area, sized for the largest automatic split-K product
   size_t part = gemm_auto_partial_elems(m, l, n, OpA::Plain);
@@ -95,9 +101,11 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   part = std::max(part, gemm_auto_partial_elems(k, n, m, OpA::LvT));
   part = std::max(part, gemm_auto_partial_elems(k, n, k, OpA::Plain));
   part = std::max(part, gemm_auto_partial_elems(m, k, k, OpA::Lv));
+  if (power) part = std::max(part, gemm_auto_partial_elems(l, n, m, OpA::LvT));
   if (pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16) {
     part = std::max(part, gemm_lp_partial_elems(m, l, n));
     part = std::max(part, gemm_lp_partial_elems(k, n, m));
+    if (power) part = std::max(part, gemm_lp_partial_elems(l, n, m));
   }
   take(L.part, part * d);
   take(L.S, (size_t)k * k * d);
@@ -114,12 +122,24 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   take(L.piv_b, (size_t)k * 4);
   take(L.ipiv_b, (size_t)k * 4);
   take(L.flags, 64);
+  take(L.zt, power ? (size_t)l * n * d : 0);
+  take(L.z, power ? (size_t)n * l * d : 0);
+  take(L.piv_z, power ? (size_t)l * 4 : 0);
+  take(L.ipiv_z, power ? (size_t)l * 4 : 0);
   L.py = plan_blocked((int)m, (int)l, cus);
   L.pb = plan_blocked((int)n, (int)k, cus);
   if (!L.py.ok || !L.pb.ok) return false;
-  take(L.xch, std::max(std::max(L.py.main.xch_bytes, L.py.last.xch_bytes),
-                       std::max(L.pb.main.xch_bytes, L.pb.last.xch_bytes)));
-  take(L.u12, std::max(L.py.u12_elems, L.pb.u12_elems) * d);
+  size_t xch = std::max(std::max(L.py.main.xch_bytes, L.py.last.xch_bytes),
+                        std::max(L.pb.main.xch_bytes, L.pb.last.xch_bytes));
+  size_t u12 = std::max(L.py.u12_elems, L.pb.u12_elems);
+  if (power) {
+    L.pz = plan_blocked((int)n, (int)l, cus);
+    if (!L.pz.ok) return false;
+    xch = std::max(xch, std::max(L.pz.main.xch_bytes, L.pz.last.xch_bytes));
+    u12 = std::max(u12, L.pz.u12_elems);
+  }
+  take(L.xch, xch);
+  take(L.u12, u12 * d);
   take(L.bt, L.pb.nblocks > 1 ? (size_t)n * k * d : 0);
   L.total = off;
   return true;
@@ -148,6 +168,7 @@ rlu_status_t validate(const rlu_problem_t* pb) {
   if (pb->G && pb->ldg < pb->n) return RLU_ERR_INVALID_ARG;
   if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS))
     return RLU_ERR_INVALID_ARG;
+  if (pb->power_iters < 0 || pb->power_iters > RLU_MAX_POWER_ITERS) return RLU_ERR_INVALID_ARG;
   if (!spd_inverse_supported(pb->k)) return RLU_ERR_UNSUPPORTED;
   return RLU_OK;
 }
@@ -278,24 +299,80 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     G = Gw;
     ldg = n;
   }
-  // Step 2: Y = A G
-  {
+  // Y (m x l) = A X for an n x l block X of the storage type (Step 2's
+  // product); phase ids < 0 leave it untimed
+  auto times_a = [&](const T* X, int64_t ldx, int ph_gemm, int ph_sum) -> rlu_status_t {
     GemmDesc d{};
     d.M = m; d.N = l; d.K = n;
     d.A = io.A; d.lda = io.lda; d.opa = OpA::Plain;
-    d.B = G; d.ldb = ldg; d.opb = OpB::Plain;
+    d.B = X; d.ldb = ldx; d.opb = OpB::Plain;
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     int ks = 1;
     d.no_sum = true; d.ksplit_out = &ks;
     {
-      PhaseScope ph(h, PH_SKETCH, s);
+      PhaseScope ph(h, ph_gemm, s);
       if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
       else HIP_TRY((launch_gemm_t<T, T, T, double>(d, s)));
     }
     if (ks > 1) {
-      PhaseScope ph(h, PH_SKETCH_SUM, s);
+      PhaseScope ph(h, ph_sum, s);
       HIP_TRY(launch_splitk_sum_f64(m, l, ks, (const double*)d.partial, Y, m, nullptr, s));
+    }
+    return RLU_OK;
+  };
+  // Out (rows x n, FP64) = Lv^T A with Lv (m x rows) the unit-lower factor
+  // of the pivoted LU of Y (the product of Step 5 and of the power scheme)
+  auto lvt_times_a = [&](double* Out, int64_t rows, int ph_gemm, int ph_sum) -> rlu_status_t {
+    GemmDesc d{};
+    d.M = rows; d.N = n; d.K = m;
+    d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
+    d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
+    d.C = Out; d.ldc = rows;
+    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    int ks = 1;
+    d.no_sum = true; d.ksplit_out = &ks;
+    {
+      PhaseScope ph(h, ph_gemm, s);
+      if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
+      else HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
+    }
+    if (ks > 1) {
+      PhaseScope ph(h, ph_sum, s);
+      HIP_TRY(launch_splitk_sum_f64(rows, n, ks, (const double*)d.partial, Out, rows, nullptr, s));
+    }
+    return RLU_OK;
+  };
+
+  // Step 2: Y = A G
+  {
+    rlu_status_t st = times_a(G, ldg, PH_SKETCH, PH_SKETCH_SUM);
+    if (st != RLU_OK) return st;
+  }
+  // Section 5.2: q power iterations, Y <- A (A^T Y).  Before each product
+  // the block is replaced by the unit-lower factor of its pivoted LU in its
+  // own row order (bounded entries, same column space).  The normalizations
+  // use the positions and row steps of Steps 3 and 6 as scratch and their
+  // zero-pivot words go to flags[3].
+  if (pb.power_iters > 0) {
+    PhaseScope ph(h, PH_POWER, s);
+    double* Zt = at<double>(ws, Ly.zt);
+    double* Z = at<double>(ws, Ly.z);
+    T* Gz = at<T>(ws, Ly.G);
+    double* u12 = at<double>(ws, Ly.u12);
+    for (int it = 0; it < pb.power_iters; ++it) {
+      rlu_status_t st = run_panel(Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
+                                  flags + 3, flags + 2, xch, u12, s);
+      if (st != RLU_OK) return st;
+      st = lvt_times_a(Zt, l, -1, -1);  // Z^T = Lv(Y)^T A  (l x n)
+      if (st != RLU_OK) return st;
+      HIP_TRY(launch_transpose(Zt, l, Z, n, l, n, s));
+      st = run_panel(Z, n, (int)n, (int)l, Ly.pz, pos_b, rstep_b, at<int>(ws, Ly.piv_z),
+                     at<int>(ws, Ly.ipiv_z), flags + 3, flags + 2, xch, u12, s);
+      if (st != RLU_OK) return st;
+      HIP_TRY(launch_lv_dense<T>(Z, n, rstep_b, Gz, n, n, l, s));
+      st = times_a(Gz, n, -1, -1);      // Y = A Lv(Z)
+      if (st != RLU_OK) return st;
     }
   }
   if (diag && io.Y) {
@@ -336,23 +413,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   }
   if (overlap) HIP_TRY(hipEventRecord(h->ev_join, h->side));
   {
-    GemmDesc d{};
-    d.M = k; d.N = n; d.K = m;
-    d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
-    d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
-    d.C = C; d.ldc = k;
-    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
-    int ks = 1;
-    d.no_sum = true; d.ksplit_out = &ks;
-    {
-      PhaseScope ph(h, PH_PROJECT, s);
-      if (lp) HIP_TRY(launch_gemm_lp(d, fp16, s));
-      else HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
-    }
-    if (ks > 1) {
-      PhaseScope ph(h, PH_PROJECT_SUM, s);
-      HIP_TRY(launch_splitk_sum_f64(k, n, ks, (const double*)d.partial, C, k, nullptr, s));
-    }
+    rlu_status_t st = lvt_times_a(C, k, PH_PROJECT, PH_PROJECT_SUM);
+    if (st != RLU_OK) return st;
   }
   if (overlap) HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {

@@ -741,6 +741,7 @@ rlu_status_t batched_validate(int count, const rlu_problem_t* pbs, const rlu_buf
       if (st != RLU_OK) return st;
     }
     if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
+    if (pbs[i].power_iters != 0) return RLU_ERR_UNSUPPORTED;
     if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
       return RLU_ERR_INVALID_ARG;
   }

@@ -15,7 +15,7 @@
 // Phases of rlu_factor / rlu_factor_batched that the timing facility reports.
 enum Phase {
   PH_GAUSSIAN = 0, PH_SKETCH, PH_PANEL_Y, PH_GRAM, PH_GRAM_INV, PH_PROJECT, PH_SOLVE,
-  PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_SKETCH_SUM, PH_PROJECT_SUM, PH_COUNT
+  PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_SKETCH_SUM, PH_PROJECT_SUM, PH_POWER, PH_COUNT
 };
 
 struct TimingSlot {
@@ -89,12 +89,13 @@ rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t*
                                 const rlu_buffers_t* ios, hipStream_t s, void* ws,
                                 size_t ws_bytes, hipEvent_t gate);
 
-// Event pair around a phase when timing is on (recorded on the phase's stream).
+// Event pair around a phase when timing is on (recorded on the phase's
+// stream); id < 0 records nothing.
 struct PhaseScope {
   rlu_handle_s* h; int id; hipStream_t s; bool on;
   PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
       : h(h_), id(id_), s(s_),
-        on(h_->timing && h_->cur && (h_->timing_mode != 2 || id_ == PH_SKETCH)) {
+        on(id_ >= 0 && h_->timing && h_->cur && (h_->timing_mode != 2 || id_ == PH_SKETCH)) {
     if (on) {
       h->cur->used[id] = true;
       hipEventRecord(h->cur->ev[id][0], s);

@@ -178,6 +178,12 @@ template <typename T>
 hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,
                          int64_t cols, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s);
+// out (rows x cols, TO) = the unit-lower factor Lv held in place in X by a
+// pivoted LU with row steps rstep (see lv_value); the normalization of the
+// power iterations (Section 5.2)
+template <typename TO>
+hipError_t launch_lv_dense(const double* X, int64_t ldx, const int* rstep, TO* out, int64_t ldo,
+                           int64_t rows, int64_t cols, hipStream_t s);
 hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
                              int32_t* info_out, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);

@@ -46,8 +46,8 @@ def test_check_info_mapping(rlu):
     assert rlu.check_info([0, 0, 1]) == -3
 
 
-def _ws(rlu, m, n, k, l, dtype=0, prec=0, G=None, ldg=0, flags=0):
-    pb = rlu.Problem(m, n, k, l, dtype, prec, 0, G, ldg, flags)
+def _ws(rlu, m, n, k, l, dtype=0, prec=0, G=None, ldg=0, flags=0, power_iters=0):
+    pb = rlu.Problem(m, n, k, l, dtype, prec, 0, G, ldg, flags, power_iters)
     out = ctypes.c_size_t()
     st = rlu.lib().rlu_workspace_size(ctypes.byref(pb), ctypes.byref(out))
     return st, out.value
@@ -79,6 +79,32 @@ def test_workspace_size_grows_with_problem(rlu):
     assert st3 == 0 and c < b
     # the dominant terms: Y (m l), C and B (2 k n) in FP64
     assert b >= 8 * (8192 * 210 + 2 * 200 * 8192)
+
+
+def test_power_iterations_range_and_workspace(rlu):
+    """Section 5.2: q in 0..RLU_MAX_POWER_ITERS; q > 0 adds the n x l blocks
+    of the power scheme (Z^T and Z in FP64, the normalized block in the
+    storage type) even when the caller passes G."""
+    assert rlu.MAX_POWER_ITERS == 16
+    assert _ws(rlu, 100, 100, 5, 8, power_iters=-1)[0] == -1
+    assert _ws(rlu, 100, 100, 5, 8, power_iters=17)[0] == -1
+    st0, a = _ws(rlu, 4096, 3000, 40, 48)
+    st1, b = _ws(rlu, 4096, 3000, 40, 48, power_iters=1)
+    st2, c = _ws(rlu, 4096, 3000, 40, 48, power_iters=16)
+    assert st0 == st1 == st2 == 0
+    assert b - a >= 2 * 8 * 3000 * 48 - 4096 and c == b  # slots are 256-byte aligned
+    st3, d = _ws(rlu, 4096, 3000, 40, 48, G=1, ldg=3000, power_iters=1)
+    assert st3 == 0 and d == b
+    # the batched form and the server do not take power iterations
+    pb = rlu.Problem(512, 512, 10, 15, 0, 0, 0, None, 0, 0, 1)
+    out = ctypes.c_size_t()
+    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -8
+    io = rlu.Buffers()
+    io.A = io.L = io.U = io.p = io.q = io.info = 1
+    io.lda = io.ldl = 512
+    io.ldu = 10
+    assert rlu.lib().rlu_factor_batched(ctypes.c_void_p(1), 1, ctypes.byref(pb),
+                                        ctypes.byref(io), None) == -8
 
 
 def test_factor_rejects_null_handle_and_buffers(rlu):

@@ -34,11 +34,13 @@ def rlu():
     return m
 
 
-def run_and_compare(rlu, A, k, l, G, label=""):
-    print(f"[parity] {label} m={A.shape[0]} n={A.shape[1]} k={k} l={l}", flush=True)
-    out = rlu.factor(to_dev_colmajor(A), k, l, G=to_dev_colmajor(G), diagnostics=True)
+def run_and_compare(rlu, A, k, l, G, label="", power=0):
+    print(f"[parity] {label} m={A.shape[0]} n={A.shape[1]} k={k} l={l} power={power}",
+          flush=True)
+    out = rlu.factor(to_dev_colmajor(A), k, l, G=to_dev_colmajor(G), diagnostics=True,
+                     power_iters=power)
     torch.cuda.synchronize()
-    o = orl.randomized_lu(A, k, l, G)
+    o = orl.randomized_lu(A, k, l, G, q=power)
     info = to_host(out.info)
     assert info[2] == 0, "pivot exchange failed"
     assert (int(info[0]), int(info[1])) == o["info"]
@@ -51,7 +53,15 @@ def run_and_compare(rlu, A, k, l, G, label=""):
     assert np.all(np.triu(L[:k], 1) == 0.0)
     assert np.all(np.tril(U, -1) == 0.0)
     # Step 2
-    assert rel_maxdiff(to_host(out.Y), o["Y"]) < 1e-13
+    if power == 0:
+        assert rel_maxdiff(to_host(out.Y), o["Y"]) < 1e-13
+    else:
+        # power scheme: the normalizations may round differently past the
+        # numerical rank, so compare what Steps 3-8 use, the span of the
+        # leading k columns of the sketch
+        Yg = to_host(out.Y)[:, :k]
+        Qo, _ = np.linalg.qr(o["Y"][:, :k])
+        assert np.abs(Yg - Qo @ (Qo.T @ Yg)).max() < 1e-10 * np.abs(Yg).max()
     # Step 3 pivots on the decided prefix
     gy = orl.pivot_gate(o["diag_y"])
     np.testing.assert_array_equal(to_host(out.ipiv)[:gy], o["ipiv"][:gy])
@@ -243,3 +253,32 @@ def test_exact_pivot_ties_go_to_lowest_position(rlu, m, seed):
     assert to_host(out.info)[2] == 0
     np.testing.assert_array_equal(to_host(out.Y), A[:, :l])
     np.testing.assert_array_equal(to_host(out.ipiv)[:upto], ipiv[:upto])
+
+
+@pytest.mark.parametrize("m,n,k,l,rate,q", [
+    (512, 512, 10, 15, 0.0, 1),         # the 512^2 rank-10 configuration
+    (512, 512, 10, 15, 0.0, 2),
+    (3000, 2500, 50, 60, 20.0, 1),      # several workgroups per panel, ragged tails
+    (3000, 2500, 50, 60, 20.0, 3),
+    (1500, 2600, 33, 41, 12.0, 1),      # m < n: the n x l normalization is the taller
+    (97, 131, 5, 9, 3.0, 2),            # sizes below one tile
+    (200, 64, 64, 64, 30.0, 1),         # l = min(m, n)
+])
+def test_power_iterations(rlu, m, n, k, l, rate, q):
+    """Section 5.2: Y = (A A^T)^q A G with the LU normalization, against the
+    oracle's power scheme."""
+    if rate == 0.0:
+        A, k, l = workloads.config_small(101)
+    else:
+        A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), rate), 1100 + m)
+    G = workloads.gaussian((A.shape[1], l), 2100 + n + q)
+    run_and_compare(rlu, A, k, l, G, f"power rate={rate}", power=q)
+
+
+def test_power_iterations_blocked_normalization(rlu):
+    """The n x l normalization (16384 x 300) factored in column blocks."""
+    m, n, k, l = 2000, 16384, 290, 300
+    A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 660)
+    G = workloads.gaussian((n, l), 661)
+    run_and_compare(rlu, A, k, l, G, "power blocked", power=1)
+

@@ -5,7 +5,9 @@ the GPU factors may exceed the oracle's by at most 1e-3, both computed the
 same way on the same FP32-stored A (upcast to FP64) with the same G; the
 structure of the factors is exact; and the pivots agree on every step whose
 choice is decided by a wide margin (relative gap >= 1e-3 and magnitude >= 1e3
-FP32 unit roundoffs of max|Y|, far above FP32 rounding of the sketch).
+FP32 unit roundoffs of max|Y|, far above FP32 rounding of the sketch; for
+the BF16 / FP16 products a gap >= 1/4 and a magnitude >= 16 unit roundoffs
+of the 16-bit format).
 """
 import numpy as np
 import pytest
@@ -34,20 +36,20 @@ def rel_residual(A, L, U, p, q):
     return np.linalg.norm(L @ U - A[np.ix_(p, q)], 2) / np.linalg.norm(A, 2)
 
 
-def check(rlu, A64, k, l, seed, precision, label):
+def check(rlu, A64, k, l, seed, precision, label, q=0):
     A32 = A64.astype(np.float32)
     A = A32.astype(np.float64)            # the matrix both sides factor
     m, n = A.shape
     G32 = workloads.gaussian((n, l), seed).astype(np.float32)
-    print(f"[precision] {label} m={m} n={n} k={k} l={l} prec={precision}", flush=True)
+    print(f"[precision] {label} m={m} n={n} k={k} l={l} prec={precision} q={q}", flush=True)
     out = rlu.factor(to_dev_colmajor(A32, dtype=torch.float32), k, l,
                      G=to_dev_colmajor(G32, dtype=torch.float32), precision=precision,
-                     diagnostics=True)
+                     diagnostics=True, power_iters=q)
     torch.cuda.synchronize()
     assert out.L.dtype == torch.float32 and out.U.dtype == torch.float32
     info = to_host(out.info)
     assert info[2] == 0
-    o = orl.randomized_lu(A, k, l, G32.astype(np.float64))
+    o = orl.randomized_lu(A, k, l, G32.astype(np.float64), q=q)
     L = to_host(out.L).astype(np.float64)
     U = to_host(out.U).astype(np.float64)
     p, q = to_host(out.p), to_host(out.q)
@@ -59,9 +61,16 @@ def check(rlu, A64, k, l, seed, precision, label):
     r_ora = rel_residual(A, o["L"], o["U"], o["p"], o["q"])
     print(f"  residual gpu {r_gpu:.3e} oracle {r_ora:.3e}", flush=True)
     assert r_gpu <= r_ora + BAR
-    # decided by a margin FP32 rounding of the sketch cannot flip: relative
-    # gap >= 1e-3 and magnitude >= 1e3 FP32 unit roundoffs of max|Y|
-    gy = orl.pivot_gate(o["diag_y"], u=2.0 ** -24, gap_min=1e-3, mag_factor=1e3)
+    # decided by a margin the rounding of the sketch cannot flip: for FP32,
+    # relative gap >= 1e-3 and magnitude >= 1e3 FP32 unit roundoffs of
+    # max|Y|; the 16-bit products round their operands to u = 2^-8 (BF16)
+    # or 2^-11 (FP16), so there the gap must be >= 1/4 and the pivot
+    # >= 16 u max|Y|
+    if precision == rlu.PREC_FP32:
+        gy = orl.pivot_gate(o["diag_y"], u=2.0 ** -24, gap_min=1e-3, mag_factor=1e3)
+    else:
+        u16 = 2.0 ** -8 if precision == rlu.PREC_MIXED_BF16 else 2.0 ** -11
+        gy = orl.pivot_gate(o["diag_y"], u=u16, gap_min=0.25, mag_factor=16)
     np.testing.assert_array_equal(to_host(out.ipiv)[:gy], o["ipiv"][:gy])
     return r_gpu, r_ora
 
@@ -149,3 +158,17 @@ def test_mixed_slow_decay_inverse_square(rlu, fp16):
     m = n = 2048
     A = workloads.spectral_matrix(m, n, workloads.inv_square(m), 77)
     check_mixed(rlu, A, 120, 130, 78, fp16, "mixed i^-2")
+
+
+@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("q", [1, 2])
+def test_power_iterations_reduced_precision(rlu, precision, q):
+    """Section 5.2 in the FP32 and mixed forms: the residual rule against the
+    oracle with the same q, on the paper's slowly decaying spectrum, where
+    the power scheme lowers the error."""
+    m, n, k, l = 2600, 1900, 40, 48
+    sig = workloads.slow_decay(n)
+    A64 = workloads.spectral_matrix(m, n, sig / sig[0], 1700 + q)
+    r_gpu, r_ora = check(rlu, A64, k, l, 1710 + q, precision, "power", q=q)
+    r0_gpu, _ = check(rlu, A64, k, l, 1710 + q, precision, "power q=0")
+    assert r_gpu < r0_gpu
