@@ -25,6 +25,10 @@ Pinned by (see ``tests/test_oracle_*.py``):
     right triangular factor); q = 0 is Step 2; exact rank-k reconstruction;
     the error falls with q on the paper's slowly decaying spectrum.
   * ``rlu.lu_normalize``       -- LAPACK getrf: P L from scipy.linalg.lu.
+  * ``rlu.lstsq_rank_deficient`` -- Algorithm 4.3: consistent rank-k systems
+    solved with at most k nonzeros; the residual equals LAPACK's least-squares
+    minimum (numpy.linalg.lstsq); A^{-1} b in the full-rank square case.
+  * ``rlu.upper_solve``        -- SciPy solve_triangular; a zero row gives 0.
   * ``bounds.xi``              -- Table 4.1 of the paper, 9 of 9 rows.
   * ``philox.philox4x32_10``   -- Random123 known-answer vectors.
   * ``philox.gaussian_matrix`` -- Box-Muller closed form on fixed uniforms and

@@ -226,6 +226,46 @@ def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray) -> dict:
     }
 
 
+def upper_solve(U1: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """z_1 = U_1^{-1} y for the k x k upper-triangular U_1 (Step 3 of
+    Algorithm 4.3), by back substitution, one right-hand side per column of
+    y.  A zero diagonal entry (a zero pivot of Step 6, whose row of U is
+    zero) makes z_1[j] a free variable; it is set to 0, as the paper sets
+    z_2."""
+    k = U1.shape[0]
+    y = np.array(y, dtype=np.float64, copy=True).reshape(k, -1)
+    z = np.zeros_like(y)
+    for j in range(k - 1, -1, -1):
+        rhs = y[j] - U1[j, j + 1:] @ z[j + 1:]
+        z[j] = rhs / U1[j, j] if U1[j, j] != 0.0 else 0.0
+    return z
+
+
+def lstsq_rank_deficient(out: dict, b: np.ndarray) -> np.ndarray:
+    """Algorithm 4.3, Steps 2-5, on the factors of Algorithm 4.1
+    (P A Q ~ L U): y = L^dagger P b, z_1 = U_1^{-1} y, z = (z_1; 0),
+    x = Q z.  b is m x r (or a vector); returns x (n x r, or a vector).
+
+    L^dagger is applied as a least-squares solve through the QR of L (as in
+    Step 5).  With the index-vector conventions of this module,
+    (P b)[i] = b[p[i]] and (Q z)[q[j]] = z[j].
+    """
+    L, U, p, q = out["L"], out["U"], out["p"], out["q"]
+    k = L.shape[1]
+    n = U.shape[1]
+    b = np.asarray(b, dtype=np.float64)
+    vec = b.ndim == 1
+    B = b.reshape(b.shape[0], -1)
+    c = B[p, :]                                      # P b
+    y = pinv_apply(L, c)                             # Step 2
+    z1 = upper_solve(U[:, :k], y)                    # Step 3
+    z = np.zeros((n, B.shape[1]))                    # Step 4: z_2 = 0
+    z[:k] = z1
+    x = np.empty_like(z)                             # Step 5: x = Q z
+    x[q, :] = z
+    return x[:, 0] if vec else x
+
+
 def permuted(A: np.ndarray, p: np.ndarray, q: np.ndarray) -> np.ndarray:
     """P A Q with the index-vector conventions of this module."""
     return np.asarray(A)[np.ix_(p, q)]

@@ -464,6 +464,66 @@ def test_power_iterations_lower_the_error_on_slow_decay():
 
 
 # ---------------------------------------------------------------------------
+# Algorithm 4.3: rank-deficient least squares on the factors
+# ---------------------------------------------------------------------------
+
+
+def _rank_k_problem(m, n, k, seed):
+    A = workloads.low_rank_plus_noise(m, n, k, 0.0, seed)
+    G = workloads.gaussian((n, k + 4), seed + 1)
+    return A, rlu.randomized_lu(A, k, k + 4, G)
+
+
+def test_lstsq_consistent_system_is_solved_with_k_nonzeros():
+    # rank(A) = k and b in range(A): the minimum of ||A x - b|| is 0, and x
+    # has at most k nonzero entries (the remark after Algorithm 4.3)
+    A, out = _rank_k_problem(150, 110, 8, 81)
+    x0 = workloads.gaussian((110, 2), 83)
+    b = A @ x0
+    x = rlu.lstsq_rank_deficient(out, b)
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+    assert np.all(np.count_nonzero(x, axis=0) <= 8)
+    xv = rlu.lstsq_rank_deficient(out, b[:, 0])
+    assert xv.shape == (110,)
+    np.testing.assert_allclose(xv, x[:, 0], rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+@pytest.mark.parametrize("shape,k", [((150, 110), 8), ((90, 140), 12), ((200, 200), 30)])
+def test_lstsq_residual_is_the_least_squares_minimum(shape, k):
+    # for a general b the residual equals the one of LAPACK's minimum-norm
+    # solution (numpy.linalg.lstsq): both minimize ||A x - b|| over all x
+    m, n = shape
+    A, out = _rank_k_problem(m, n, k, 85 + k)
+    b = workloads.gaussian((m, 3), 86 + k)
+    x = rlu.lstsq_rank_deficient(out, b)
+    xr = np.linalg.lstsq(A, b, rcond=None)[0]
+    r = np.linalg.norm(A @ x - b, axis=0)
+    rr = np.linalg.norm(A @ xr - b, axis=0)
+    np.testing.assert_allclose(r, rr, rtol=1e-10)
+
+
+def test_lstsq_full_rank_square_is_the_inverse():
+    # k = l = m = n: A x = b has the unique solution A^{-1} b
+    n = 60
+    A = workloads.spectral_matrix(n, n, workloads.exp_decay(n, 40.0), 87)
+    out = rlu.randomized_lu(A, n, n, workloads.gaussian((n, n), 88))
+    b = workloads.gaussian((n, 2), 89)
+    np.testing.assert_allclose(rlu.lstsq_rank_deficient(out, b), np.linalg.solve(A, b),
+                               rtol=0, atol=1e-9 * np.abs(np.linalg.solve(A, b)).max())
+
+
+def test_upper_solve_is_back_substitution():
+    U = np.triu(workloads.gaussian((9, 9), 90)) + 4 * np.eye(9)
+    y = workloads.gaussian((9, 2), 91)
+    np.testing.assert_allclose(rlu.upper_solve(U, y), scipy.linalg.solve_triangular(U, y),
+                               rtol=1e-13, atol=1e-13)
+    # a zero pivot of Step 6 leaves a zero row of U: its unknown is free, set to 0
+    Z = np.array([[2.0, 1.0, 1.0], [0.0, 0.0, 0.0], [0.0, 0.0, 4.0]])
+    np.testing.assert_allclose(rlu.upper_solve(Z, np.array([3.0, 0.0, 8.0]))[:, 0],
+                               [0.5, 0.0, 2.0])
+
+
+# ---------------------------------------------------------------------------
 # Planted mistakes: each broken copy of a step must fail a pin above
 # ---------------------------------------------------------------------------
 
@@ -509,7 +569,23 @@ def _broken_variants():
             Y = A @ rlu.lu_normalize(A.T @ rlu.lu_normalize(Y))
         return Y
 
-    return {"normalize_keeps_pivot_order": ("normalize", normalize_keeps_pivot_order),
+    def lstsq_without_p(out, b):
+        bb = np.asarray(b, float).reshape(b.shape[0], -1)
+        k = out["L"].shape[1]
+        z1 = rlu.upper_solve(out["U"][:, :k], rlu.pinv_apply(out["L"], bb))
+        x = np.zeros((out["U"].shape[1], bb.shape[1])); x[out["q"][:k]] = z1
+        return x
+
+    def lstsq_without_q(out, b):
+        bb = np.asarray(b, float).reshape(b.shape[0], -1)
+        k = out["L"].shape[1]
+        z1 = rlu.upper_solve(out["U"][:, :k], rlu.pinv_apply(out["L"], bb[out["p"]]))
+        x = np.zeros((out["U"].shape[1], bb.shape[1])); x[:k] = z1
+        return x
+
+    return {"lstsq_without_p": ("lstsq", lstsq_without_p),
+            "lstsq_without_q": ("lstsq", lstsq_without_q),
+            "normalize_keeps_pivot_order": ("normalize", normalize_keeps_pivot_order),
             "power_without_transpose": ("power", power_without_transpose),
             "power_one_round_short": ("power", power_one_round_short),
             "wrong_sign_update": ("lu", wrong_sign_update),
@@ -518,6 +594,7 @@ def _broken_variants():
 
 
 @pytest.mark.parametrize("name", ["wrong_sign_update", "max_not_abs", "transposed_projection",
+                                  "lstsq_without_p", "lstsq_without_q",
                                   "normalize_keeps_pivot_order", "power_without_transpose",
                                   "power_one_round_short"])
 def test_planted_mistakes_are_caught(name, monkeypatch):
@@ -529,6 +606,17 @@ def test_planted_mistakes_are_caught(name, monkeypatch):
                                                      "max_abs": 1.0},))
     elif kind == "pinv":
         monkeypatch.setattr(rlu, "pinv_apply", fn)
+    elif kind == "lstsq":
+        monkeypatch.setattr(rlu, "lstsq_rank_deficient", fn)
+        failed = False
+        for t in (test_lstsq_consistent_system_is_solved_with_k_nonzeros,
+                  lambda: test_lstsq_residual_is_the_least_squares_minimum((150, 110), 8)):
+            try:
+                t()
+            except AssertionError:
+                failed = True
+        assert failed, name
+        return
     else:
         monkeypatch.setattr(rlu, "lu_normalize" if kind == "normalize" else "power_sketch", fn)
     if kind in ("normalize", "power"):
