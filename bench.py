@@ -10,7 +10,8 @@ pivoted LU of B^T, assembly of L and U) on a device-resident input; for the
 batched workload a step is one rlu_factor_batched call over 256 problems.
 Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
 under "forms", the same matrix through the FP32 path and with one power
-iteration (Section 5.2), the 16384 x 16384
+iteration (Section 5.2), least squares on its factors (Algorithm 4.3),
+the 16384 x 16384
 mixed-precision configuration beside the FP64 path on the same matrix, the
 256-problem batch, and the served request stream (throughput with p50/p99
 latency; disable the extra measurements with --forms none).  Only one GPU is used; --gpus N with
@@ -299,6 +300,43 @@ def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_
     return out, steps / wall, wall * 1e3 / steps, lat, ph
 
 
+def run_lstsq(rlu, torch, np, A, f, k, steps=20):
+    """Algorithm 4.3 (Section 4.4) on the factors of the timed run: solve
+    A x ~ b for b = A x0 (x0 Gaussian, fixed seed) with 1 and 64 right-hand
+    sides; per-call time from events around each call, relative residual
+    ||A x - b|| / ||b||."""
+    m, n = A.shape
+    h = rlu.Handle(0)
+    st = torch.cuda.current_stream()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7206)
+    res = {"workload": "rank-deficient least squares (Algorithm 4.3) on the 8192x8192 "
+                       f"FP64 factors, k={k}, b = A x0"}
+    for r in (1, 64):
+        x0 = torch.randn(r, n, dtype=A.dtype, device="cuda", generator=gen).t()
+        b = (A @ x0).t().contiguous().t()
+        x = rlu.lstsq(f, b, handle=h, stream=st)
+        for _ in range(3):
+            rlu.lstsq(f, b, handle=h, stream=st, x=x)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record(st)
+            rlu.lstsq(f, b, handle=h, stream=st, x=x)
+            e1.record(st)
+        torch.cuda.synchronize()
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+        rel = float(torch.linalg.norm(A @ x - b) / torch.linalg.norm(b))
+        # bytes the solve must move: L (m k) and b (m r) read, x (n r) written
+        byts = 8.0 * (m * k + m * r + n * r)
+        res[f"rhs{r}"] = {"ms_per_call": float(np.median(ms)), "p99_ms": float(np.percentile(ms, 99)),
+                          "rel_residual": rel,
+                          "hbm_gbs": byts / (float(np.median(ms)) * 1e-3) / 1e9}
+        log(f"lstsq form, {r} rhs: {np.median(ms):.3f} ms, residual {rel:.3e}")
+    return res
+
+
 def run_mixed(rlu, torch, np, steps):
     import workloads
 
@@ -530,8 +568,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp32,power,batch,mixed,serve",
-                    help="extra measurements in the same line: comma list of fp32, power, batch, "
+    ap.add_argument("--forms", default="fp32,power,lstsq,batch,mixed,serve",
+                    help="extra measurements in the same line: comma list of fp32, power, lstsq, batch, "
                          "mixed, serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
@@ -664,6 +702,8 @@ def main():
             "info": outp.info.cpu().tolist()}
         log(f"power form: {vp:.1f}/s ({msp:.2f} ms), residual {rp:.3e} against {r0}")
         del outp
+    if "lstsq" in forms and name == "exp8192":
+        result["forms"]["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
     if "mixed" in forms:
         result["forms"]["mixed16384"] = run_mixed(rlu, torch, np, 8)
     if "batch" in forms:

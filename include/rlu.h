@@ -180,6 +180,40 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
 rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count, const rlu_problem_t* pbs,
                                 const rlu_buffers_t* ios, rlu_stream_t stream);
 
+/* Rank-deficient least squares on the factors (Section 4.4, Algorithm 4.3):
+ * for P A Q ~ L U from rlu_factor (same m, n, k, dtype), minimize
+ * ||A x - b|| for each column of b by
+ *   Step 2  y   <- L^+ P b        (Gram route, as Step 5: (L^T L)^{-1} L^T,
+ *                                  with P folded into the rows of L)
+ *   Step 3  z_1 <- U_1^{-1} y     (U_1 = the leading k x k block of U)
+ *   Step 4  z   <- (z_1; 0)       (z_2 = 0: x has at most k nonzeros)
+ *   Step 5  x   <- Q z            (x[q[j]] = z[j])
+ * Arithmetic is FP64 for both storage types.  A zero diagonal entry of U_1
+ * (a zero pivot of Step 6, whose row of U is zero) leaves its unknown 0.
+ * All pointers are device pointers on the handle's device; L, U, p, q and b
+ * are read only, x is written (n x nrhs).  p and q must be the permutations
+ * rlu_factor returned: entries outside [0, m) or [0, n) are skipped (no
+ * out-of-range access) and the result is then undefined.  Requires
+ * 1 <= k <= min(m, n), k <= 1024, nrhs >= 0 (0: no-op), ldl >= m,
+ * ldu >= k, ldb >= m, ldx >= n; otherwise RLU_ERR_INVALID_ARG (k > 1024:
+ * RLU_ERR_UNSUPPORTED) before any device work.  Uses the handle's workspace,
+ * so calls on one handle are ordered like rlu_factor calls. */
+typedef struct {
+  int64_t m, n, k;
+  rlu_dtype_t dtype;           /* storage of L, U, b and x                   */
+  const void* L; int64_t ldl;  /* m x k, unit lower trapezoidal (rlu_factor) */
+  const void* U; int64_t ldu;  /* k x n, upper trapezoidal                   */
+  const int64_t* p;            /* length m: (P A)(i, :) = A(p[i], :)        */
+  const int64_t* q;            /* length n: (A Q)(:, j) = A(:, q[j])        */
+  int64_t nrhs;
+  const void* b; int64_t ldb;  /* m x nrhs                                   */
+  void* x; int64_t ldx;        /* out n x nrhs                               */
+} rlu_lstsq_t;
+
+/* Device workspace rlu_lstsq needs for this problem, in bytes. */
+rlu_status_t rlu_lstsq_workspace_size(const rlu_lstsq_t* ls, size_t* bytes);
+rlu_status_t rlu_lstsq(rlu_handle_t h, const rlu_lstsq_t* ls, rlu_stream_t stream);
+
 /* Tile shapes of the grouped products of rlu_factor_batched, for tuning
  * tools.  product: 0 sketch (Step 2), 1 Gram matrix, 2 projection (Step 5),
  * 3 S^{-1} C, 4 L = Lv L_b (Step 7).  cfg: an index for which rlu_tile_name

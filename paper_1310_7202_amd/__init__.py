@@ -13,7 +13,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
-__all__ = ["RluError", "Handle", "factor", "factor_batched", "Batch", "Server",
+__all__ = ["RluError", "Handle", "factor", "factor_batched", "lstsq", "Batch", "Server",
            "serve_footprint", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
            "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS"]
@@ -37,7 +37,8 @@ EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_fact
                     "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
                     "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
-                    "rlu_status_string", "rlu_version"]
+                    "rlu_status_string", "rlu_version", "rlu_lstsq",
+                    "rlu_lstsq_workspace_size"]
 
 
 class RluError(RuntimeError):
@@ -54,6 +55,17 @@ class Problem(ctypes.Structure):
 
 
 MAX_POWER_ITERS = 16
+
+
+class LstsqDesc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("dtype", ctypes.c_int),
+                ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
+                ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("p", ctypes.c_void_p), ("q", ctypes.c_void_p),
+                ("nrhs", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("ldx", ctypes.c_int64)]
 
 
 class Buffers(ctypes.Structure):
@@ -118,6 +130,9 @@ def lib() -> ctypes.CDLL:
         L.rlu_status_string.restype = ctypes.c_char_p
         L.rlu_version.restype = ctypes.c_char_p
         L.rlu_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.rlu_lstsq.argtypes = [ctypes.c_void_p, ctypes.POINTER(LstsqDesc), ctypes.c_void_p]
+        L.rlu_lstsq_workspace_size.argtypes = [ctypes.POINTER(LstsqDesc),
+                                               ctypes.POINTER(ctypes.c_size_t)]
         L.rlu_phase_times.argtypes = [ctypes.c_void_p, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_float),
                                       ctypes.POINTER(ctypes.c_char_p), ctypes.c_int,
@@ -126,7 +141,8 @@ def lib() -> ctypes.CDLL:
                      "rlu_factor_batched", "rlu_set_tile", "rlu_check_info", "rlu_set_timing",
                      "rlu_phase_times", "rlu_serve_create", "rlu_serve_submit",
                      "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
-                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy"):
+                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
+                     "rlu_lstsq", "rlu_lstsq_workspace_size"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -297,6 +313,43 @@ def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=
                           ctypes.c_void_p(s.cuda_stream))
     _check(st, "rlu_factor")
     return out
+
+
+def _ld(t, rows):
+    return max(t.stride(1), rows) if t.dim() == 2 and t.shape[1] > 1 else rows
+
+
+def lstsq(f: Factors, b, *, handle: Handle | None = None, stream=None, x=None):
+    """Rank-deficient least squares on the factors of ``factor`` (Section
+    4.4, Algorithm 4.3): x = Q (U_1^{-1} L^+ P b; 0) minimizes ||A x - b||.
+    ``b`` is an m-vector or an m x r column-major device tensor of the
+    factors' dtype; returns x (n, or n x r) on the same stream, not
+    synchronized."""
+    import torch
+
+    L, U = f.L, f.U
+    m, k = L.shape
+    n = U.shape[1]
+    if not b.is_cuda or b.dtype != L.dtype or b.shape[0] != m:
+        raise ValueError("b must be a device tensor of L's dtype with m rows")
+    vec = b.dim() == 1
+    B = b.view(m, 1) if vec else b
+    if B.stride(0) != 1:
+        raise ValueError("b must be column-major (stride(0) == 1)")
+    r = B.shape[1]
+    if x is None:
+        x = torch.empty((r, n), dtype=L.dtype, device=L.device).t()
+    X = x.view(n, 1) if x.dim() == 1 else x
+    if X.stride(0) != 1 or X.shape != (n, r):
+        raise ValueError("x must be an n x r column-major tensor")
+    d = LstsqDesc(m, n, k, F64 if L.dtype == torch.float64 else F32,
+                  L.data_ptr(), _ld(L, m), U.data_ptr(), _ld(U, k),
+                  f.p.data_ptr(), f.q.data_ptr(), r,
+                  B.data_ptr(), _ld(B, m), X.data_ptr(), _ld(X, n))
+    h = handle or default_handle(L.device.index or 0)
+    s = stream if stream is not None else torch.cuda.current_stream(L.device)
+    _check(lib().rlu_lstsq(h.ptr, ctypes.byref(d), ctypes.c_void_p(s.cuda_stream)), "rlu_lstsq")
+    return x[:, 0] if vec and x.dim() == 2 else x
 
 
 class Batch:

@@ -29,6 +29,7 @@ HIP_FLAGS = [
 ]
 
 SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
+           "lstsq.hip",
            "rlu_api.cpp", "rlu_batch.cpp", "rlu_serve.cpp"]
 
 

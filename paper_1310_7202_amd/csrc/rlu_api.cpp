@@ -478,6 +478,106 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   return RLU_OK;
 }
 
+// ----- Rank-deficient least squares (Section 4.4, Algorithm 4.3) ------------
+
+rlu_status_t lstsq_validate(const rlu_lstsq_t* ls) {
+  if (!ls) return RLU_ERR_INVALID_ARG;
+  if (ls->m < 1 || ls->n < 1 || ls->k < 1 || ls->k > std::min(ls->m, ls->n) || ls->nrhs < 0)
+    return RLU_ERR_INVALID_ARG;
+  if (ls->m >= (1LL << 31) || ls->n >= (1LL << 31) || ls->nrhs >= (1LL << 31))
+    return RLU_ERR_TOO_LARGE;
+  if (ls->dtype != RLU_F64 && ls->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
+  if (ls->ldl < ls->m || ls->ldu < ls->k || ls->ldb < ls->m || ls->ldx < ls->n)
+    return RLU_ERR_INVALID_ARG;
+  if (ls->nrhs > 0 && (!ls->L || !ls->U || !ls->p || !ls->q || !ls->b || !ls->x))
+    return RLU_ERR_INVALID_ARG;
+  if (ls->k > kLsMaxK || !spd_inverse_supported(ls->k)) return RLU_ERR_UNSUPPORTED;
+  return RLU_OK;
+}
+
+struct LsLayout {
+  size_t Ld = 0, bd = 0, S = 0, gj = 0, C = 0, Yk = 0, steps = 0, part = 0, total = 0;
+};
+
+LsLayout lstsq_layout(const rlu_lstsq_t& ls) {
+  LsLayout L;
+  size_t off = 0;
+  auto take = [&](size_t& slot, size_t bytes) {
+    slot = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+  };
+  const size_t d = sizeof(double);
+  const int64_t m = ls.m, k = ls.k, r = std::max<int64_t>(ls.nrhs, 1);
+  take(L.Ld, (size_t)m * k * d);
+  take(L.bd, ls.dtype == RLU_F32 ? (size_t)m * r * d : 0);
+  take(L.S, (size_t)k * k * d);
+  take(L.gj, spd_inverse_scratch_elems(k) * d);
+  take(L.C, (size_t)k * r * d);
+  take(L.Yk, (size_t)k * r * d);
+  take(L.steps, (size_t)m * 4);
+  take(L.part, std::max(gemm_auto_partial_elems(k, k, m, OpA::LvT),
+                        gemm_auto_partial_elems(k, r, m, OpA::LvT)) * d);
+  L.total = off;
+  return L;
+}
+
+// Step 2 as in Step 5 of Algorithm 4.1: with Ld = P^T L (rows scattered),
+// L^T P b = Ld^T b and L^T L = Ld^T Ld; Ld enters the products through the
+// in-place Lv operand forms with every row step set to k (all entries
+// stored), so no transposed copy is made.
+template <typename T>
+rlu_status_t lstsq_path(rlu_handle_s* h, const rlu_lstsq_t& ls, hipStream_t s,
+                        const LsLayout& Ly) {
+  const int64_t m = ls.m, n = ls.n, k = ls.k, r = ls.nrhs;
+  void* ws = h->ws;
+  double* Ld = at<double>(ws, Ly.Ld);
+  double* S = at<double>(ws, Ly.S);
+  double* C = at<double>(ws, Ly.C);
+  double* Yk = at<double>(ws, Ly.Yk);
+  int* steps = at<int>(ws, Ly.steps);
+  HIP_TRY(launch_fill_u32((uint32_t*)steps, (size_t)m, (uint32_t)k, s));
+  HIP_TRY(launch_lstsq_scatter_rows<T>((const T*)ls.L, ls.ldl, ls.p, m, k, Ld, s));
+  const double* bd = (const double*)ls.b;
+  int64_t ldb = ls.ldb;
+  if (std::is_same<T, float>::value) {
+    double* bw = at<double>(ws, Ly.bd);
+    HIP_TRY((launch_convert2d<float, double>((const float*)ls.b, ls.ldb, bw, m, m, r, s)));
+    bd = bw;
+    ldb = m;
+  }
+  {  // S = Ld^T Ld
+    GemmDesc g{};
+    g.M = k; g.N = k; g.K = m;
+    g.A = Ld; g.lda = m; g.opa = OpA::LvT; g.astep = steps;
+    g.B = Ld; g.ldb = m; g.opb = OpB::Lv; g.bstep = steps;
+    g.C = S; g.ldc = k;
+    g.ksplit = 0; g.partial = at<void>(ws, Ly.part);
+    HIP_TRY(launch_gemm<double>(g, s));
+  }
+  HIP_TRY(launch_spd_inverse_scratch(S, k, at<double>(ws, Ly.gj), s));
+  {  // C = Ld^T b
+    GemmDesc g{};
+    g.M = k; g.N = r; g.K = m;
+    g.A = Ld; g.lda = m; g.opa = OpA::LvT; g.astep = steps;
+    g.B = bd; g.ldb = ldb; g.opb = OpB::Plain;
+    g.C = C; g.ldc = k;
+    g.ksplit = 0; g.partial = at<void>(ws, Ly.part);
+    HIP_TRY(launch_gemm<double>(g, s));
+  }
+  {  // y = S^{-1} C
+    GemmDesc g{};
+    g.M = k; g.N = r; g.K = k;
+    g.A = S; g.lda = k; g.opa = OpA::Plain;
+    g.B = C; g.ldb = k; g.opb = OpB::Plain;
+    g.C = Yk; g.ldc = k;
+    g.ksplit = 1;
+    HIP_TRY(launch_gemm<double>(g, s));
+  }
+  // Steps 3-5
+  HIP_TRY(launch_lstsq_back<T>((const T*)ls.U, ls.ldu, Yk, k, ls.q, n, r, (T*)ls.x, ls.ldx, s));
+  return RLU_OK;
+}
+
 }  // namespace
 
 using namespace rlu_detail;
@@ -568,6 +668,32 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffe
       st = factor_path<double>(h, *pb, *io, (hipStream_t)stream, L);
     else
       st = factor_path<float>(h, *pb, *io, (hipStream_t)stream, L);
+  }
+  if (prev != h->device) hipSetDevice(prev);
+  return st;
+}
+
+rlu_status_t rlu_lstsq_workspace_size(const rlu_lstsq_t* ls, size_t* bytes) {
+  if (!bytes) return RLU_ERR_INVALID_ARG;
+  const rlu_status_t st = lstsq_validate(ls);
+  if (st != RLU_OK) return st;
+  *bytes = lstsq_layout(*ls).total;
+  return RLU_OK;
+}
+
+rlu_status_t rlu_lstsq(rlu_handle_t h, const rlu_lstsq_t* ls, rlu_stream_t stream) {
+  if (!h) return RLU_ERR_INVALID_ARG;
+  rlu_status_t st = lstsq_validate(ls);
+  if (st != RLU_OK) return st;
+  if (ls->nrhs == 0) return RLU_OK;
+  const LsLayout L = lstsq_layout(*ls);
+  int prev = 0;
+  hipGetDevice(&prev);
+  if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RLU_ERR_DEVICE;
+  st = ensure_ws(h, L.total);
+  if (st == RLU_OK) {
+    if (ls->dtype == RLU_F64) st = lstsq_path<double>(h, *ls, (hipStream_t)stream, L);
+    else st = lstsq_path<float>(h, *ls, (hipStream_t)stream, L);
   }
   if (prev != h->device) hipSetDevice(prev);
   return st;

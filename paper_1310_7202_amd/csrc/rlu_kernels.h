@@ -156,6 +156,20 @@ hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_
 // One matrix.
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
 
+// ----- Rank-deficient least squares, Algorithm 4.3 (lstsq.hip) -------------
+constexpr int kLsMaxK = 1024;   // largest k of the back substitution (= kSpdMaxK)
+// Ld (m x k, FP64, ld m) with row p[i] = row i of L (entries of p outside
+// [0, m) are skipped).
+template <typename T>
+hipError_t launch_lstsq_scatter_rows(const T* L, int64_t ldl, const int64_t* p, int64_t m,
+                                     int64_t k, double* Ld, hipStream_t s);
+// X(:, r) = Q (U_1^{-1} Y(:, r); 0) for r < nrhs; U_1 = U(0:k, 0:k); Y is
+// k x nrhs FP64 (ld k); a zero diagonal entry of U_1 gives a zero unknown.
+template <typename T>
+hipError_t launch_lstsq_back(const T* U, int64_t ldu, const double* Y, int64_t k,
+                             const int64_t* q, int64_t n, int64_t nrhs, T* X, int64_t ldx,
+                             hipStream_t s);
+
 // ----- Permutations and factor assembly (finish.hip) ------------------------
 hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
 // L_b (k x k, unit lower) from the pivoted LU of B^T stored in B (k x n)

@@ -181,3 +181,36 @@ def test_timing_rejects_null_handle_and_unknown_modes(rlu):
     for mode in (0, 1, 2):
         assert lib.rlu_set_timing(None, mode) == -1
     assert lib.rlu_set_timing(None, 3) == -1
+
+
+def _ls(rlu, m=100, n=80, k=5, nrhs=1, dtype=0, ldl=None, ldu=None, ldb=None, ldx=None):
+    d = rlu.LstsqDesc(m, n, k, dtype, 1, ldl if ldl is not None else m,
+                      1, ldu if ldu is not None else k, 1, 1, nrhs,
+                      1, ldb if ldb is not None else m, 1, ldx if ldx is not None else n)
+    out = ctypes.c_size_t()
+    return rlu.lib().rlu_lstsq_workspace_size(ctypes.byref(d), ctypes.byref(out)), out.value, d
+
+
+def test_lstsq_argument_checks(rlu):
+    """Algorithm 4.3 entry point: shapes, leading dimensions and the k limit
+    are checked on the host before any device work."""
+    assert _ls(rlu)[0] == 0
+    assert _ls(rlu, k=0)[0] == -1
+    assert _ls(rlu, k=81)[0] == -1            # k > min(m, n)
+    assert _ls(rlu, nrhs=-1)[0] == -1
+    assert _ls(rlu, dtype=5)[0] == -1
+    assert _ls(rlu, ldl=99)[0] == -1
+    assert _ls(rlu, ldu=4)[0] == -1
+    assert _ls(rlu, ldb=99)[0] == -1
+    assert _ls(rlu, ldx=79)[0] == -1
+    assert _ls(rlu, m=3000, n=2000, k=1025)[0] == -8
+    st1, a, _ = _ls(rlu, m=3000, n=2000, k=40, nrhs=1)
+    st2, b, _ = _ls(rlu, m=3000, n=2000, k=40, nrhs=64)
+    st3, c, _ = _ls(rlu, m=3000, n=2000, k=40, nrhs=64, dtype=1)
+    assert st1 == st2 == st3 == 0 and a < b < c   # FP32 b is widened to FP64
+    assert b >= 8 * (3000 * 40 + 2 * 40 * 64)
+    _, _, d = _ls(rlu)
+    assert rlu.lib().rlu_lstsq(None, ctypes.byref(d), None) == -1
+    assert rlu.lib().rlu_lstsq(ctypes.c_void_p(1), None, None) == -1
+    d.ldx = 3
+    assert rlu.lib().rlu_lstsq(ctypes.c_void_p(1), ctypes.byref(d), None) == -1

@@ -70,6 +70,20 @@ def slow_decay(count: int) -> np.ndarray:
     return 100.0 / (9.0 + i) ** 2
 
 
+def synthetic_factors(m: int, n: int, k: int, seed: int):
+    """Seeded stand-ins for the outputs of a rank-k randomized LU, as inputs
+    of the least-squares solve: L (m x k) unit lower trapezoidal with
+    entries U(-1, 1) below the diagonal, U (k x n) upper trapezoidal with
+    N(0, 1) entries and a diagonal of magnitude in [2, 3], and random
+    permutations p (length m) and q (length n)."""
+    g = rng(seed)
+    L = np.tril(g.uniform(-1.0, 1.0, (m, k)), -1)
+    L[np.arange(k), np.arange(k)] = 1.0
+    U = np.triu(g.standard_normal((k, n)))
+    U[np.arange(k), np.arange(k)] = g.choice([-1.0, 1.0], k) * g.uniform(2.0, 3.0, k)
+    return L, U, g.permutation(m), g.permutation(n)
+
+
 def spectral_matrix(m: int, n: int, sigma: np.ndarray, seed: int) -> np.ndarray:
     """U diag(sigma) V^T with Haar U (m x r), V (n x r), r = len(sigma)."""
     r = len(sigma)
