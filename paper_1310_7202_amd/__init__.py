@@ -428,9 +428,10 @@ class Server:
         self._keep = {}
 
     def submit(self, A, k: int, l: int, *, seed: int = 0, precision: int | None = None,
-               G=None) -> int:
+               G=None, power_iters: int = 0) -> int:
         """Queue A (column-major device tensor); returns the ticket.  Raises
-        RluError on rejection (e.g. RLU_ERR_TOO_LARGE, RLU_ERR_QUEUE_FULL)."""
+        RluError on rejection (e.g. RLU_ERR_TOO_LARGE, RLU_ERR_QUEUE_FULL).
+        A request with power iterations (Section 5.2) runs alone."""
         import torch
 
         if A.dim() != 2 or not A.is_cuda or A.stride(0) != 1:
@@ -443,7 +444,7 @@ class Server:
             dtype, prec = F32, (PREC_FP32 if precision is None else precision)
         else:
             raise ValueError("A must be float64 or float32")
-        pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, 0)
+        pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, 0, power_iters)
         if G is not None:
             pb.G = G.data_ptr()
             pb.ldg = max(G.stride(1), n) if l > 1 else n

@@ -80,11 +80,24 @@ size_t output_layout(const rlu_problem_t& pb, size_t* offU, size_t* offp, size_t
 }
 
 // Workspace a request needs: its share of a batch, or, for a shape the
-// batched kernels cannot run, the single-problem workspace (it then runs
-// alone through rlu_factor).
+// batched kernels cannot run or a request with power iterations, the
+// single-problem workspace (it then runs alone through rlu_factor).
+
+// Argument checks of a request: those of the batched form, except that
+// power iterations are allowed (such a request runs alone).
+rlu_status_t request_validate(const rlu_problem_t* pb) {
+  if (!pb) return RLU_ERR_INVALID_ARG;
+  rlu_status_t st = validate(pb);
+  if (st != RLU_OK) return st;
+  rlu_problem_t v = *pb;
+  v.power_iters = 0;
+  return batched_validate(1, &v, nullptr);
+}
+
 rlu_status_t request_ws_bytes(const rlu_problem_t& pb, int cus, size_t* bytes, bool* solo) {
-  rlu_status_t st = batched_item_bytes(pb, cus, bytes);
   *solo = false;
+  // power iterations (Section 5.2) exist only on the single-problem path
+  rlu_status_t st = pb.power_iters != 0 ? RLU_ERR_UNSUPPORTED : batched_item_bytes(pb, cus, bytes);
   if (st != RLU_ERR_UNSUPPORTED) return st;
   st = rlu_workspace_size(&pb, bytes);
   if (st == RLU_OK) *solo = true;
@@ -268,7 +281,7 @@ extern "C" {
 
 rlu_status_t rlu_serve_footprint(const rlu_problem_t* pb, size_t* bytes) {
   if (!pb || !bytes) return RLU_ERR_INVALID_ARG;
-  rlu_status_t st = batched_validate(1, pb, nullptr);
+  rlu_status_t st = request_validate(pb);
   if (st != RLU_OK) return st;
   size_t ws = 0, oU, op, oq, oi;
   bool solo = false;
@@ -332,7 +345,7 @@ rlu_status_t rlu_serve_submit(rlu_server_t srv, const rlu_problem_t* pb, const v
                               int64_t lda, uint64_t* ticket) {
   if (!srv || !pb || !A || !ticket) return RLU_ERR_INVALID_ARG;
   if (lda < pb->m) return RLU_ERR_INVALID_ARG;
-  rlu_status_t st = batched_validate(1, pb, nullptr);
+  rlu_status_t st = request_validate(pb);
   if (st != RLU_OK) return st;
   Req* r = new (std::nothrow) Req();
   if (!r) return RLU_ERR_OUT_OF_MEMORY;

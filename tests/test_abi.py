@@ -95,10 +95,15 @@ def test_power_iterations_range_and_workspace(rlu):
     assert b - a >= 2 * 8 * 3000 * 48 - 4096 and c == b  # slots are 256-byte aligned
     st3, d = _ws(rlu, 4096, 3000, 40, 48, G=1, ldg=3000, power_iters=1)
     assert st3 == 0 and d == b
-    # the batched form and the server do not take power iterations
+    # the batched form does not take power iterations; the server runs such
+    # a request alone, so its footprint is the single-problem workspace
     pb = rlu.Problem(512, 512, 10, 15, 0, 0, 0, None, 0, 0, 1)
     out = ctypes.c_size_t()
-    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -8
+    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == 0
+    assert out.value > _ws(rlu, 512, 512, 10, 15, power_iters=1)[1]
+    pb.power_iters = 17
+    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -1
+    pb.power_iters = 1
     io = rlu.Buffers()
     io.A = io.L = io.U = io.p = io.q = io.info = 1
     io.lda = io.ldl = 512

@@ -45,8 +45,8 @@ def _inputs(seed0):
     return out
 
 
-def _check(A, k, l, G, f):
-    o = orl.randomized_lu(A, k, l, G)
+def _check(A, k, l, G, f, power=0):
+    o = orl.randomized_lu(A, k, l, G, q=power)
     L, U, p, q, info = (to_host(f.L), to_host(f.U), to_host(f.p), to_host(f.q),
                         to_host(f.info))
     assert info[2] == 0 and (int(info[0]), int(info[1])) == o["info"]
@@ -229,4 +229,37 @@ def test_oversize_request_runs_alone_in_the_mix(rlu):
         _check(X, kk, ll, G, srv.result(t))
         srv.release(t)
     srv.release(tb)
+    srv.close()
+
+
+def test_power_iteration_requests_run_alone_in_the_mix(rlu):
+    """Requests with power iterations (Section 5.2) run through the
+    single-problem path between batched requests: each equals a direct
+    rlu_factor call bitwise and the oracle's power scheme under the FP64
+    rule."""
+    srv = rlu.Server(0)
+    small = _inputs(1700)
+    devs = [(to_dev_colmajor(X), to_dev_colmajor(G)) for X, kk, ll, G in small]
+    pw = []
+    for i, (m, n, k, l, q) in enumerate([(1500, 1100, 30, 38, 1), (900, 1300, 20, 26, 2)]):
+        A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), 15.0), 1750 + i)
+        G = workloads.gaussian((n, l), 1760 + i)
+        pw.append((A, k, l, G, q, to_dev_colmajor(A), to_dev_colmajor(G)))
+    print("[serve] power-iteration requests in a mix", flush=True)
+    ts = [srv.submit(Xd, kk, ll, G=Gd) for (Xd, Gd), (X, kk, ll, G) in zip(devs[:3], small[:3])]
+    tp = [srv.submit(Ad, k, l, G=Gd, power_iters=q) for A, k, l, G, q, Ad, Gd in pw]
+    ts += [srv.submit(Xd, kk, ll, G=Gd) for (Xd, Gd), (X, kk, ll, G) in zip(devs[3:], small[3:])]
+    for t, (A, k, l, G, q, Ad, Gd) in zip(tp, pw):
+        assert srv.wait(t) == 0
+        f = srv.result(t)
+        ref = rlu.factor(Ad, k, l, G=Gd, power_iters=q)
+        torch.cuda.synchronize()
+        for a, b in zip((f.L, f.U, f.p, f.q), (ref.L, ref.U, ref.p, ref.q)):
+            np.testing.assert_array_equal(to_host(a), to_host(b))
+        _check(A, k, l, G, f, power=q)
+        srv.release(t)
+    for t, (X, kk, ll, G) in zip(ts, small):
+        assert srv.wait(t) == 0
+        _check(X, kk, ll, G, srv.result(t))
+        srv.release(t)
     srv.close()
