@@ -55,17 +55,25 @@ __global__ void __launch_bounds__(256) sweep_copy_kernel(const SpdTaskDev* __res
 
 // One tile: RA = 8 when the augmented matrix has the rows of block I (I != J),
 // else 4; RB likewise for the columns of block c.  Thread (ty, tx) holds
-// augmented rows ty + 16 a and columns tx + 16 b.  Each pivot costs one
-// barrier: the owners of its column and row (and of the next pivot) publish
-// them in LDS; every thread then updates its entries and, from the same
-// LDS values, the next pivot, so the division leaves the critical path.
+// augmented rows ty + 16 a and columns tx + 16 b.
+//
+// Pivots are swept two at a time: sweeping the pair J2 = {p, p + 1} at once
+// is the same as sweeping p and then p + 1 (the sweep of a block replaces
+// M_rs by M_rs - M_rJ2 D^{-1} M_J2s, M_rJ2 by M_rJ2 D^{-1}, M_J2s by
+// D^{-1} M_J2s and D by -D^{-1}, D = M_J2J2, symmetric positive definite),
+// so each pair costs one barrier.  The owners of the pair's two columns and
+// two rows publish them in LDS, and the owners of the next pair's 2 x 2
+// block publish it; every thread then applies the rank-2 update and, from
+// the same LDS values, forms the next pair's block and its inverse, so the
+// division leaves the critical path.  An odd last pivot is a pair whose
+// second member is absent (zero row and column, D = diag(d, 1)).
 template <int RA, int RB>
 __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double* __restrict__ out,
                                            int k, int J, int I, int cb, bool last) {
   const int bj = blk_size(k, J), bi = blk_size(k, I), bc = blk_size(k, cb);
-  __shared__ double colb[2][2 * GB];
-  __shared__ double rowb[2][2 * GB];
-  __shared__ double diagb[2];
+  __shared__ double colb[2][2][2 * GB];  // [parity][member of the pair][augmented row]
+  __shared__ double rowb[2][2][2 * GB];
+  __shared__ double dnx[2][3];           // next pair's block before this step
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   double M[RA][RB];
 #pragma unroll
@@ -81,56 +89,103 @@ __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double
       M[a][b] = (rin && cin) ? in[gr + gc * k] : 0.0;
     }
   }
-  double rd = 1.0 / in[(int64_t)GB * J * (k + 1)];  // first pivot
+  // inverse of the first pair's block: [e11 e12; e12 e22]
+  double e11, e12, e22;
+  {
+    const int64_t o = (int64_t)GB * J;
+    const double d11 = in[o + o * k];
+    if (bj >= 2) {
+      const double d12 = in[o + (o + 1) * k], d22 = in[(o + 1) + (o + 1) * k];
+      const double r = 1.0 / __fma_rn(d11, d22, -d12 * d12);
+      e11 = d22 * r; e12 = -d12 * r; e22 = d11 * r;
+    } else {
+      e11 = 1.0 / d11; e12 = 0.0; e22 = 0.0;
+    }
+  }
 
-  // pivot p = 16 pa + pt sits in register slot pa of the threads with
-  // ty = pt (its row) and tx = pt (its column); pa is unrolled so that every
-  // register index is static
+  // pair (p, p + 1), p = 16 pa + pt with pt even: both sit in register slot
+  // pa of the threads with ty (rows) or tx (columns) = pt, pt + 1; pa is
+  // unrolled so that every register index is static
 #pragma unroll
   for (int pa = 0; pa < 4; ++pa) {
-    for (int pt = 0; pt < 16; ++pt) {
+    const int pn = pa < 3 ? pa + 1 : 3;
+    for (int pt = 0; pt < 16; pt += 2) {
       const int p = 16 * pa + pt;
       if (p >= bj) break;
-      const int par = p & 1, q = p + 1;
-      const bool orow = ty == pt, ocol = tx == pt;
-      if (ocol) {
+      const int par = (pt >> 1) & 1;
+      const bool two = p + 1 < bj;
+      const bool orow0 = ty == pt, orow1 = two && ty == pt + 1;
+      const bool ocol0 = tx == pt, ocol1 = two && tx == pt + 1;
+      if (ocol0 || ocol1) {
 #pragma unroll
-        for (int a = 0; a < RA; ++a) colb[par][ty + 16 * a] = M[a][pa];
+        for (int a = 0; a < RA; ++a) colb[par][tx - pt][ty + 16 * a] = M[a][pa];
       }
-      if (orow) {
+      if (orow0 || orow1) {
 #pragma unroll
-        for (int b = 0; b < RB; ++b) rowb[par][tx + 16 * b] = M[pa][b];
+        for (int b = 0; b < RB; ++b) rowb[par][ty - pt][tx + 16 * b] = M[pa][b];
       }
-      // the next pivot's entry, before this step
-      if (q < bj && ty == (q & 15) && tx == (q & 15)) {
-        const int pn = pa < 3 ? pa + 1 : 3;
-        diagb[par] = pt < 15 ? M[pa][pa] : M[pn][pn];
+      // the next pair (q0, q1) = (p + 2, p + 3): its block before this step
+      // sits in slot pa, or pa + 1 when pt = 14
+      const int q0 = p + 2, qt = q0 & 15;
+      const bool nxt = q0 < bj, nxt2 = q0 + 1 < bj;
+      if (nxt && ty >= qt && ty <= qt + 1 && tx >= qt && tx <= qt + 1 && ty <= tx) {
+        const int slot = (ty - qt) + (tx - qt);  // 0: (q0, q0), 1: (q0, q1), 2: (q1, q1)
+        if (slot == 0 || nxt2) dnx[par][slot] = pt < 14 ? M[pa][pa] : M[pn][pn];
       }
       __syncthreads();
-      double fr[RA], gs[RB];
+      double f0[RA], f1[RA], g0[RB], g1[RB];
 #pragma unroll
-      for (int a = 0; a < RA; ++a) fr[a] = colb[par][ty + 16 * a];
+      for (int a = 0; a < RA; ++a) {
+        f0[a] = colb[par][0][ty + 16 * a];
+        f1[a] = two ? colb[par][1][ty + 16 * a] : 0.0;
+      }
 #pragma unroll
-      for (int b = 0; b < RB; ++b) gs[b] = rowb[par][tx + 16 * b] * rd;
-      // the next pivot after this step, as its owner computes it below
-      // (straight-line code, so that the division overlaps the update)
-      const double den = q < bj ? __fma_rn(-colb[par][q], rowb[par][q] * rd, diagb[par]) : 1.0;
-      const double rd_next = 1.0 / den;
-      // The pivot row and column come out of the same fused multiply-add:
-      // with its entries cleared, fr = -1 on the pivot row gives M[p][s] / d
-      // (= gs), gs = -1/d on the pivot column gives M[r][p] / d, and both
-      // together give -1/d on the pivot.
-      fr[pa] = orow ? -1.0 : fr[pa];
-      gs[pa] = ocol ? -rd : gs[pa];
+      for (int b = 0; b < RB; ++b) {
+        const double r0 = rowb[par][0][tx + 16 * b];
+        const double r1 = two ? rowb[par][1][tx + 16 * b] : 0.0;
+        g0[b] = __fma_rn(e12, r1, e11 * r0);
+        g1[b] = __fma_rn(e22, r1, e12 * r0);
+      }
+      // the next pair's block after this step and its inverse (straight-line
+      // code, so that the division overlaps the update)
+      double n11 = 1.0, n12 = 0.0, n22 = 1.0;
+      if (nxt) {
+        const int q1 = nxt2 ? q0 + 1 : q0;
+        const double c00 = colb[par][0][q0], c01 = two ? colb[par][1][q0] : 0.0;
+        const double c10 = colb[par][0][q1], c11 = two ? colb[par][1][q1] : 0.0;
+        const double s00 = rowb[par][0][q0], s01 = two ? rowb[par][1][q0] : 0.0;
+        const double s10 = rowb[par][0][q1], s11 = two ? rowb[par][1][q1] : 0.0;
+        // D^{-1} M_J2,q for the columns q0 and q1
+        const double h00 = __fma_rn(e12, s01, e11 * s00), h01 = __fma_rn(e22, s01, e12 * s00);
+        const double h10 = __fma_rn(e12, s11, e11 * s10), h11 = __fma_rn(e22, s11, e12 * s10);
+        n11 = dnx[par][0] - __fma_rn(c00, h00, c01 * h01);
+        if (nxt2) {
+          n12 = dnx[par][1] - __fma_rn(c00, h10, c01 * h11);
+          n22 = dnx[par][2] - __fma_rn(c10, h10, c11 * h11);
+        }
+      }
+      const double rn = 1.0 / (nxt2 ? __fma_rn(n11, n22, -n12 * n12) : n11);
+      // rows and columns of the pair come out of the same multiply-adds: with
+      // their entries cleared, f = -e_i on pivot row i and g = -D^{-1} e_j on
+      // pivot column j give D^{-1} M_J2s, M_rJ2 D^{-1} and -D^{-1}
+      f0[pa] = orow0 ? -1.0 : (orow1 ? 0.0 : f0[pa]);
+      f1[pa] = orow0 ? 0.0 : (orow1 ? -1.0 : f1[pa]);
+      g0[pa] = ocol0 ? -e11 : (ocol1 ? -e12 : g0[pa]);
+      g1[pa] = ocol0 ? -e12 : (ocol1 ? -e22 : g1[pa]);
 #pragma unroll
-      for (int b = 0; b < RB; ++b) M[pa][b] = orow ? 0.0 : M[pa][b];
+      for (int b = 0; b < RB; ++b) M[pa][b] = (orow0 || orow1) ? 0.0 : M[pa][b];
 #pragma unroll
-      for (int a = 0; a < RA; ++a) M[a][pa] = ocol ? 0.0 : M[a][pa];
+      for (int a = 0; a < RA; ++a) M[a][pa] = (ocol0 || ocol1) ? 0.0 : M[a][pa];
 #pragma unroll
       for (int a = 0; a < RA; ++a)
 #pragma unroll
-        for (int b = 0; b < RB; ++b) M[a][b] = __fma_rn(-fr[a], gs[b], M[a][b]);
-      rd = rd_next;
+        for (int b = 0; b < RB; ++b)
+          M[a][b] = __fma_rn(-f1[a], g1[b], __fma_rn(-f0[a], g0[b], M[a][b]));
+      if (nxt2) {
+        e11 = n22 * rn; e12 = -n12 * rn; e22 = n11 * rn;
+      } else {
+        e11 = rn; e12 = 0.0; e22 = 0.0;
+      }
     }
   }
 
