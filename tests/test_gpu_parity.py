@@ -118,17 +118,26 @@ def test_single_column_rank_one(rlu):
     out, o = run_and_compare(rlu, A, 1, 3, G, "rank one")
 
 
-def test_zero_matrix_sets_info(rlu):
+@pytest.mark.parametrize("power", [0, 1, 2])
+def test_zero_matrix_sets_info(rlu, power):
+    # with power iterations every normalization meets only zero pivots too
     A = np.zeros((64, 48))
     G = workloads.gaussian((48, 6), 3)
-    out = rlu.factor(to_dev_colmajor(A), 4, 6, G=to_dev_colmajor(G), diagnostics=True)
+    print(f"[parity] zero matrix power={power}", flush=True)
+    out = rlu.factor(to_dev_colmajor(A), 4, 6, G=to_dev_colmajor(G), diagnostics=True,
+                     power_iters=power)
     torch.cuda.synchronize()
+    o = orl.randomized_lu(A, 4, 6, G, q=power)
+    assert o["info"] == (1, 1)
     info = to_host(out.info)
     assert tuple(info) == (1, 1, 0)
     assert rlu.check_info(info) == 2  # RLU_WARN_ZERO_PIVOT
     L, U = to_host(out.L), to_host(out.U)
     assert np.all(U == 0.0)
     assert np.all(np.diag(L[:4]) == 1.0)
+    np.testing.assert_array_equal(L, o["L"])
+    np.testing.assert_array_equal(to_host(out.p), o["p"])
+    np.testing.assert_array_equal(to_host(out.q), o["q"])
 
 
 def test_rank_deficient_second_pivot_zero(rlu):
