@@ -102,9 +102,9 @@ typedef struct {
                           becomes Y = (A A^T)^q A G, each product but the last
                           replaced by the unit-lower factor of its pivoted LU
                           (same column space; see rlu_factor).  0 = plain
-                          Step 2.  rlu_factor and the server (such a request
-                          runs alone, through rlu_factor); the batched form
-                          returns RLU_ERR_UNSUPPORTED for q != 0. */
+                          Step 2.  In rlu_factor_batched every problem of a
+                          call must have the same q (else RLU_ERR_INVALID_ARG);
+                          the server runs a request with q != 0 alone. */
 } rlu_problem_t;
 
 #define RLU_MAX_POWER_ITERS 16

@@ -357,9 +357,11 @@ class Batch:
     arrays stay alive (and unchanged) so that repeated calls replay the
     library's recorded launch graph."""
 
-    def __init__(self, problems, *, precision: int | None = None, outs=None):
+    def __init__(self, problems, *, precision: int | None = None, outs=None,
+                 power_iters: int = 0):
         """problems: sequence of (A, k, l) or (A, k, l, seed) or
-        (A, k, l, seed, G) with A a column-major device tensor."""
+        (A, k, l, seed, G) with A a column-major device tensor; power_iters
+        (Section 5.2) applies to every problem."""
         items = [tuple(p) + (0, None)[len(p) - 3:] if len(p) < 5 else tuple(p) for p in problems]
         self.count = len(items)
         self.pbs = (Problem * max(1, self.count))()
@@ -368,7 +370,7 @@ class Batch:
         self.inputs = []
         for i, (A, k, l, seed, G) in enumerate(items):
             o = outs[i] if outs is not None else None
-            pb, io, o = _prepare(A, k, l, precision, seed, G, False, o)
+            pb, io, o = _prepare(A, k, l, precision, seed, G, False, o, power_iters)
             self.pbs[i] = pb
             self.ios[i] = io
             self.outs.append(o)
@@ -389,11 +391,13 @@ class Batch:
 
 
 def factor_batched(problems, *, precision: int | None = None, handle: Handle | None = None,
-                   stream=None, outs=None) -> list:
+                   stream=None, outs=None, power_iters: int = 0) -> list:
     """Algorithm 4.1 for every (A, k, l[, seed[, G]]) in `problems`, as one
-    batched call.  Returns a list of Factors (device tensors, not
+    batched call (with q = power_iters power iterations, Section 5.2, for
+    all of them).  Returns a list of Factors (device tensors, not
     synchronized)."""
-    return Batch(problems, precision=precision, outs=outs).run(handle, stream)
+    return Batch(problems, precision=precision, outs=outs,
+                 power_iters=power_iters).run(handle, stream)
 
 
 def tile_names() -> dict:

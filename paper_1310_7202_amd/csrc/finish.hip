@@ -92,6 +92,21 @@ __global__ void __launch_bounds__(256) lv_dense_kernel(const double* __restrict_
   }
 }
 
+// Batched form of lv_dense_kernel over strided panels: out(i, c) =
+// Lv(i, c) of the panel whose entry (i, c) is X[i rs + c cs].
+template <typename TO>
+__global__ void __launch_bounds__(256) lv_dense_batched_kernel(
+    const LvDenseTaskDev* __restrict__ tasks) {
+  const LvDenseTaskDev t = tasks[blockIdx.y];
+  const int64_t total = t.rows * t.cols;
+  TO* out = (TO*)t.out;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % t.rows, c = e / t.rows;
+    out[i + c * t.ldo] = (TO)lv_value<double>(t.X[i * t.rs + c * t.cs], (int)c, t.rstep[i]);
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) copy2d_kernel(const T* __restrict__ src, int64_t lds,
                                                      T* __restrict__ dst, int64_t ldd,
@@ -253,6 +268,20 @@ template hipError_t launch_lv_dense<double>(const double*, int64_t, const int*, 
                                             int64_t, int64_t, hipStream_t);
 template hipError_t launch_lv_dense<float>(const double*, int64_t, const int*, float*, int64_t,
                                            int64_t, int64_t, hipStream_t);
+
+template <typename TO>
+hipError_t launch_lv_dense_batched(const LvDenseTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((lv_dense_batched_kernel<TO>), dim3(grid_for(max_elems, 2048), (unsigned)count),
+                     dim3(256), 0, s, tasks);
+  return hipGetLastError();
+}
+template hipError_t launch_lv_dense_batched<double>(const LvDenseTaskDev*, int, int64_t,
+                                                    hipStream_t);
+template hipError_t launch_lv_dense_batched<float>(const LvDenseTaskDev*, int, int64_t,
+                                                   hipStream_t);
 
 template <typename T>
 hipError_t launch_copy2d(const T* src, int64_t lds, T* dst, int64_t ldd, int64_t rows,

@@ -41,10 +41,16 @@ struct Item {
   size_t G = 0, Y = 0, S = 0, gj = 0, part = 0, C = 0, Bst = 0, Lb = 0;
   size_t pos_y = 0, rstep_y = 0, piv_y = 0, ipiv_y = 0;
   size_t pos_b = 0, rstep_b = 0, piv_b = 0, ipiv_b = 0;
-  size_t flags = 0, xy = 0, xb = 0;  // cleared before each run
+  size_t flags = 0, xy = 0, xb = 0, xz = 0;  // cleared before each run
+  size_t zt = 0, gz = 0, piv_z = 0, ipiv_z = 0;  // power iterations (Section 5.2)
   int gram_ks = 1;
-  int nwg_y = 0, R_y = 0, nwg_b = 0, R_b = 0;
+  int nwg_y = 0, R_y = 0, nwg_b = 0, R_b = 0, nwg_z = 0, R_z = 0;
 };
+
+// The four panel runs: Step 3 on Y, Step 6 on B^T, and the two
+// normalizations of the power iterations, on Y (zero pivots recorded apart
+// from Step 3's) and on Z^T (n x l, stored l x n like B^T).
+enum class PanelRun { Y, BT, YNorm, Z };
 
 struct GemmLaunch {
   int cfg = 0;
@@ -73,6 +79,13 @@ struct Plan {
   std::vector<GemmLaunch> sketch, gram, project, solve, forml;
   size_t gram_all = 0; int gram_count = 0; int64_t gram_max = 0; bool gram_split = false;
   PanelLaunch py, pbt;
+  // power iterations: q rounds of panel(Y), Z^T = Lv^T A, panel(Z), the
+  // dense Lv(Z), Y = A Lv(Z); the exchange areas are cleared before each run
+  int power = 0;
+  size_t xch_begin = 0;   // [xch_begin, zero_bytes): the exchange areas
+  std::vector<GemmLaunch> zproj, resketch;
+  PanelLaunch pyn, pz;
+  size_t lvd = 0; int64_t lvd_max = 0;
   size_t spd = 0; int64_t kmax = 0;
   size_t asmb = 0; int64_t asm_max = 0;
 };
@@ -235,19 +248,21 @@ int schedule_gangs(const std::vector<int>& nwg, const std::vector<int>& ncols, i
   return (int)rounds.size();
 }
 
-rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableWriter& tw,
+rlu_status_t plan_panels(const Plan& P, PanelRun run, int cus, char* base, TableWriter& tw,
                          PanelLaunch& L) {
+  const bool second = run == PanelRun::BT;
+  const bool zrun = run == PanelRun::Z;
   // every problem keeps its own rows per workgroup (the most its width
   // allows); the launch is compiled for the largest and sized for the
   // largest LDS image, including the bulk update's read of a full 64 * RPL
   // rows past the last column of a shorter block
   int R = 0;
   size_t lds = 0;
-  for (const Item& it : P.items) R = std::max(R, second ? it.R_b : it.R_y);
+  for (const Item& it : P.items) R = std::max(R, second ? it.R_b : zrun ? it.R_z : it.R_y);
   if (R == 0) return RLU_ERR_UNSUPPORTED;
   const int rmax = R <= 64 ? 64 : R <= 128 ? 128 : R <= 256 ? 256 : 512;
   for (const Item& it : P.items) {
-    const int r = second ? it.R_b : it.R_y;
+    const int r = second ? it.R_b : zrun ? it.R_z : it.R_y;
     const int c = (int)(second ? it.pb.k : it.pb.l);
     lds = std::max(lds, panel_lds_bytes(r, c));
     lds = std::max(lds, (size_t)8 * ((size_t)(c - 1) * r + rmax));
@@ -264,13 +279,21 @@ rlu_status_t plan_panels(const Plan& P, bool second, int cus, char* base, TableW
   std::vector<int> nwg, ncols;
   for (const Item& it : P.items) {
     PanelTaskDev t{};
-    if (!second) {
+    if (zrun) {
+      t.X = (double*)(base + it.zt); t.rs = it.pb.l; t.cs = 1;
+      t.nrows = (int)it.pb.n; t.ncols = (int)it.pb.l;
+      t.nwg = it.nwg_z; t.R = it.R_z;
+      t.pos = (int*)(base + it.pos_b); t.rstep = (int*)(base + it.rstep_b);
+      t.piv_row = (int*)(base + it.piv_z); t.ipiv = (int*)(base + it.ipiv_z);
+      t.info = (int*)(base + it.flags) + 3;
+      t.xch = base + it.xz;
+    } else if (!second) {
       t.X = (double*)(base + it.Y); t.rs = 1; t.cs = it.pb.m;
       t.nrows = (int)it.pb.m; t.ncols = (int)it.pb.l;
       t.nwg = it.nwg_y; t.R = it.R_y;
       t.pos = (int*)(base + it.pos_y); t.rstep = (int*)(base + it.rstep_y);
       t.piv_row = (int*)(base + it.piv_y); t.ipiv = (int*)(base + it.ipiv_y);
-      t.info = (int*)(base + it.flags) + 0;
+      t.info = (int*)(base + it.flags) + (run == PanelRun::YNorm ? 3 : 0);
       t.xch = base + it.xy;
     } else {
       t.X = (double*)(base + it.Bst); t.rs = it.pb.k; t.cs = 1;
@@ -316,7 +339,9 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     slot = off;
     off = align_up(off + std::max<size_t>(bytes, 1));
   };
-  // cleared region first
+  P.power = pbs[0].power_iters;
+  // cleared region first: the flags of every problem, then the exchange
+  // areas (which the power iterations clear again before each panel run)
   for (int i = 0; i < count; ++i) {
     Item& it = P.items[i];
     it.pb = pbs[i];
@@ -328,9 +353,19 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     it.R_y = (int)((pb.m + it.nwg_y - 1) / it.nwg_y);
     it.nwg_b = (int)((pb.n + Rb - 1) / Rb);
     it.R_b = (int)((pb.n + it.nwg_b - 1) / it.nwg_b);
+    if (P.power > 0) {
+      it.nwg_z = (int)((pb.n + Ry - 1) / Ry);
+      it.R_z = (int)((pb.n + it.nwg_z - 1) / it.nwg_z);
+    }
     take(it.flags, 64);
+  }
+  P.xch_begin = off;
+  for (int i = 0; i < count; ++i) {
+    Item& it = P.items[i];
+    const rlu_problem_t& pb = it.pb;
     take(it.xy, it.nwg_y > 1 ? panel_xch_bytes(it.nwg_y, (int)pb.l) : 0);
     take(it.xb, it.nwg_b > 1 ? panel_xch_bytes(it.nwg_b, (int)pb.k) : 0);
+    take(it.xz, it.nwg_z > 1 ? panel_xch_bytes(it.nwg_z, (int)pb.l) : 0);
   }
   P.zero_bytes = off;
   const size_t d = sizeof(double);
@@ -355,6 +390,11 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
     take(it.rstep_b, (size_t)n * 4);
     take(it.piv_b, (size_t)k * 4);
     take(it.ipiv_b, (size_t)k * 4);
+    const bool pw = P.power > 0;
+    take(it.zt, pw ? (size_t)l * n * d : 0);
+    take(it.gz, pw ? (size_t)n * l * sa : 0);
+    take(it.piv_z, pw ? (size_t)l * 4 : 0);
+    take(it.ipiv_z, pw ? (size_t)l * 4 : 0);
   }
   P.data_end = off;
   P.tab_off = off;
@@ -365,6 +405,7 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
 rlu_status_t build_tables(Plan& P, char* base, int cus) {
   P.tab.clear();
   P.sketch.clear(); P.gram.clear(); P.project.clear(); P.solve.clear(); P.forml.clear();
+  P.zproj.clear(); P.resketch.clear();
   TableWriter tw(P.tab);
   // Step 1
   std::vector<GaussTaskDev> gauss;
@@ -393,8 +434,46 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
     }
     add_gemm_launches(tw, t, cfg, P.lp, P.sketch);
   }
+  // Section 5.2: the tables of one round of the power iterations
+  if (P.power > 0) {
+    rlu_status_t st = plan_panels(P, PanelRun::YNorm, cus, base, tw, P.pyn);
+    if (st != RLU_OK) return st;
+    std::vector<GemmTaskDev> t, r;
+    std::vector<int> cfg, rcfg;
+    std::vector<LvDenseTaskDev> lv;
+    P.lvd_max = 0;
+    for (const Item& it : P.items) {
+      GemmTaskDev g{};  // Z^T = Lv(Y)^T A  (l x n)
+      g.M = it.pb.l; g.N = it.pb.n; g.K = it.pb.m;
+      g.A = base + it.Y; g.lda = it.pb.m; g.astep = (const int*)(base + it.rstep_y);
+      g.B = it.io.A; g.ldb = it.io.lda;
+      g.C = base + it.zt; g.ldc = it.pb.l;
+      g.ksplit = 1;
+      t.push_back(g);
+      cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Project, g.N));
+      LvDenseTaskDev x{};  // Lv(Z), n x l, in the storage type
+      x.X = (const double*)(base + it.zt); x.rs = it.pb.l; x.cs = 1;
+      x.rstep = (const int*)(base + it.rstep_b);
+      x.out = base + it.gz; x.ldo = it.pb.n; x.rows = it.pb.n; x.cols = it.pb.l;
+      lv.push_back(x);
+      P.lvd_max = std::max<int64_t>(P.lvd_max, it.pb.n * it.pb.l);
+      GemmTaskDev y{};  // Y = A Lv(Z)
+      y.M = it.pb.m; y.N = it.pb.l; y.K = it.pb.n;
+      y.A = it.io.A; y.lda = it.io.lda;
+      y.B = base + it.gz; y.ldb = it.pb.n;
+      y.C = base + it.Y; y.ldc = it.pb.m;
+      y.ksplit = 1;
+      r.push_back(y);
+      rcfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Sketch, y.N));
+    }
+    add_gemm_launches(tw, t, cfg, P.lp, P.zproj);
+    st = plan_panels(P, PanelRun::Z, cus, base, tw, P.pz);
+    if (st != RLU_OK) return st;
+    P.lvd = tw.put(lv);
+    add_gemm_launches(tw, r, rcfg, P.lp, P.resketch);
+  }
   // Step 3
-  rlu_status_t st = plan_panels(P, false, cus, base, tw, P.py);
+  rlu_status_t st = plan_panels(P, PanelRun::Y, cus, base, tw, P.py);
   if (st != RLU_OK) return st;
   // Step 5: S = Lv^T Lv (split K), S <- S^{-1}, C = Lv^T A, B = S^{-1} C
   {
@@ -463,7 +542,7 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
     add_gemm_launches(tw, t, cfg, false, P.solve);
   }
   // Step 6
-  st = plan_panels(P, true, cus, base, tw, P.pbt);
+  st = plan_panels(P, PanelRun::BT, cus, base, tw, P.pbt);
   if (st != RLU_OK) return st;
   // Steps 7-8
   {
@@ -548,6 +627,24 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
     PhaseScope ph(h, PH_SKETCH, s);
     rlu_status_t st = enqueue_gemms(P.sketch, tab, GemmRole::Sketch, OpA::Plain, P.f32, P.fp16, s);
     if (st != RLU_OK) return st;
+  }
+  if (P.power > 0) {
+    PhaseScope ph(h, PH_POWER, s);
+    uint32_t* xch = (uint32_t*)(base + P.xch_begin);
+    const size_t xwords = (P.zero_bytes - P.xch_begin) / 4;
+    for (int r = 0; r < P.power; ++r) {
+      HIP_TRY(launch_fill_u32(xch, xwords, 0u, s));
+      HIP_TRY(gated_panel(P.pyn, tab, gate, s));
+      rlu_status_t st = enqueue_gemms(P.zproj, tab, GemmRole::Project, OpA::LvT, P.f32, P.fp16, s);
+      if (st != RLU_OK) return st;
+      HIP_TRY(launch_fill_u32(xch, xwords, 0u, s));
+      HIP_TRY(gated_panel(P.pz, tab, gate, s));
+      HIP_TRY(launch_lv_dense_batched<T>((const LvDenseTaskDev*)(tab + P.lvd), count, P.lvd_max,
+                                         s));
+      st = enqueue_gemms(P.resketch, tab, GemmRole::Sketch, OpA::Plain, P.f32, P.fp16, s);
+      if (st != RLU_OK) return st;
+    }
+    HIP_TRY(launch_fill_u32(xch, xwords, 0u, s));
   }
   {
     PhaseScope ph(h, PH_PANEL_Y, s);
@@ -741,7 +838,7 @@ rlu_status_t batched_validate(int count, const rlu_problem_t* pbs, const rlu_buf
       if (st != RLU_OK) return st;
     }
     if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
-    if (pbs[i].power_iters != 0) return RLU_ERR_UNSUPPORTED;
+    if (pbs[i].power_iters != pbs[0].power_iters) return RLU_ERR_INVALID_ARG;
     if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
       return RLU_ERR_INVALID_ARG;
   }

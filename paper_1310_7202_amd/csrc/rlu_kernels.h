@@ -198,6 +198,15 @@ hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s)
 template <typename TO>
 hipError_t launch_lv_dense(const double* X, int64_t ldx, const int* rstep, TO* out, int64_t ldo,
                            int64_t rows, int64_t cols, hipStream_t s);
+// Batched: task t gives out (rows x cols, TO, ld ldo) = Lv of the panel whose
+// entry (i, c) is X[i rs + c cs] (max_elems = largest rows cols).
+struct LvDenseTaskDev {
+  const double* X; int64_t rs, cs; const int* rstep;
+  void* out; int64_t ldo, rows, cols;
+};
+template <typename TO>
+hipError_t launch_lv_dense_batched(const LvDenseTaskDev* tasks, int count, int64_t max_elems,
+                                   hipStream_t s);
 hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
                              int32_t* info_out, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);

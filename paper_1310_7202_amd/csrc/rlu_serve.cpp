@@ -83,8 +83,8 @@ size_t output_layout(const rlu_problem_t& pb, size_t* offU, size_t* offp, size_t
 // batched kernels cannot run or a request with power iterations, the
 // single-problem workspace (it then runs alone through rlu_factor).
 
-// Argument checks of a request: those of the batched form, except that
-// power iterations are allowed (such a request runs alone).
+// Argument checks of a request: those of the batched form for the request
+// on its own (a request with power iterations runs alone).
 rlu_status_t request_validate(const rlu_problem_t* pb) {
   if (!pb) return RLU_ERR_INVALID_ARG;
   rlu_status_t st = validate(pb);
@@ -96,7 +96,8 @@ rlu_status_t request_validate(const rlu_problem_t* pb) {
 
 rlu_status_t request_ws_bytes(const rlu_problem_t& pb, int cus, size_t* bytes, bool* solo) {
   *solo = false;
-  // power iterations (Section 5.2) exist only on the single-problem path
+  // a request with power iterations (Section 5.2) runs alone, so that the
+  // batches the server forms keep one q
   rlu_status_t st = pb.power_iters != 0 ? RLU_ERR_UNSUPPORTED : batched_item_bytes(pb, cus, bytes);
   if (st != RLU_ERR_UNSUPPORTED) return st;
   st = rlu_workspace_size(&pb, bytes);

@@ -95,8 +95,8 @@ def test_power_iterations_range_and_workspace(rlu):
     assert b - a >= 2 * 8 * 3000 * 48 - 4096 and c == b  # slots are 256-byte aligned
     st3, d = _ws(rlu, 4096, 3000, 40, 48, G=1, ldg=3000, power_iters=1)
     assert st3 == 0 and d == b
-    # the batched form does not take power iterations; the server runs such
-    # a request alone, so its footprint is the single-problem workspace
+    # the server runs a request with power iterations alone, so its
+    # footprint is the single-problem workspace
     pb = rlu.Problem(512, 512, 10, 15, 0, 0, 0, None, 0, 0, 1)
     out = ctypes.c_size_t()
     assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == 0
@@ -108,8 +108,11 @@ def test_power_iterations_range_and_workspace(rlu):
     io.A = io.L = io.U = io.p = io.q = io.info = 1
     io.lda = io.ldl = 512
     io.ldu = 10
-    assert rlu.lib().rlu_factor_batched(ctypes.c_void_p(1), 1, ctypes.byref(pb),
-                                        ctypes.byref(io), None) == -8
+    # one q per batched call
+    pbs = (rlu.Problem * 2)(rlu.Problem(512, 512, 10, 15, 0, 0, 0, None, 0, 0, 1),
+                            rlu.Problem(512, 512, 10, 15, 0, 0, 0, None, 0, 0, 2))
+    ios = (rlu.Buffers * 2)(io, io)
+    assert rlu.lib().rlu_factor_batched(ctypes.c_void_p(1), 2, pbs, ios, None) == -1
 
 
 def test_factor_rejects_null_handle_and_buffers(rlu):

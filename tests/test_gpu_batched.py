@@ -279,3 +279,64 @@ def test_batched_blocked_gram_inverse(rlu):
     for (A, k, l, G), f in zip(probs, outs):
         _check_f64(A, k, l, G, to_host(f.L), to_host(f.U), to_host(f.p), to_host(f.q),
                    to_host(f.info), label=f"{A.shape} k={k}")
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_batched_power_iterations(rlu, q):
+    """Section 5.2 in the batched form: every problem equals a single
+    rlu_factor call with the same q (FP64 rule) and the oracle's power
+    scheme; replaying the recorded graph gives the same factors."""
+    shapes = [(300, 500, 8, 16, 4.0), (1200, 700, 40, 48, 12.0), (2048, 1500, 64, 72, 20.0),
+              (97, 131, 5, 9, 3.0), (1500, 3000, 30, 38, 10.0), (4096, 300, 12, 20, 5.0)]
+    probs = []
+    for i, (m, n, k, l, rate) in enumerate(shapes):
+        A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), rate), 1300 + i)
+        G = workloads.gaussian((n, l), 1350 + i)
+        probs.append((A, k, l, G))
+    print(f"[batched] power q={q}, {len(probs)} problems", flush=True)
+    items = [(to_dev_colmajor(A), k, l, 0, to_dev_colmajor(G)) for A, k, l, G in probs]
+    batch = rlu.Batch(items, power_iters=q)
+    outs = batch.run()
+    torch.cuda.synchronize()
+    first = [(to_host(f.L).copy(), to_host(f.U).copy()) for f in outs]
+    singles = [rlu.factor(Ad, k, l, G=Gd, power_iters=q) for Ad, k, l, _, Gd in items]
+    torch.cuda.synchronize()
+    for (A, k, l, G), fb, fs in zip(probs, outs, singles):
+        o = orl.randomized_lu(A, k, l, G, q=q)
+        _check_f64(A, k, l, G, to_host(fb.L), to_host(fb.U), to_host(fb.p), to_host(fb.q),
+                   to_host(fb.info), o=o, label=f"{A.shape} k={k} q={q}")
+        np.testing.assert_array_equal(to_host(fb.q), to_host(fs.q))
+        assert rel_maxdiff(to_host(fb.U), to_host(fs.U)) < TOL
+    outs = batch.run()  # graph replay
+    torch.cuda.synchronize()
+    for (L0, U0), f in zip(first, outs):
+        np.testing.assert_array_equal(to_host(f.L), L0)
+        np.testing.assert_array_equal(to_host(f.U), U0)
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_batched_power_iterations_reduced_precision(rlu, precision):
+    """FP32 and BF16 batches with one power iteration: the residual rule
+    against the oracle's power scheme on the same FP32 matrix."""
+    shapes = [(1800, 1500, 30, 38), (900, 1200, 20, 26), (2500, 700, 24, 32)]
+    items, probs = [], []
+    for i, (m, n, k, l) in enumerate(shapes):
+        sig = workloads.slow_decay(min(m, n))
+        A32 = workloads.spectral_matrix(m, n, sig / sig[0], 1400 + i).astype(np.float32)
+        G32 = workloads.gaussian((n, l), 1450 + i).astype(np.float32)
+        probs.append((A32, k, l, G32))
+        items.append((to_dev_colmajor(A32, dtype=torch.float32), k, l, 0,
+                      to_dev_colmajor(G32, dtype=torch.float32)))
+    print(f"[batched] power q=1 precision={precision}", flush=True)
+    outs = rlu.factor_batched(items, precision=precision, power_iters=1)
+    torch.cuda.synchronize()
+    for (A32, k, l, G32), f in zip(probs, outs):
+        A = A32.astype(np.float64)
+        o = orl.randomized_lu(A, k, l, G32.astype(np.float64), q=1)
+        g = {"L": to_host(f.L).astype(np.float64), "U": to_host(f.U).astype(np.float64),
+             "p": to_host(f.p), "q": to_host(f.q)}
+        assert to_host(f.info)[2] == 0
+        r_gpu = orl.relative_residual(A, g)
+        r_ora = orl.relative_residual(A, o)
+        print(f"  {A.shape} k={k} residual gpu {r_gpu:.3e} oracle {r_ora:.3e}", flush=True)
+        assert r_gpu <= r_ora + BAR
