@@ -14,7 +14,7 @@ namespace rlu {
 namespace {
 
 // ---------------------------------------------------------------------------
-// The symmetric sweep operator, 64 pivots per launch.  Sweeping pivot p of
+// The symmetric sweep operator, GB pivots per launch.  Sweeping pivot p of
 // a matrix M replaces
 //   M[r][s] by M[r][s] - M[r][p] M[p][s] / M[p][p]     (r, s != p)
 //   M[r][p] by M[r][p] / M[p][p],  M[p][s] by M[p][s] / M[p][p]
@@ -24,7 +24,7 @@ namespace {
 // is a Schur complement of the SPD matrix S, hence positive.
 //
 // The new value of an entry (r, s) under the sweep of a pivot set J depends
-// only on rows J + {r} and columns J + {s}.  So launch J gives each 64 x 64
+// only on rows J + {r} and columns J + {s}.  So launch J gives each GB x GB
 // tile (I, c) of S one workgroup, which gathers the augmented matrix
 //   [ S_JJ  S_Jc ]
 //   [ S_IJ  S_Ic ]      (rows I and columns c left out when I = J or c = J)
@@ -33,29 +33,36 @@ namespace {
 // alternating so that the last launch writes S); the last launch also
 // negates.
 // ---------------------------------------------------------------------------
-constexpr int GB = 64;
-constexpr int kSwThreads = 256;  // 16 x 16 threads, 8 x 8 entries each
+// The block size GB is 64 for k <= 64 (one launch in place) and 32 above:
+// a 32-block launch gives each workgroup a quarter of the work (a 64 x 64
+// augmented matrix) on four times as many CUs, at the cost of twice as many
+// launches.
+constexpr int kSwThreads = 256;  // 16 x 16 threads, (2 GB / 16)^2 entries each
 
+template <int GB>
 __device__ __forceinline__ int blk_size(int k, int J) { return min(GB, k - GB * J); }
+template <int GB>
 __device__ __forceinline__ int num_blocks(int k) { return (k + GB - 1) / GB; }
 // launch J writes S when an even number of launches follow it
 __device__ __forceinline__ bool writes_s(int nb, int J) { return ((nb - 1 - J) & 1) == 0; }
 
 // odd block counts start from the copy in scratch (so that the last launch
 // still writes S): copy S there first
+template <int GB>
 __global__ void __launch_bounds__(256) sweep_copy_kernel(const SpdTaskDev* __restrict__ tasks,
                                                          SpdTaskDev one) {
   const SpdTaskDev t = tasks ? tasks[blockIdx.y] : one;
-  const int nb = num_blocks(t.k);
+  const int nb = num_blocks<GB>(t.k);
   if (nb < 2 || !writes_s(nb, 0)) return;
   const int64_t kk = (int64_t)t.k * t.k;
   for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < kk; e += (int64_t)gridDim.x * 256)
     t.scratch[e] = t.S[e];
 }
 
-// One tile: RA = 8 when the augmented matrix has the rows of block I (I != J),
-// else 4; RB likewise for the columns of block c.  Thread (ty, tx) holds
-// augmented rows ty + 16 a and columns tx + 16 b.
+// One tile: RA = 2 S (S = GB / 16 register slots per block) when the
+// augmented matrix has the rows of block I (I != J), else S; RB likewise for
+// the columns of block c.  Thread (ty, tx) holds augmented rows ty + 16 a and
+// columns tx + 16 b.
 //
 // Pivots are swept two at a time: sweeping the pair J2 = {p, p + 1} at once
 // is the same as sweeping p and then p + 1 (the sweep of a block replaces
@@ -67,10 +74,11 @@ __global__ void __launch_bounds__(256) sweep_copy_kernel(const SpdTaskDev* __res
 // the same LDS values, forms the next pair's block and its inverse, so the
 // division leaves the critical path.  An odd last pivot is a pair whose
 // second member is absent (zero row and column, D = diag(d, 1)).
-template <int RA, int RB>
+template <int GB, int RA, int RB>
 __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double* __restrict__ out,
                                            int k, int J, int I, int cb, bool last) {
-  const int bj = blk_size(k, J), bi = blk_size(k, I), bc = blk_size(k, cb);
+  constexpr int S = GB / 16;
+  const int bj = blk_size<GB>(k, J), bi = blk_size<GB>(k, I), bc = blk_size<GB>(k, cb);
   __shared__ double colb[2][2][2 * GB];  // [parity][member of the pair][augmented row]
   __shared__ double rowb[2][2][2 * GB];
   __shared__ double dnx[2][3];           // next pair's block before this step
@@ -79,13 +87,13 @@ __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double
 #pragma unroll
   for (int a = 0; a < RA; ++a) {
     const int r = ty + 16 * a;
-    const bool rin = a < 4 ? r < bj : r - GB < bi;
-    const int64_t gr = a < 4 ? (int64_t)GB * J + r : (int64_t)GB * I + (r - GB);
+    const bool rin = a < S ? r < bj : r - GB < bi;
+    const int64_t gr = a < S ? (int64_t)GB * J + r : (int64_t)GB * I + (r - GB);
 #pragma unroll
     for (int b = 0; b < RB; ++b) {
       const int c = tx + 16 * b;
-      const bool cin = b < 4 ? c < bj : c - GB < bc;
-      const int64_t gc = b < 4 ? (int64_t)GB * J + c : (int64_t)GB * cb + (c - GB);
+      const bool cin = b < S ? c < bj : c - GB < bc;
+      const int64_t gc = b < S ? (int64_t)GB * J + c : (int64_t)GB * cb + (c - GB);
       M[a][b] = (rin && cin) ? in[gr + gc * k] : 0.0;
     }
   }
@@ -107,8 +115,8 @@ __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double
   // pa of the threads with ty (rows) or tx (columns) = pt, pt + 1; pa is
   // unrolled so that every register index is static
 #pragma unroll
-  for (int pa = 0; pa < 4; ++pa) {
-    const int pn = pa < 3 ? pa + 1 : 3;
+  for (int pa = 0; pa < S; ++pa) {
+    const int pn = pa < S - 1 ? pa + 1 : S - 1;
     for (int pt = 0; pt < 16; pt += 2) {
       const int p = 16 * pa + pt;
       if (p >= bj) break;
@@ -190,7 +198,7 @@ __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double
   }
 
   // the (I, c) part of the augmented matrix
-  constexpr int a0 = RA == 8 ? 4 : 0, b0 = RB == 8 ? 4 : 0;
+  constexpr int a0 = RA == 2 * S ? S : 0, b0 = RB == 2 * S ? S : 0;
 #pragma unroll
   for (int a = a0; a < RA; ++a) {
     const int i = ty + 16 * (a - a0);
@@ -204,10 +212,12 @@ __device__ __forceinline__ void sweep_tile(const double* __restrict__ in, double
   }
 }
 
+template <int GB>
 __global__ void __launch_bounds__(kSwThreads) sweep_step_kernel(const SpdTaskDev* __restrict__ tasks,
                                                                SpdTaskDev one, int J) {
+  constexpr int S = GB / 16;
   const SpdTaskDev t = tasks ? tasks[blockIdx.y] : one;
-  const int k = t.k, nb = num_blocks(k);
+  const int k = t.k, nb = num_blocks<GB>(k);
   if (J >= nb || (int)blockIdx.x >= nb * nb) return;
   const int I = blockIdx.x % nb, cb = blockIdx.x / nb;
   const double* in;
@@ -221,11 +231,11 @@ __global__ void __launch_bounds__(kSwThreads) sweep_step_kernel(const SpdTaskDev
   }
   const bool last = J == nb - 1;
   if (I != J) {
-    if (cb != J) sweep_tile<8, 8>(in, out, k, J, I, cb, last);
-    else sweep_tile<8, 4>(in, out, k, J, I, cb, last);
+    if (cb != J) sweep_tile<GB, 2 * S, 2 * S>(in, out, k, J, I, cb, last);
+    else sweep_tile<GB, 2 * S, S>(in, out, k, J, I, cb, last);
   } else {
-    if (cb != J) sweep_tile<4, 8>(in, out, k, J, I, cb, last);
-    else sweep_tile<4, 4>(in, out, k, J, I, cb, last);
+    if (cb != J) sweep_tile<GB, S, 2 * S>(in, out, k, J, I, cb, last);
+    else sweep_tile<GB, S, S>(in, out, k, J, I, cb, last);
   }
 }
 
@@ -236,23 +246,31 @@ bool spd_inverse_supported(int64_t k) { return k >= 1 && k <= kSpdMaxK; }
 size_t spd_inverse_scratch_elems(int64_t k) { return (size_t)k * (size_t)k; }
 
 namespace {
-hipError_t sweep_steps(const SpdTaskDev* tasks, SpdTaskDev one, int count, int64_t kmax,
-                       hipStream_t s) {
+template <int GB>
+hipError_t sweep_steps_gb(const SpdTaskDev* tasks, SpdTaskDev one, int count, int64_t kmax,
+                          hipStream_t s) {
   const int nb = (int)((kmax + GB - 1) / GB);
   if (nb >= 2) {
     const unsigned g = (unsigned)std::min<int64_t>((kmax * kmax + 255) / 256, 1024);
-    hipLaunchKernelGGL(sweep_copy_kernel, dim3(g, (unsigned)count), dim3(256), 0, s, tasks, one);
+    hipLaunchKernelGGL(sweep_copy_kernel<GB>, dim3(g, (unsigned)count), dim3(256), 0, s, tasks,
+                       one);
   }
   for (int J = 0; J < nb; ++J)
-    hipLaunchKernelGGL(sweep_step_kernel, dim3((unsigned)(nb * nb), (unsigned)count),
+    hipLaunchKernelGGL(sweep_step_kernel<GB>, dim3((unsigned)(nb * nb), (unsigned)count),
                        dim3(kSwThreads), 0, s, tasks, one, J);
   return hipGetLastError();
+}
+
+hipError_t sweep_steps(const SpdTaskDev* tasks, SpdTaskDev one, int count, int64_t kmax,
+                       hipStream_t s) {
+  return kmax > 64 ? sweep_steps_gb<32>(tasks, one, count, kmax, s)
+                   : sweep_steps_gb<64>(tasks, one, count, kmax, s);
 }
 }  // namespace
 
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s) {
   if (!spd_inverse_supported(k)) return hipErrorInvalidValue;
-  if (k > GB && !scratch) return hipErrorInvalidValue;
+  if (k > 64 && !scratch) return hipErrorInvalidValue;
   return sweep_steps(nullptr, SpdTaskDev{S, (int)k, scratch}, 1, k, s);
 }
 
