@@ -313,7 +313,8 @@ int g_force_cfg = -1;  // tuning override (-1: automatic)
 //     which measured fastest for it;
 //   * split-K raises the workgroup count to about four per CU (one
 //     workgroup per CU leaves the FP64 MFMA pipe idle at every barrier),
-//     keeping at least 512 of K per split.
+//     keeping at least 256 of K per split (the Gram product of Step 5 went
+//     from 55 to 51 us at 8192 x 200 with 256 workgroups instead of 128).
 GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
   GemmShape sh{C64x64x16, 1};
   // Long products with one short side (the two products with A): one
@@ -348,7 +349,7 @@ GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
   const CfgInfo& c = kCfg[sh.cfg];
   const int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
   int ks = 1;
-  while (tiles * ks < 1024 && K / (ks * 2) >= 512 && ks < 32) ks *= 2;
+  while (tiles * ks < 1024 && K / (ks * 2) >= 256 && ks < 32) ks *= 2;
   sh.ksplit = ks;
   return sh;
 }
