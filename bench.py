@@ -11,7 +11,7 @@ batched workload a step is one rlu_factor_batched call over 256 problems.
 Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
 under "forms", the same matrix through the FP32 path and with one power
 iteration (Section 5.2), least squares on its factors (Algorithm 4.3),
-the 16384 x 16384
+the 512 x 512 configuration's p50/p99 latency, the 16384 x 16384
 mixed-precision configuration beside the FP64 path on the same matrix, the
 256-problem batch, and the served request stream (throughput with p50/p99
 latency; disable the extra measurements with --forms none).  Only one GPU is used; --gpus N with
@@ -300,6 +300,37 @@ def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_
     return out, steps / wall, wall * 1e3 / steps, lat, ph
 
 
+def run_small(rlu, torch, np, calls=1000, warm=50):
+    """The 512 x 512 configuration (rank-10 + 1e-9 noise, k = 10, l = 15):
+    a latency-bound call; p50/p99 over `calls` calls after `warm` warm-up
+    calls (events around each call), plus the throughput of the sequence."""
+    A, k, l, sseed = make_input("small512", torch)
+    h = rlu.Handle(0)
+    st = torch.cuda.current_stream()
+    out = None
+    for _ in range(warm):
+        out = rlu.factor(A, k, l, seed=sseed, handle=h, stream=st, out=out)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(calls)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record(st)
+        rlu.factor(A, k, l, seed=sseed, handle=h, stream=st, out=out)
+        e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    rel = power_residual(A, out.L, out.U, out.p, out.q)
+    log(f"small512: p50 {np.percentile(lat, 50) * 1e3:.1f} us, p99 "
+        f"{np.percentile(lat, 99) * 1e3:.1f} us, residual {rel:.3e}")
+    return {"workload": WORKLOADS["small512"][8], "value": calls / wall,
+            "unit": "factorizations/s", "calls": calls, "warmup": warm,
+            "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                           "p99": float(np.percentile(lat, 99))},
+            "rel_residual": rel, "info": out.info.cpu().tolist()}
+
+
 def run_lstsq(rlu, torch, np, A, f, k, steps=20):
     """Algorithm 4.3 (Section 4.4) on the factors of the timed run: solve
     A x ~ b for b = A x0 (x0 Gaussian, fixed seed) with 1 and 64 right-hand
@@ -568,8 +599,8 @@ def main():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp32,power,lstsq,batch,mixed,serve",
-                    help="extra measurements in the same line: comma list of fp32, power, lstsq, batch, "
+    ap.add_argument("--forms", default="fp32,power,lstsq,small,batch,mixed,serve",
+                    help="extra measurements in the same line: comma list of fp32, power, lstsq, small, batch, "
                          "mixed, serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
@@ -702,6 +733,8 @@ def main():
             "info": outp.info.cpu().tolist()}
         log(f"power form: {vp:.1f}/s ({msp:.2f} ms), residual {rp:.3e} against {r0}")
         del outp
+    if "small" in forms:
+        result["forms"]["small512"] = run_small(rlu, torch, np)
     if "lstsq" in forms and name == "exp8192":
         result["forms"]["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
     if "mixed" in forms:

@@ -745,6 +745,11 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
                             : (const void*)panel_lu_kernel<8>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
   if (e != hipSuccess) return e;
+  // the pivot exchange needs every workgroup resident at once (cooperative
+  // launch); a single workgroup exchanges through LDS and needs no guarantee
+  if (nwg == 1)
+    return hipLaunchKernel(fn, dim3(1), dim3(threads_for_rows(R)), args, (unsigned)plan.lds_bytes,
+                           s);
   return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(threads_for_rows(R)), args,
                                     (unsigned)plan.lds_bytes, s);
 }
