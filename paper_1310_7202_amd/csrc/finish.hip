@@ -142,12 +142,14 @@ __global__ void __launch_bounds__(256) copy_i32_kernel(const int* __restrict__ s
     dst[e] = src[e];
 }
 
-// Steps 7-8 assembly for a batch (blockIdx.y = problem): the permutations p
-// and q from the row positions, U = U_b scattered by column position (the
-// same values build_u computes), L_b, and the info words.
+// Steps 7-8 assembly (blockIdx.y = problem of a batch, or the one task
+// passed by value): the permutations p and q from the row positions, U = U_b
+// scattered by column position (the same values build_u computes), L_b, and
+// the info words.
 template <typename TO>
-__global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev* __restrict__ tasks) {
-  const AsmTaskDev& t = tasks[blockIdx.y];
+__global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev* __restrict__ tasks,
+                                                               AsmTaskDev one) {
+  const AsmTaskDev t = tasks ? tasks[blockIdx.y] : one;
   const int64_t m = t.m, n = t.n, k = t.k;
   const int64_t e_q = m, e_u = m + n, e_lb = m + n + k * n, total = e_lb + k * k;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -321,11 +323,21 @@ hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t m
   if (bx < 1) bx = 1;
   if (bx > 128) bx = 128;
   hipLaunchKernelGGL(assemble_batched_kernel<TO>, dim3((unsigned)bx, (unsigned)count), dim3(256),
-                     0, s, tasks);
+                     0, s, tasks, AsmTaskDev{});
   return hipGetLastError();
 }
 template hipError_t launch_assemble_batched<double>(const AsmTaskDev*, int, int64_t, hipStream_t);
 template hipError_t launch_assemble_batched<float>(const AsmTaskDev*, int, int64_t, hipStream_t);
+
+template <typename TO>
+hipError_t launch_assemble_one(const AsmTaskDev& t, hipStream_t s) {
+  const int64_t total = t.m + t.n + t.k * t.n + t.k * t.k;
+  hipLaunchKernelGGL(assemble_batched_kernel<TO>, dim3(grid_for(total, 1024)), dim3(256), 0, s,
+                     (const AsmTaskDev*)nullptr, t);
+  return hipGetLastError();
+}
+template hipError_t launch_assemble_one<double>(const AsmTaskDev&, hipStream_t);
+template hipError_t launch_assemble_one<float>(const AsmTaskDev&, hipStream_t);
 
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd,
                             int64_t rows, int64_t cols, hipStream_t s) {

@@ -13,8 +13,8 @@
 //           gemm                C = Lv^T A          while this product runs)
 //           gemm                B = S^{-1} C
 //   Step 6  panel_lu(B^T)       packed LU of B^T in the storage of B
-//   Step 8  build_u             U = U_b  (k x n, positions)
-//   Step 7  build_lb, gemm      L = P (Lv L_b)     (rows scattered to positions)
+//   Step 8  assemble            p, q, U = U_b (k x n, positions), L_b, info
+//   Step 7  gemm                L = P (Lv L_b)     (rows scattered to positions)
 // Lv is the unit-lower factor of Step 3 in original row order; P enters
 // only through the row positions, never through a gather of A (Step 5:
 // L_y^T P A = Lv^T A).
@@ -452,16 +452,15 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   }
   if (diag && io.qpiv) HIP_TRY(launch_copy_i32(ipiv_b, io.qpiv, k, s));
   {
+    // p and q, Step 8 (U = U_b), the L_b that Step 7 needs and the info
+    // words, in one launch
     PhaseScope ph(h, PH_ASSEMBLE, s);
-    HIP_TRY(launch_positions_to_perm(pos_y, m, io.p, s));
-    HIP_TRY(launch_positions_to_perm(pos_b, n, io.q, s));
-    // Step 8: U = U_b
-    if (std::is_same<T, float>::value)
-      HIP_TRY(launch_build_u_f32(Bst, k, k, n, piv_b, rstep_b, io.q, (float*)io.U, io.ldu, s));
-    else
-      HIP_TRY(launch_build_u<double>(Bst, k, k, n, piv_b, rstep_b, io.q, (double*)io.U, io.ldu, s));
-    // Step 7 needs L_b
-    HIP_TRY(launch_build_lb<double>(Bst, k, k, piv_b, Lb, s));
+    AsmTaskDev a{};
+    a.pos_y = pos_y; a.pos_b = pos_b; a.Bst = Bst; a.piv_b = piv_b; a.rstep_b = rstep_b;
+    a.m = m; a.n = n; a.k = k;
+    a.p = io.p; a.q = io.q; a.U = io.U; a.ldu = io.ldu; a.Lb = Lb;
+    a.flags = flags; a.info = io.info;
+    HIP_TRY(launch_assemble_one<T>(a, s));
   }
   {
     GemmDesc d{};
@@ -474,7 +473,6 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     PhaseScope ph(h, PH_FORM_L, s);
     HIP_TRY((launch_gemm_t<double, double, double, T>(d, s)));
   }
-  HIP_TRY(launch_info_merge(flags + 0, flags + 1, flags + 2, io.info, s));
   return RLU_OK;
 }
 

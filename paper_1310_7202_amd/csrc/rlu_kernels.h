@@ -224,5 +224,8 @@ struct AsmTaskDev {
 template <typename TO>
 hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t max_elems,
                                    hipStream_t s);
+// The same for one problem, its task passed by value.
+template <typename TO>
+hipError_t launch_assemble_one(const AsmTaskDev& t, hipStream_t s);
 
 }  // namespace rlu
