@@ -16,55 +16,6 @@
 namespace rlu {
 namespace {
 
-__global__ void __launch_bounds__(256) positions_to_perm_kernel(const int* __restrict__ pos,
-                                                                int64_t n,
-                                                                int64_t* __restrict__ perm) {
-  for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n;
-       o += (int64_t)gridDim.x * blockDim.x)
-    perm[pos[o]] = o;
-}
-
-// Bst(r, o) = B^T(o, r): the packed LU of B^T with rows never moved.
-template <typename T>
-__global__ void __launch_bounds__(256) build_lb_kernel(const T* __restrict__ Bst, int64_t ldb,
-                                                       int64_t k, const int* __restrict__ piv_row,
-                                                       T* __restrict__ Lb) {
-  const int64_t total = k * k;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % k, r = e / k;  // Lb(i, r)
-    T v = T(0);
-    if (i == r) {
-      v = T(1);
-    } else if (i > r) {
-      const int64_t o = piv_row[r];
-      const T d = Bst[r + o * ldb];      // U'(r, r)
-      const T u = Bst[i + o * ldb];      // U'(r, i)
-      v = d != T(0) ? u / d : T(0);
-    }
-    Lb[i + r * k] = v;
-  }
-}
-
-template <typename TI, typename TO>
-__global__ void __launch_bounds__(256) build_u_kernel(const TI* __restrict__ Bst, int64_t ldb,
-                                                      int64_t k, int64_t n,
-                                                      const int* __restrict__ piv_row,
-                                                      const int* __restrict__ rstep,
-                                                      const int64_t* __restrict__ q,
-                                                      TO* __restrict__ U, int64_t ldu) {
-  const int64_t total = k * n;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e % k, c = e / k;   // U(r, c)
-    const int64_t o = q[c];              // original column of B at position c
-    const int s = rstep[o];
-    const TI d = Bst[r + (int64_t)piv_row[r] * ldb];
-    const TI lv = lv_value<TI>(Bst[r + o * ldb], (int)r, s);
-    U[r + c * ldu] = (TO)(d * lv);
-  }
-}
-
 template <typename TI, typename TO>
 __global__ void __launch_bounds__(256) convert2d_kernel(const TI* __restrict__ src, int64_t lds,
                                                         TO* __restrict__ dst, int64_t ldd,
@@ -126,15 +77,6 @@ __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ p,
     p[e] = v;
 }
 
-__global__ void info_merge_kernel(const int* info_y, const int* info_b, const int* fail,
-                                  int32_t* out) {
-  if (threadIdx.x == 0) {
-    out[0] = *info_y;
-    out[1] = *info_b;
-    out[2] = *fail;
-  }
-}
-
 __global__ void __launch_bounds__(256) copy_i32_kernel(const int* __restrict__ src,
                                                        int32_t* __restrict__ dst, int64_t n) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
@@ -144,8 +86,7 @@ __global__ void __launch_bounds__(256) copy_i32_kernel(const int* __restrict__ s
 
 // Steps 7-8 assembly (blockIdx.y = problem of a batch, or the one task
 // passed by value): the permutations p and q from the row positions, U = U_b
-// scattered by column position (the same values build_u computes), L_b, and
-// the info words.
+// scattered by column position, L_b, and the info words.
 template <typename TO>
 __global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev* __restrict__ tasks,
                                                                AsmTaskDev one) {
@@ -212,40 +153,6 @@ inline unsigned grid_for(int64_t n, int64_t cap = 8192) {
 
 }  // namespace
 
-hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s) {
-  hipLaunchKernelGGL(positions_to_perm_kernel, dim3(grid_for(n)), dim3(256), 0, s, pos, n, perm);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_build_lb(const T* Bst, int64_t ldb, int64_t k, const int* piv_row, T* Lb,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(build_lb_kernel<T>, dim3(grid_for(k * k)), dim3(256), 0, s, Bst, ldb, k,
-                     piv_row, Lb);
-  return hipGetLastError();
-}
-template hipError_t launch_build_lb<double>(const double*, int64_t, int64_t, const int*, double*,
-                                            hipStream_t);
-
-template <typename T>
-hipError_t launch_build_u(const T* Bst, int64_t ldb, int64_t k, int64_t n, const int* piv_row,
-                          const int* rstep, const int64_t* q, T* U, int64_t ldu, hipStream_t s) {
-  hipLaunchKernelGGL((build_u_kernel<T, T>), dim3(grid_for(k * n)), dim3(256), 0, s, Bst, ldb, k,
-                     n, piv_row, rstep, q, U, ldu);
-  return hipGetLastError();
-}
-template hipError_t launch_build_u<double>(const double*, int64_t, int64_t, int64_t, const int*,
-                                           const int*, const int64_t*, double*, int64_t,
-                                           hipStream_t);
-
-hipError_t launch_build_u_f32(const double* Bst, int64_t ldb, int64_t k, int64_t n,
-                              const int* piv_row, const int* rstep, const int64_t* q, float* U,
-                              int64_t ldu, hipStream_t s) {
-  hipLaunchKernelGGL((build_u_kernel<double, float>), dim3(grid_for(k * n)), dim3(256), 0, s, Bst,
-                     ldb, k, n, piv_row, rstep, q, U, ldu);
-  return hipGetLastError();
-}
-
 template <typename TI, typename TO>
 hipError_t launch_convert2d(const TI* src, int64_t lds, TO* dst, int64_t ldd, int64_t rows,
                             int64_t cols, hipStream_t s) {
@@ -301,12 +208,6 @@ hipError_t launch_fill_u32(uint32_t* p, size_t count, uint32_t v, hipStream_t s)
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for((int64_t)count, 1024)), dim3(256), 0, s, p,
                      count, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
-                             int32_t* info_out, hipStream_t s) {
-  hipLaunchKernelGGL(info_merge_kernel, dim3(1), dim3(64), 0, s, info_y, info_b, fail, info_out);
   return hipGetLastError();
 }
 

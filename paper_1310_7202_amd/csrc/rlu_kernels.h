@@ -171,19 +171,6 @@ hipError_t launch_lstsq_back(const T* U, int64_t ldu, const double* Y, int64_t k
                              hipStream_t s);
 
 // ----- Permutations and factor assembly (finish.hip) ------------------------
-hipError_t launch_positions_to_perm(const int* pos, int64_t n, int64_t* perm, hipStream_t s);
-// L_b (k x k, unit lower) from the pivoted LU of B^T stored in B (k x n)
-template <typename T>
-hipError_t launch_build_lb(const T* Bst, int64_t ldb, int64_t k, const int* piv_row,
-                           T* Lb, hipStream_t s);
-// U (k x n) from the pivoted LU of B^T
-template <typename T>
-hipError_t launch_build_u(const T* Bst, int64_t ldb, int64_t k, int64_t n,
-                          const int* piv_row, const int* rstep, const int64_t* q,
-                          T* U, int64_t ldu, hipStream_t s);
-hipError_t launch_build_u_f32(const double* Bst, int64_t ldb, int64_t k, int64_t n,
-                              const int* piv_row, const int* rstep, const int64_t* q, float* U,
-                              int64_t ldu, hipStream_t s);
 // dst (rows x cols, TO) = src (TI), element-wise conversion
 template <typename TI, typename TO>
 hipError_t launch_convert2d(const TI* src, int64_t lds, TO* dst, int64_t ldd, int64_t rows,
@@ -207,8 +194,6 @@ struct LvDenseTaskDev {
 template <typename TO>
 hipError_t launch_lv_dense_batched(const LvDenseTaskDev* tasks, int count, int64_t max_elems,
                                    hipStream_t s);
-hipError_t launch_info_merge(const int* info_y, const int* info_b, const int* fail,
-                             int32_t* info_out, hipStream_t s);
 hipError_t launch_copy_i32(const int* src, int32_t* dst, int64_t n, hipStream_t s);
 // dst (cols x rows, ld ldd) = src (rows x cols, ld lds)^T
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd,
