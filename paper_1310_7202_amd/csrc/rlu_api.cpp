@@ -399,9 +399,11 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     HIP_TRY(launch_gemm<double>(d, s));
   }
   // The one-workgroup inverse (k <= 64) overlaps the projection on the side
-  // stream; the blocked form is a chain of small launches that the
-  // projection would starve of CUs, so it runs first on the caller's stream.
-  const bool overlap = k <= 64;
+  // stream when the projection is large enough to hide it (a fork and a join
+  // cost more than a small projection); the blocked form is a chain of small
+  // launches that the projection would starve of CUs, so it runs first on
+  // the caller's stream.
+  const bool overlap = k <= 64 && (double)m * (double)n * (double)k >= 134217728.0;
   hipStream_t sinv = overlap ? h->side : s;
   if (overlap) {
     HIP_TRY(hipEventRecord(h->ev_fork, s));
