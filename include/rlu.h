@@ -137,7 +137,8 @@ typedef struct rlu_handle_s* rlu_handle_t;
 typedef void* rlu_stream_t; /* a hipStream_t; NULL = the null stream */
 
 /* Create a handle bound to HIP device `device` (the handle caches device
- * workspace and a second stream used to overlap independent steps). */
+ * workspace, and for rlu_factor_batched a capture stream and the recorded
+ * launch graph). */
 rlu_status_t rlu_create(rlu_handle_t* h, int device);
 rlu_status_t rlu_destroy(rlu_handle_t h);
 
@@ -300,7 +301,7 @@ rlu_status_t rlu_serve_destroy(rlu_server_t srv);
 
 /* Phase timing for measurement tools.  enable = 1: rlu_factor records a HIP
  * event pair around each phase on the stream that runs the phase (the
- * caller's stream, or the handle's side stream for the Gram inverse);
+ * caller's stream);
  * enable = 2: around the sketch product (Step 2) only, so that timing the
  * dominant kernel adds one event pair per call; 0: off.  The handle keeps
  * the events of the last RLU_TIMING_RING calls.  Other values:

@@ -9,8 +9,8 @@
 //             lv_dense, gemm Y = A Lv(Z)
 //   Step 3  panel_lu(Y)         packed LU of Y in place, rows never moved
 //   Step 5  gemm (split-K)      S = Lv^T Lv        (Gram matrix)
-//           spd_inverse         S <- S^{-1}        (k <= 64: on a second stream,
-//           gemm                C = Lv^T A          while this product runs)
+//           spd_inverse         S <- S^{-1}
+//           gemm                C = Lv^T A
 //           gemm                B = S^{-1} C
 //   Step 6  panel_lu(B^T)       packed LU of B^T in the storage of B
 //   Step 8  assemble            p, q, U = U_b (k x n, positions), L_b, info
@@ -387,7 +387,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     if (st != RLU_OK) return st;
   }
   if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
-  // Step 5: S = Lv^T Lv, S <- S^{-1} (side stream) while C = Lv^T A
+  // Step 5: S = Lv^T Lv, S <- S^{-1}, C = Lv^T A
   {
     GemmDesc d{};
     d.M = k; d.N = k; d.K = m;
@@ -398,27 +398,18 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     PhaseScope ph(h, PH_GRAM, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
-  // The one-workgroup inverse (k <= 64) overlaps the projection on the side
-  // stream when the projection is large enough to hide it (a fork and a join
-  // cost more than a small projection); the blocked form is a chain of small
-  // launches that the projection would starve of CUs, so it runs first on
-  // the caller's stream.
-  const bool overlap = k <= 64 && (double)m * (double)n * (double)k >= 134217728.0;
-  hipStream_t sinv = overlap ? h->side : s;
-  if (overlap) {
-    HIP_TRY(hipEventRecord(h->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(h->side, h->ev_fork, 0));
-  }
+  // The inverse runs on the caller's stream before the projection: forking
+  // it to a second stream to overlap the projection saved at most the ~10 us
+  // of a one-workgroup inverse and, once a process had created more streams
+  // than hardware queues, cost up to ~300 us per call in the fork and join.
   {
-    PhaseScope ph(h, PH_GRAM_INV, sinv);
-    HIP_TRY(launch_spd_inverse_scratch(S, k, at<double>(ws, Ly.gj), sinv));
+    PhaseScope ph(h, PH_GRAM_INV, s);
+    HIP_TRY(launch_spd_inverse_scratch(S, k, at<double>(ws, Ly.gj), s));
   }
-  if (overlap) HIP_TRY(hipEventRecord(h->ev_join, h->side));
   {
     rlu_status_t st = lvt_times_a(C, k, PH_PROJECT, PH_PROJECT_SUM);
     if (st != RLU_OK) return st;
   }
-  if (overlap) HIP_TRY(hipStreamWaitEvent(s, h->ev_join, 0));
   {
     GemmDesc d{};
     d.M = k; d.N = n; d.K = k;
@@ -598,10 +589,7 @@ rlu_status_t rlu_create(rlu_handle_t* out, int device) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return RLU_ERR_DEVICE; }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cus = prop.multiProcessorCount;
-  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess ||
+  if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess) {
     hipSetDevice(prev);
@@ -624,9 +612,6 @@ rlu_status_t rlu_destroy(rlu_handle_t h) {
     for (int p = 0; p < PH_COUNT; ++p)
       for (int e = 0; e < 2; ++e)
         if (t.ev[p][e]) hipEventDestroy(t.ev[p][e]);
-  if (h->ev_fork) hipEventDestroy(h->ev_fork);
-  if (h->ev_join) hipEventDestroy(h->ev_join);
-  if (h->side) hipStreamDestroy(h->side);
   if (h->bgraph.exec) hipGraphExecDestroy(h->bgraph.exec);
   if (h->bgraph.graph) hipGraphDestroy(h->bgraph.graph);
   if (h->bws) hipFree(h->bws);

@@ -41,8 +41,6 @@ struct rlu_handle_s {
   TimingSlot ring[RLU_TIMING_RING];
   TimingSlot* cur = nullptr;
   int cus = 256;
-  hipStream_t side = nullptr;    // second stream for the Gram inverse
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void* ws = nullptr;            // workspace of rlu_factor
   size_t ws_bytes = 0;
   // rlu_factor_batched
