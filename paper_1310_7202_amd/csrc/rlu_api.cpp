@@ -589,8 +589,8 @@ rlu_status_t rlu_create(rlu_handle_t* out, int device) {
   if (hipSetDevice(device) != hipSuccess) { delete h; return RLU_ERR_DEVICE; }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->cus = prop.multiProcessorCount;
-  if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess ||
+  // (the capture stream of rlu_factor_batched is created on its first use)
+  if (hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming) != hipSuccess) {
     hipSetDevice(prev);
     delete h;

@@ -737,6 +737,9 @@ void drop_graph(rlu_handle_s* h) {
 
 template <typename T>
 rlu_status_t capture(rlu_handle_s* h, const Plan& P) {
+  // created on first use, so that handles that never batch hold no extra
+  // stream (streams beyond the device's hardware queues share queues)
+  if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   rlu_status_t st = enqueue<T>(h, P, (char*)h->bws, nullptr, h->cap);
   hipGraph_t g = nullptr;
