@@ -6,7 +6,8 @@ configuration (one rlu_factor call on the whole matrix).
     and without one power iteration (Section 5.2);
   * the same matrix in FP32 storage: the reduced-precision residual rule;
   * 16384 x 16384, sigma_i = i^-2, k = 500, l = 520, BF16 products with FP32
-    accumulation: the residual rule against the oracle on the same FP32 A.
+    accumulation: the residual rule against the oracle on the same FP32 A;
+  * the least-squares solve (Algorithm 4.3) on the 8192^2 factors.
 The matrices are generated on the device (a host QR of the Haar factors
 would take minutes); G comes from the host generator and is passed in.
 """
@@ -52,6 +53,27 @@ def test_exp_spectrum_8192_fp64(rlu, exp8192, q):
         e0 = orl.relative_residual(A, orl.randomized_lu(A, k, l, G), exact=False)
         print(f"  oracle residual q=1 {e1:.3e} q=0 {e0:.3e}", flush=True)
         assert e1 < e0
+
+
+def test_exp_spectrum_8192_lstsq(rlu, exp8192):
+    """Algorithm 4.3 on the full-size factors, as the least-squares form of
+    the benchmark runs it (b = A x0): the GPU solve on the GPU factors
+    against the oracle's solve on its own factors of the same A and G."""
+    A, k, l, G = exp8192
+    print("[full] 8192^2 least squares, 4 right-hand sides", flush=True)
+    Ad = to_dev_colmajor(A)
+    f = rlu.factor(Ad, k, l, G=to_dev_colmajor(G))
+    x0 = np.random.default_rng(7206).standard_normal((A.shape[1], 4))
+    b = A @ x0
+    x = to_host(rlu.lstsq(f, to_dev_colmajor(b)))
+    torch.cuda.synchronize()
+    o = orl.randomized_lu(A, k, l, G)
+    assert np.array_equal(to_host(f.q)[:k], o["q"][:k])
+    xo = orl.lstsq_rank_deficient(o, b)
+    assert np.abs(x - xo).max() <= 1e-9 * np.abs(xo).max()
+    zero = np.ones(A.shape[1], bool)
+    zero[o["q"][:k]] = False
+    assert np.all(x[zero] == 0.0)
 
 
 def _residual_rule(rlu, A32, k, l, G32, precision, label):
