@@ -350,6 +350,10 @@ GemmShape choose_shape(int64_t M, int64_t N, int64_t K, bool kcontig_a) {
   const int64_t tiles = ((M + c.bm - 1) / c.bm) * ((N + c.bn - 1) / c.bn);
   int ks = 1;
   while (tiles * ks < 1024 && K / (ks * 2) >= 256 && ks < 32) ks *= 2;
+  // A grid still smaller than one workgroup per CU (the products of small
+  // problems) is bound by the latency of its chain of K slices, about 1.3 us
+  // each: split further, down to 64 of K per split.
+  while (tiles * ks < 256 && K / (ks * 2) >= 64 && ks < 32) ks *= 2;
   sh.ksplit = ks;
   return sh;
 }
