@@ -490,16 +490,28 @@ __device__ __forceinline__ void panel_body(
       } else {
         // ---- (4) bookkeeping and multipliers of step j --------------------------
         const int wr = win_row - row0;  // local index if the winner is ours
-        const bool big_piv = fabs(piv) >= 2.2250738585072014e-308;  // smallest normal
-        const double rpiv = 1.0 / piv;
+        // multiply by the reciprocal pivot unless it would overflow.  piv is
+        // the same in every lane: one uniform branch for the whole wave
+        // instead of a masked branch per row
+        const int how = __builtin_amdgcn_readfirstlane(
+            piv == 0.0 ? 0 : (fabs(piv) >= 2.2250738585072014e-308 ? 1 : 2));  // smallest normal
+        double mqs[RPL];
+        if (how == 1) {
+          const double rpiv = 1.0 / piv;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) mqs[q] = val_q[q] * rpiv;
+        } else if (how == 2) {
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) mqs[q] = val_q[q] / piv;
+        } else {
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) mqs[q] = 0.0;
+        }
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
           const int r = lane + 64 * q;
           const bool live = st_q[q] == kNone, isw = r == wr;
-          // multiply by the reciprocal pivot unless it would overflow
-          double mq = 0.0;
-          if (piv != 0.0) mq = big_piv ? val_q[q] * rpiv : val_q[q] / piv;
-          mq = live && !isw ? mq : 0.0;
+          const double mq = live && !isw ? mqs[q] : 0.0;
           // column j: the winner keeps its pivot, the other live rows take
           // their multipliers (their values when the pivot is zero)
           if (live) Ts[(int64_t)j * R + r] = isw || piv == 0.0 ? val_q[q] : mq;
