@@ -221,6 +221,18 @@ def test_large_rank_blocked_gram_inverse(rlu, m, n, k, l):
 
 
 @pytest.mark.parametrize("m,n,k,l", [
+    (2000, 4500, 230, 240),    # Y = A G: K = 4500, short side l = 240 in 128 x 224 tiles
+    (4500, 1500, 250, 260),    # Lv^T A: K = 4500, short side k = 250 in 128 x 224 tiles
+])
+def test_wide_short_side_products(rlu, m, n, k, l):
+    """Long products whose short side spans two 128 x 224 tiles (ragged
+    second tile), with split-K."""
+    A = workloads.low_rank_plus_noise(m, n, k, 1e-6, 660 + k)
+    G = workloads.gaussian((n, l), 670 + k)
+    run_and_compare(rlu, A, k, l, G, f"wide {m}x{n}")
+
+
+@pytest.mark.parametrize("m,n,k,l", [
     (16384, 2000, 290, 300),   # Y (16384 x 300) factored in column blocks
     (2000, 16384, 290, 300),   # B^T (16384 x 290) factored in column blocks
 ])
