@@ -20,15 +20,29 @@ Pinned by (see ``tests/test_oracle_*.py``):
     block elimination, in exact rational arithmetic on tiny inputs.
   * ``rlu.lu_col_pivot``       -- LAPACK getrf of the transpose (pivots) and
     the closed-form Schur complement.
-  * ``rlu.power_sketch``       -- Section 5.2: the plain product
-    (A A^T)^q A G gives the same pivots and factors (the normalization is a
-    right triangular factor); q = 0 is Step 2; exact rank-k reconstruction;
-    the error falls with q on the paper's slowly decaying spectrum.
+  * ``rlu.power_sketch_plain`` -- Section 5.2, (A A^T)^q A G for small q:
+    the closed form U S^(2q+1) V^T G of a matrix built from its SVD.
+  * ``rlu.power_sketch_normalized`` -- Section 5.2's normalized scheme (a
+    reading): the same pivots and factors as the plain product (the
+    normalization is a right triangular factor); q = 0 is Step 2; exact
+    rank-k reconstruction; the error falls with q on the paper's slowly
+    decaying spectrum.
+  * ``rlu.power_sketch``       -- plain up to PLAIN_POWER_MAX_Q, normalized
+    above (both pinned above).
   * ``rlu.lu_normalize``       -- LAPACK getrf: P L from scipy.linalg.lu.
   * ``rlu.lstsq_rank_deficient`` -- Algorithm 4.3: consistent rank-k systems
     solved with at most k nonzeros; the residual equals LAPACK's least-squares
     minimum (numpy.linalg.lstsq); A^{-1} b in the full-rank square case.
   * ``rlu.upper_solve``        -- SciPy solve_triangular; a zero row gives 0.
+  * ``rlu.spectral_norm_estimate``, ``rlu.residual(exact=False)``,
+    ``rlu._power_norm`` -- exact SVD values (to 1e-6 relative) with a clear
+    top gap, a clustered top and the paper's slow decay; the lower-bound
+    property; the residual operator against the formed difference.
+  * ``rlu.pivot_gate``         -- constructed diagnostics on either side of
+    each threshold; exact ties and rank deficiency; LAPACK's pivots on the
+    gated prefix.
+  * ``rlu.kappa``              -- closed forms (diagonal, orthogonal, SVD
+    construction) and the Gram-route accuracy it predicts.
   * ``bounds.xi``              -- Table 4.1 of the paper, 9 of 9 rows.
   * ``philox.philox4x32_10``   -- Random123 known-answer vectors.
   * ``philox.gaussian_matrix`` -- Box-Muller closed form on fixed uniforms and

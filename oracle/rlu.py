@@ -163,16 +163,31 @@ def lu_normalize(X: np.ndarray) -> np.ndarray:
     return out
 
 
-def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
-    """Step 2 with q power iterations (Section 5.2): Y = (A A^*)^q A G.
+# Section 5.2 replaces Step 2 by Y = (A A^*)^q A G for a small integer q and
+# asks for a normalized scheme for larger q.  Up to this q the oracle forms
+# the plain product; above it, the normalized scheme.
+PLAIN_POWER_MAX_Q = 2
 
-    A G is followed by q rounds of one product with A^T and one with A.
-    Every product except the last is normalized by ``lu_normalize``, the
-    normalized scheme the paper points to for larger q.  Each normalization
-    multiplies the block on the right by an upper-triangular matrix, which
-    changes neither the pivots nor the unit-lower factor of Step 3, so
-    Steps 3-8 agree with the plain product in exact arithmetic.
-    """
+
+def power_sketch_plain(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
+    """Y = (A A^T)^q A G by plain products, no normalization (Section 5.2
+    for small q)."""
+    if q < 0:
+        raise ValueError("q must be >= 0")
+    Y = sketch(A, G)
+    for _ in range(q):
+        Y = A @ (A.T @ Y)
+    return Y
+
+
+def power_sketch_normalized(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
+    """The normalized power scheme (Section 5.2, for larger q): A G is
+    followed by q rounds of one product with A^T and one with A, and every
+    product except the last is replaced by ``lu_normalize`` of it.  Each
+    normalization multiplies the block on the right by an upper-triangular
+    matrix, which changes neither the pivots nor the unit-lower factor of
+    Step 3, so Steps 3-8 agree with the plain product in exact arithmetic
+    (a reading of the paper; pinned against ``power_sketch_plain``)."""
     if q < 0:
         raise ValueError("q must be >= 0")
     Y = sketch(A, G)
@@ -183,12 +198,24 @@ def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
     return Y
 
 
-def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0) -> dict:
+def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
+    """Step 2 with q power iterations (Section 5.2): Y = (A A^*)^q A G,
+    formed plainly for q <= PLAIN_POWER_MAX_Q and by the normalized scheme
+    above that."""
+    if q <= PLAIN_POWER_MAX_Q:
+        return power_sketch_plain(A, G, q)
+    return power_sketch_normalized(A, G, q)
+
+
+def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
+                  scheme: str = "auto") -> dict:
     """Algorithm 4.1 of the paper, Steps 2-8, for a given Gaussian G (Step 1).
 
     Inputs: A (m x n), k (target rank), l (number of sketch columns,
     k <= l <= min(m, n)), G (n x l) and the number q of power iterations
-    of Section 5.2 (0: the plain Step 2).  Returns a dict with the outputs
+    of Section 5.2 (0: the plain Step 2).  ``scheme`` picks how the power
+    sketch is formed: "plain", "normalized", or "auto" (plain up to
+    PLAIN_POWER_MAX_Q, normalized above).  Returns a dict with the outputs
     L (m x k unit lower trapezoidal), U (k x n upper trapezoidal), p, q and
     the intermediates (Y, packed LU of Y, ipiv, L_y, B, L_b, qpiv, info words
     and pivot diagnostics).
@@ -200,7 +227,9 @@ def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0) -> d
         raise ValueError("need 1 <= k <= l <= min(m, n)")
     if G.shape != (n, l):
         raise ValueError("G must be n x l")
-    Y = power_sketch(A, G, q)                          # Step 2 (Section 5.2)
+    make = {"auto": power_sketch, "plain": power_sketch_plain,
+            "normalized": power_sketch_normalized}[scheme]
+    Y = make(A, G, q)                                  # Step 2 (Section 5.2)
     return randomized_lu_from_sketch(A, k, Y)
 
 
@@ -278,37 +307,57 @@ def spectral_norm(X: np.ndarray) -> float:
     return float(np.linalg.svd(X, compute_uv=False)[0])
 
 
-def residual(A: np.ndarray, out: dict, exact: bool = True, iters: int = 60,
-             seed: int = 0) -> float:
-    """||L U - P A Q||_2 (the quantity bounded by Theorem 4.1).
-
-    ``exact`` uses a full SVD; otherwise a fixed number of power iterations
-    on the operator x -> (L U - P A Q)^T (L U - P A Q) x, never forming the
-    difference for large inputs (an estimate from below).
-    """
+def residual_operator(A: np.ndarray, out: dict):
+    """The residual E = L U - P A Q of Theorem 4.1 as a pair of products
+    (X -> E X, Y -> E^T Y), never forming E: (P A Q) X is A applied to X
+    with its rows put in the order q^{-1}, then rows picked by p."""
     L, U, p, q = out["L"], out["U"], out["p"], out["q"]
-    if exact:
-        return spectral_norm(L @ U - permuted(A, p, q))
-    rng = np.random.default_rng(seed)
-    n = U.shape[1]
-    x = rng.standard_normal(n)
-    x /= np.linalg.norm(x)
     qinv = np.empty_like(q)
     qinv[q] = np.arange(q.size)
     pinv = np.empty_like(p)
     pinv[p] = np.arange(p.size)
-    est = 0.0
+
+    def mv(X):
+        return L @ (U @ X) - (A @ X[qinv])[p]
+
+    def rmv(Y):
+        return U.T @ (L.T @ Y) - (A.T @ Y[pinv])[q]
+
+    return mv, rmv, U.shape[1]
+
+
+def spectral_norm_estimate(mv, rmv, n: int, iters: int = 60, block: int = 8,
+                           seed: int = 0) -> float:
+    """Largest singular value of an operator given by its products, by
+    subspace iteration on E^T E with a block of ``block`` Gaussian start
+    vectors (orthonormalized after every step), then the largest singular
+    value of E X on the final orthonormal block X.  Always a lower bound
+    (||E X||_2 <= ||E||_2 for orthonormal X); the error in sigma_1 decays
+    like (sigma_{block+1} / sigma_1)^(2 iters), so a cluster of up to
+    ``block`` near-equal leading values does not slow it down."""
+    b = max(1, min(block, n))
+    X = np.random.default_rng(seed).standard_normal((n, b))
+    X, _ = np.linalg.qr(X)
     for _ in range(iters):
-        # y = (L U - P A Q) x
-        y = L @ (U @ x) - (A @ x[qinv])[p]
-        # z = (L U - P A Q)^T y
-        z = U.T @ (L.T @ y) - (A.T @ y[pinv])[q]
-        nz = np.linalg.norm(z)
-        if nz == 0.0:
+        Z = rmv(mv(X))
+        if not np.any(Z):
             return 0.0
-        est = np.sqrt(nz)
-        x = z / nz
-    return float(est)
+        X, _ = np.linalg.qr(Z)
+    return float(np.linalg.svd(mv(X), compute_uv=False)[0])
+
+
+def residual(A: np.ndarray, out: dict, exact: bool = True, iters: int = 60,
+             seed: int = 0) -> float:
+    """||L U - P A Q||_2 (the quantity bounded by Theorem 4.1).
+
+    ``exact`` uses a full SVD of the difference; otherwise
+    ``spectral_norm_estimate`` on ``residual_operator`` (the difference is
+    never formed, for large inputs)."""
+    if exact:
+        L, U, p, q = out["L"], out["U"], out["p"], out["q"]
+        return spectral_norm(L @ U - permuted(A, p, q))
+    mv, rmv, n = residual_operator(np.asarray(A), out)
+    return spectral_norm_estimate(mv, rmv, n, iters=iters, seed=seed)
 
 
 def relative_residual(A: np.ndarray, out: dict, exact: bool = True) -> float:
@@ -318,18 +367,10 @@ def relative_residual(A: np.ndarray, out: dict, exact: bool = True) -> float:
 
 
 def _power_norm(A: np.ndarray, iters: int = 60, seed: int = 1) -> float:
-    rng = np.random.default_rng(seed)
-    x = rng.standard_normal(A.shape[1])
-    x /= np.linalg.norm(x)
-    est = 0.0
-    for _ in range(iters):
-        z = A.T @ (A @ x)
-        nz = np.linalg.norm(z)
-        if nz == 0.0:
-            return 0.0
-        est = np.sqrt(nz)
-        x = z / nz
-    return float(est)
+    """||A||_2 by ``spectral_norm_estimate`` (A is never factored)."""
+    A = np.asarray(A)
+    return spectral_norm_estimate(lambda X: A @ X, lambda Y: A.T @ Y, A.shape[1],
+                                  iters=iters, seed=seed)
 
 
 def pivot_gate(diag: dict, u: float = 2.0 ** -53, gap_min: float = 1e-8,

@@ -416,7 +416,7 @@ def test_power_sketch_gives_the_factors_of_the_plain_product(q, shape):
     k, l = 6, 9
     A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), 12.0), 61)
     G = workloads.gaussian((n, l), 62)
-    got = rlu.randomized_lu(A, k, l, G, q=q)
+    got = rlu.randomized_lu(A, k, l, G, q=q, scheme="normalized")
     ref = rlu.randomized_lu_from_sketch(A, k, _plain_power_sketch(A, G, q))
     np.testing.assert_array_equal(got["ipiv"], ref["ipiv"])
     np.testing.assert_array_equal(got["p"], ref["p"])
@@ -455,11 +455,12 @@ def test_power_iterations_lower_the_error_on_slow_decay():
     sig = sig / sig[0]
     A = workloads.spectral_matrix(m, n, sig, 70)
     errs = []
-    for q in (0, 1, 2):
+    for q in (0, 1, 2, 3):
         G = workloads.gaussian((n, l), 71)
         errs.append(rlu.relative_residual(A, rlu.randomized_lu(A, k, l, G, q=q)))
     assert errs[1] < 0.8 * errs[0]
     assert errs[2] < errs[1]
+    assert errs[3] < errs[2]          # q = 3 takes the normalized scheme
     assert min(errs) >= sig[k] * (1 - 1e-9)
 
 
@@ -618,7 +619,8 @@ def test_planted_mistakes_are_caught(name, monkeypatch):
         assert failed, name
         return
     else:
-        monkeypatch.setattr(rlu, "lu_normalize" if kind == "normalize" else "power_sketch", fn)
+        monkeypatch.setattr(rlu, "lu_normalize" if kind == "normalize" else "power_sketch_normalized",
+                            fn)
     if kind in ("normalize", "power"):
         failed = False
         for q in (1, 2):
