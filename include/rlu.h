@@ -40,12 +40,20 @@
  *     Step 3) or info[1] (for Step 6) as the 1-based step where it occurred,
  *     0 meaning none.  The factors stay defined (see the zero-pivot rules in
  *     the documentation of rlu_factor).
- *   - A device-side failure of the cross-workgroup pivot exchange (it never
- *     completes within its time limit) sets info[2] to 1; the outputs are
- *     then undefined.  rlu_check_info maps the three words to a status.
+ *   - info[2] is a bit set.  Bit 0 (value 1): a device-side failure of the
+ *     cross-workgroup pivot exchange (one of its waits did not complete
+ *     within its time limit); the outputs are then undefined.  Bit 1 (value
+ *     2): with RLU_FLAG_CHECK_FINITE, a NaN or an infinity was found in the
+ *     sketch Y = A G, i.e. in A or G (a non-finite entry of either reaches
+ *     every entry of its row of Y) or in an overflowed product; the outputs
+ *     are then unspecified.  rlu_check_info maps the three words to a status.
  *   - No exception crosses this interface.
  *
- * Threading: a handle may be used by one host thread at a time.
+ * Threading: a handle may be used by one host thread at a time and serves
+ * one stream at a time: its workspace (Y, the Gram matrix, the pivot
+ * exchange area, the split-K partials) is reused by every call, and nothing
+ * orders calls on different streams, so a caller that switches streams
+ * must order the calls itself (or use one handle per stream).
  */
 #ifndef RLU_H
 #define RLU_H
@@ -84,7 +92,9 @@ typedef enum {
 } rlu_precision_t;
 
 enum {
-  RLU_FLAG_CHECK_FINITE = 1u, /* reserved */
+  RLU_FLAG_CHECK_FINITE = 1u, /* scan the sketch for NaN / infinity: info[2]
+                                 bit 1, status RLU_ERR_NONFINITE (one pass
+                                 over the m x l sketch, no pass over A)   */
   RLU_FLAG_DIAGNOSTICS = 2u   /* fill the optional diagnostic outputs      */
 };
 
@@ -123,7 +133,8 @@ typedef struct {
   int64_t* p;                  /* out length m: row permutation P               */
   int64_t* q;                  /* out length n: column permutation Q            */
   int32_t* info;               /* out 3 words: zero-pivot step of Step 3, of
-                                  Step 6 (1-based, 0 = none), exchange failure */
+                                  Step 6 (1-based, 0 = none), failure bits
+                                  (1: exchange, 2: non-finite input)         */
   /* Optional diagnostics, filled only with RLU_FLAG_DIAGNOSTICS (each may be
    * NULL).  Y and B use the storage dtype of the FP64/FP32 path (FP64 for the
    * FP64 and mixed modes, FP32 for the FP32 mode). */
@@ -250,7 +261,9 @@ typedef struct {
 
 typedef struct {
   rlu_status_t status;     /* RLU_PENDING, RLU_OK, RLU_WARN_ZERO_PIVOT, or an
-                              error (RLU_ERR_DEVICE: exchange failure)        */
+                              error (RLU_ERR_DEVICE: exchange failure;
+                              RLU_ERR_NONFINITE: the requested check found a
+                              NaN or infinity)                                 */
   const void* L; int64_t ldl;  /* server-owned device outputs, valid until    */
   const void* U; int64_t ldu;  /*   rlu_serve_release (NULL unless finished)  */
   const int64_t* p;
@@ -303,25 +316,46 @@ rlu_status_t rlu_serve_destroy(rlu_server_t srv);
  * event pair around each phase on the stream that runs the phase (the
  * caller's stream);
  * enable = 2: around the sketch product (Step 2) only, so that timing the
- * dominant kernel adds one event pair per call; 0: off.  The handle keeps
- * the events of the last RLU_TIMING_RING calls.  Other values:
- * RLU_ERR_INVALID_ARG. */
+ * dominant product adds one event pair per call;
+ * enable = 3: around the sketch product and around every launch of the
+ * pivoted-LU kernel (Steps 3 and 6, their column blocks and the power
+ * iterations' normalizations; the first RLU_MAX_KERNEL_TIMES launches of a
+ * call); 0: off.  The handle keeps the events of the last RLU_TIMING_RING
+ * calls.  Other values: RLU_ERR_INVALID_ARG. */
 #define RLU_TIMING_RING 64
 #define RLU_MAX_PHASES 16
+#define RLU_MAX_KERNEL_TIMES 16
 rlu_status_t rlu_set_timing(rlu_handle_t h, int enable);
 
 /* Durations (milliseconds) of the phases of the call `back` calls before the
  * most recent one (back = 0: the most recent), waiting for its events.
  * Fills up to `cap` entries of ms[] and names[] (static strings; either may
- * be NULL) and stores the phase count in *count.  RLU_ERR_INVALID_ARG if no
- * timed call is that far back. */
+ * be NULL) and stores the entry count in *count: the phases (fewer than
+ * RLU_MAX_PHASES; untimed phases read 0), then, in timing mode 3, one entry
+ * named "panel_lu_kernel" per timed pivoted-LU kernel launch, in launch
+ * order (so cap = RLU_MAX_PHASES + RLU_MAX_KERNEL_TIMES always suffices).
+ * RLU_ERR_INVALID_ARG if no timed call is that far back. */
 rlu_status_t rlu_phase_times(rlu_handle_t h, int back, float* ms, const char** names, int cap,
                              int* count);
 
 /* Map the three info words (already copied to the host) to a status:
- * RLU_ERR_DEVICE if the exchange failed, RLU_WARN_ZERO_PIVOT if a zero pivot
+ * RLU_ERR_DEVICE if the exchange failed (info[2] bit 0, or any bit this
+ * version does not define), RLU_ERR_NONFINITE if the requested non-finite
+ * check found a NaN or infinity (bit 1), RLU_WARN_ZERO_PIVOT if a zero pivot
  * occurred, RLU_OK otherwise. */
 rlu_status_t rlu_check_info(const int32_t info_host[3]);
+
+/* For tests of the failure path of the pivot exchange (callers that want to
+ * see RLU_ERR_DEVICE produced without a faulty device).  timeout_ticks bounds
+ * each wait of the exchange, in ticks of the 100 MHz device clock, counted
+ * from the wait's first unsuccessful poll (< 0: the library default, 2 s;
+ * 0: a wait gives up at its second unsuccessful poll).  preset_failure = 1
+ * makes later rlu_factor calls start as if a partner workgroup had already
+ * given up: every wait that does not succeed at once ends, every kernel
+ * exits normally and info[2] bit 0 is set.  Applies to later calls on this
+ * handle (the timeout also to rlu_factor_batched; preset_failure only to
+ * rlu_factor).  RLU_ERR_INVALID_ARG for preset_failure outside {0, 1}. */
+rlu_status_t rlu_set_exchange_limit(rlu_handle_t h, int64_t timeout_ticks, int preset_failure);
 
 const char* rlu_status_string(rlu_status_t st);
 

@@ -9,6 +9,7 @@ memory and streams.  If the library has not been built, every call raises
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -16,7 +17,7 @@ from dataclasses import dataclass
 __all__ = ["RluError", "Handle", "factor", "factor_batched", "lstsq", "Batch", "Server",
            "serve_footprint", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
-           "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS"]
+           "FLAG_CHECK_FINITE", "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS", "close_default_handles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librlu.so")
 
@@ -38,7 +39,7 @@ EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_fact
                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
                     "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
                     "rlu_status_string", "rlu_version", "rlu_lstsq",
-                    "rlu_lstsq_workspace_size"]
+                    "rlu_lstsq_workspace_size", "rlu_set_exchange_limit"]
 
 
 class RluError(RuntimeError):
@@ -130,6 +131,7 @@ def lib() -> ctypes.CDLL:
         L.rlu_status_string.restype = ctypes.c_char_p
         L.rlu_version.restype = ctypes.c_char_p
         L.rlu_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.rlu_set_exchange_limit.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int]
         L.rlu_lstsq.argtypes = [ctypes.c_void_p, ctypes.POINTER(LstsqDesc), ctypes.c_void_p]
         L.rlu_lstsq_workspace_size.argtypes = [ctypes.POINTER(LstsqDesc),
                                                ctypes.POINTER(ctypes.c_size_t)]
@@ -142,7 +144,7 @@ def lib() -> ctypes.CDLL:
                      "rlu_phase_times", "rlu_serve_create", "rlu_serve_submit",
                      "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
                      "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
-                     "rlu_lstsq", "rlu_lstsq_workspace_size"):
+                     "rlu_lstsq", "rlu_lstsq_workspace_size", "rlu_set_exchange_limit"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -188,30 +190,62 @@ class Handle:
         """Tile shape of a grouped product of the batched form (-1: tuned table)."""
         _check(lib().rlu_set_tile(self._h, product, cfg), "rlu_set_tile")
 
+    def set_exchange_limit(self, timeout_ticks: int = -1, preset_failure: bool = False):
+        """Test hook of the failure path of the pivot exchange (see
+        rlu_set_exchange_limit): per-wait limit in 100 MHz ticks (< 0: the
+        default) and whether calls start with the failure word set."""
+        _check(lib().rlu_set_exchange_limit(self._h, int(timeout_ticks), int(bool(preset_failure))),
+               "rlu_set_exchange_limit")
+
     def set_timing(self, enable=True):
-        """True / 1: every phase; 2: the sketch product only; False / 0: off."""
+        """True / 1: every phase; 2: the sketch product only; 3: the sketch
+        product and every pivoted-LU kernel launch; False / 0: off."""
         mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
         _check(lib().rlu_set_timing(self._h, mode), "rlu_set_timing")
 
     def phase_times(self, back: int = 0) -> dict:
-        """{phase name: ms} of the call `back` calls before the latest."""
-        cap = 16
+        """{phase name: ms} of the call `back` calls before the latest; in
+        timing mode 3 also "panel_lu_kernel": [ms of each launch]."""
+        cap = 32
         ms = (ctypes.c_float * cap)()
         names = (ctypes.c_char_p * cap)()
         cnt = ctypes.c_int()
         _check(lib().rlu_phase_times(self._h, back, ms, names, cap, ctypes.byref(cnt)),
                "rlu_phase_times")
-        return {names[i].decode(): float(ms[i]) for i in range(cnt.value)}
+        out, kern = {}, []
+        for i in range(min(cnt.value, cap)):
+            name = names[i].decode()
+            if name == "panel_lu_kernel":
+                kern.append(float(ms[i]))
+            else:
+                out[name] = float(ms[i])
+        if kern:
+            out["panel_lu_kernel"] = kern
+        return out
 
 
+# Default handles, one per (device, stream): a handle's workspace is reused by
+# every call and nothing orders calls on different streams.
 _handles: dict = {}
 
 
-def default_handle(device: int = 0) -> Handle:
-    h = _handles.get(device)
+def default_handle(device: int = 0, stream=None) -> Handle:
+    key = (device, int(stream.cuda_stream) if stream is not None else 0)
+    h = _handles.get(key)
     if h is None:
-        h = _handles[device] = Handle(device)
+        h = _handles[key] = Handle(device)
     return h
+
+
+def close_default_handles():
+    """Destroy the default handles (registered to run at interpreter exit,
+    before the HIP runtime and any profiler attached to it shut down)."""
+    while _handles:
+        _, h = _handles.popitem()
+        h.close()
+
+
+atexit.register(close_default_handles)
 
 
 def workspace_size(m, n, k, l, dtype=F64, precision=PREC_FP64, with_g=False,
@@ -297,18 +331,22 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters=0):
 
 def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
            diagnostics: bool = False, handle: Handle | None = None, stream=None,
-           out: Factors | None = None, power_iters: int = 0) -> Factors:
+           out: Factors | None = None, power_iters: int = 0,
+           check_finite: bool = False) -> Factors:
     """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
     float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
     tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
     p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
     current torch stream by default) and not synchronized.  ``power_iters``
-    is q of the power scheme, Y = (A A^T)^q A G (Section 5.2)."""
+    is q of the power scheme, Y = (A A^T)^q A G (Section 5.2).
+    ``check_finite`` asks for the scan for NaN / infinity (info[2] bit 1)."""
     import torch
 
     pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters)
-    h = handle or default_handle(A.device.index or 0)
+    if check_finite:
+        pb.flags |= FLAG_CHECK_FINITE
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
+    h = handle or default_handle(A.device.index or 0, s)
     st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),
                           ctypes.c_void_p(s.cuda_stream))
     _check(st, "rlu_factor")
@@ -346,8 +384,8 @@ def lstsq(f: Factors, b, *, handle: Handle | None = None, stream=None, x=None):
                   L.data_ptr(), _ld(L, m), U.data_ptr(), _ld(U, k),
                   f.p.data_ptr(), f.q.data_ptr(), r,
                   B.data_ptr(), _ld(B, m), X.data_ptr(), _ld(X, n))
-    h = handle or default_handle(L.device.index or 0)
     s = stream if stream is not None else torch.cuda.current_stream(L.device)
+    h = handle or default_handle(L.device.index or 0, s)
     _check(lib().rlu_lstsq(h.ptr, ctypes.byref(d), ctypes.c_void_p(s.cuda_stream)), "rlu_lstsq")
     return x[:, 0] if vec and x.dim() == 2 else x
 
@@ -358,10 +396,10 @@ class Batch:
     library's recorded launch graph."""
 
     def __init__(self, problems, *, precision: int | None = None, outs=None,
-                 power_iters: int = 0):
+                 power_iters: int = 0, check_finite: bool = False):
         """problems: sequence of (A, k, l) or (A, k, l, seed) or
         (A, k, l, seed, G) with A a column-major device tensor; power_iters
-        (Section 5.2) applies to every problem."""
+        (Section 5.2) and check_finite apply to every problem."""
         items = [tuple(p) + (0, None)[len(p) - 3:] if len(p) < 5 else tuple(p) for p in problems]
         self.count = len(items)
         self.pbs = (Problem * max(1, self.count))()
@@ -371,6 +409,8 @@ class Batch:
         for i, (A, k, l, seed, G) in enumerate(items):
             o = outs[i] if outs is not None else None
             pb, io, o = _prepare(A, k, l, precision, seed, G, False, o, power_iters)
+            if check_finite:
+                pb.flags |= FLAG_CHECK_FINITE
             self.pbs[i] = pb
             self.ios[i] = io
             self.outs.append(o)
@@ -382,8 +422,8 @@ class Batch:
 
         if self.count == 0:
             return self.outs
-        h = handle or default_handle(self.device.index or 0)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = handle or default_handle(self.device.index or 0, s)
         st = lib().rlu_factor_batched(h.ptr, self.count, self.pbs, self.ios,
                                       ctypes.c_void_p(s.cuda_stream))
         _check(st, "rlu_factor_batched")
@@ -391,13 +431,14 @@ class Batch:
 
 
 def factor_batched(problems, *, precision: int | None = None, handle: Handle | None = None,
-                   stream=None, outs=None, power_iters: int = 0) -> list:
+                   stream=None, outs=None, power_iters: int = 0,
+                   check_finite: bool = False) -> list:
     """Algorithm 4.1 for every (A, k, l[, seed[, G]]) in `problems`, as one
     batched call (with q = power_iters power iterations, Section 5.2, for
     all of them).  Returns a list of Factors (device tensors, not
     synchronized)."""
-    return Batch(problems, precision=precision, outs=outs,
-                 power_iters=power_iters).run(handle, stream)
+    return Batch(problems, precision=precision, outs=outs, power_iters=power_iters,
+                 check_finite=check_finite).run(handle, stream)
 
 
 def tile_names() -> dict:
@@ -432,7 +473,7 @@ class Server:
         self._keep = {}
 
     def submit(self, A, k: int, l: int, *, seed: int = 0, precision: int | None = None,
-               G=None, power_iters: int = 0) -> int:
+               G=None, power_iters: int = 0, check_finite: bool = False) -> int:
         """Queue A (column-major device tensor); returns the ticket.  Raises
         RluError on rejection (e.g. RLU_ERR_TOO_LARGE, RLU_ERR_QUEUE_FULL).
         A request with power iterations (Section 5.2) runs alone."""
@@ -448,7 +489,8 @@ class Server:
             dtype, prec = F32, (PREC_FP32 if precision is None else precision)
         else:
             raise ValueError("A must be float64 or float32")
-        pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, 0, power_iters)
+        pb = Problem(m, n, k, l, dtype, prec, seed, None, 0,
+                     FLAG_CHECK_FINITE if check_finite else 0, power_iters)
         if G is not None:
             pb.G = G.data_ptr()
             pb.ldg = max(G.stride(1), n) if l > 1 else n

@@ -122,8 +122,27 @@ __global__ void __launch_bounds__(256) assemble_batched_kernel(const AsmTaskDev*
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     t.info[0] = t.flags[0];
     t.info[1] = t.flags[1];
-    t.info[2] = t.flags[2];
+    // bit 0: the pivot exchange failed; bit 1: a non-finite value was found
+    // in the sketch (the check the caller asked for)
+    t.info[2] = (t.flags[2] != 0 ? 1 : 0) | (t.flags[4] != 0 ? 2 : 0);
   }
+}
+
+// Non-finite scan of a sketch (blockIdx.y = task): any NaN or infinity in
+// A or G reaches every entry of its row of Y = A G (x * 0 and inf - inf are
+// NaN), so scanning Y finds it without another pass over A.  A wave that
+// finds one stores 1 into the task's flag word (every writer stores the same
+// value).
+__global__ void __launch_bounds__(256) check_finite_kernel(const FiniteTaskDev* __restrict__ tasks,
+                                                           FiniteTaskDev one) {
+  const FiniteTaskDev t = tasks ? tasks[blockIdx.y] : one;
+  bool bad = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < t.count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long b = __double_as_longlong(t.Y[e]);
+    bad |= (b & 0x7ff0000000000000ull) == 0x7ff0000000000000ull;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) *t.flag = 1;
 }
 
 // dst (cols x rows) = src (rows x cols)^T through 32 x 32 LDS tiles.
@@ -239,6 +258,22 @@ hipError_t launch_assemble_one(const AsmTaskDev& t, hipStream_t s) {
 }
 template hipError_t launch_assemble_one<double>(const AsmTaskDev&, hipStream_t);
 template hipError_t launch_assemble_one<float>(const AsmTaskDev&, hipStream_t);
+
+hipError_t launch_check_finite(const FiniteTaskDev& t, hipStream_t s) {
+  if (t.count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(t.count, 2048)), dim3(256), 0, s,
+                     (const FiniteTaskDev*)nullptr, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite_batched(const FiniteTaskDev* tasks, int count, int64_t max_elems,
+                                       hipStream_t s) {
+  if (count <= 0 || max_elems <= 0) return hipSuccess;
+  if (count > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(max_elems, 256), (unsigned)count),
+                     dim3(256), 0, s, tasks, FiniteTaskDev{});
+  return hipGetLastError();
+}
 
 hipError_t launch_transpose(const double* src, int64_t lds, double* dst, int64_t ldd,
                             int64_t rows, int64_t cols, hipStream_t s) {

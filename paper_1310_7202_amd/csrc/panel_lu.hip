@@ -39,8 +39,10 @@
 //     step j+2 key, which each publishes only after it finished reading the
 //     buffers of step j (keys and header in its exchange, the winner's row in
 //     its bulk update of step j+1).
-//   * every wait is bounded by a wall-clock limit; on expiry the kernel sets
-//     a failure flag and all workgroups leave.
+//   * every wait is bounded by a wall-clock limit of its own (the clock
+//     starts at the wait's first unsuccessful poll, so a long batched launch
+//     whose later rounds start late never eats into a wait's budget); on
+//     expiry the kernel sets a failure flag and all workgroups leave.
 #include "rlu_device.h"
 #include "rlu_kernels.h"
 
@@ -175,13 +177,28 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // so the only device round trips on wave 0's path are the key exchange and
 // one header read; the row fetch spans a whole step, and the bulk waves
 // touch no device memory but their own publication.
+// A bound on one wait: its clock starts at the wait's first unsuccessful
+// poll (so a wait that succeeds at once never reads the clock) and the wait
+// gives up once more than `tmo` ticks have passed since then.
+struct WaitLimit {
+  long long t0 = -1;
+  __device__ __forceinline__ bool expired(long long tmo) {
+    const long long now = now_ticks();
+    if (t0 < 0) {
+      t0 = now;
+      return false;
+    }
+    return now - t0 > tmo;
+  }
+};
+
 template <int RPL>
 __device__ __forceinline__ void panel_body(
     double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R, int nwg,
     int* __restrict__ pos_out, int* __restrict__ rstep_out, int* __restrict__ piv_row_out,
     int* __restrict__ ipiv_out, int* __restrict__ info_out, int* __restrict__ fail,
     char* __restrict__ xch, int64_t rec_stride, long long timeout_ticks, int w, double* smem,
-    long long t_start, int step0, int total_cols, const int* __restrict__ pos_in,
+    int step0, int total_cols, const int* __restrict__ pos_in,
     const int* __restrict__ rstep_in) {
   constexpr int kThreads = threads_for<RPL>();
   double* Ts = smem;                        // R x ncols, column-major (ld R)
@@ -224,6 +241,14 @@ __device__ __forceinline__ void panel_body(
       if (s0 < step0) st = s0;
     }
     step_s[r] = st;
+  }
+  // the pivot row and position of every step start as valid indices (the
+  // step's own row and position), so that a factorization that stops early
+  // (an exchange failure) still hands its consumers, the assembly and the
+  // column blocks' triangular solves, in-range rows
+  for (int c = tid; c < ncols; c += kThreads) {
+    pivrow_s[c] = c;
+    ipiv_s[c] = step0 + c;
   }
   if (tid == 0) {
     sh_stop = 0;
@@ -351,8 +376,9 @@ __device__ __forceinline__ void panel_body(
           const int c = j + 1 + lane + 64 * t;
           if (c < ncols && !stop) {
             unsigned long long lo = bl[t], hi = bh[t];
+            WaitLimit wl;
             while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
-              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+              if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
                 stop = true;
                 break;
               }
@@ -365,8 +391,9 @@ __device__ __forceinline__ void panel_body(
         // columns past the prefetched ones (panels wider than 64 kPF)
         for (int c = j + 1 + 64 * kPF + lane; c < ncols && !stop; c += 64) {
           unsigned long long lo = ld_agent(pbody + 2 * c), hi = ld_agent(pbody + 2 * c + 1);
+          WaitLimit wl;
           while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
-            if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+            if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
               stop = true;
               break;
             }
@@ -400,6 +427,7 @@ __device__ __forceinline__ void panel_body(
           qa[q] = -1.0; qp[q] = INT_MAX; qrow[q] = -1;
           if (q < nq && lane + 64 * q < nwg) need |= 1u << q;
         }
+        WaitLimit wl;
         while (true) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -421,7 +449,7 @@ __device__ __forceinline__ void panel_body(
             }
           }
           if (__all(seen == need)) break;
-          if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) {
+          if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
             stop = true;
             break;
           }
@@ -451,6 +479,7 @@ __device__ __forceinline__ void panel_body(
             const unsigned long long* h =
                 (const unsigned long long*)(recs + (int64_t)bw * rec_stride);
             unsigned long long x[kHdrWords];
+            WaitLimit wh;
             while (!stop) {
               bool ok = true;
 #pragma unroll
@@ -458,7 +487,7 @@ __device__ __forceinline__ void panel_body(
 #pragma unroll
               for (int t = 0; t < kHdrWords; ++t) ok = ok && tagged(x[t], tag);
               if (__all(ok)) break;
-              if (now_ticks() - t_start > timeout_ticks || ld_agent_i(fail) != 0) stop = true;
+              if (wh.expired(timeout_ticks) || ld_agent_i(fail) != 0) stop = true;
             }
             if (!stop) {
               piv = bitsd(join64(x[0], x[1]));
@@ -669,7 +698,7 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
   extern __shared__ double smem[];
   panel_body<RPL>(X, rs, cs, nrows, ncols, R, nwg, pos_out, rstep_out, piv_row_out, ipiv_out,
                   info_out, fail, xch, rec_stride, timeout_ticks, (int)blockIdx.x, smem,
-                  now_ticks(), step0, total_cols, pos_in, rstep_in);
+                  step0, total_cols, pos_in, rstep_in);
 }
 
 // Many panels in one persistent launch.  Workgroup b runs, round by round,
@@ -682,13 +711,12 @@ __global__ void __launch_bounds__(threads_for<RPL>())
 panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __restrict__ sched,
                         int rounds, int nslots, long long timeout_ticks) {
   extern __shared__ double smem[];
-  const long long t0 = now_ticks();
   for (int r = 0; r < rounds; ++r) {
     const int e = sched[(int64_t)r * nslots + blockIdx.x];
     if (e < 0) continue;
     const PanelTaskDev t = tasks[e >> 8];
     panel_body<RPL>(t.X, t.rs, t.cs, t.nrows, t.ncols, t.R, t.nwg, t.pos, t.rstep, t.piv_row,
-                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem, t0,
+                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem,
                     0, t.ncols, nullptr, nullptr);
     __syncthreads();
   }

@@ -145,8 +145,22 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   return true;
 }
 
+// The integer a caller stored in an enum field.  A C caller may store any
+// int there; reading it as the C++ enum type is only defined for the
+// enumerators' range, so the raw bits are read and checked first.
+template <typename E>
+int raw_enum(const E& e) {
+  static_assert(sizeof(E) == sizeof(int), "enums of the C ABI are int-sized");
+  int v;
+  std::memcpy(&v, &e, sizeof v);
+  return v;
+}
+
 rlu_status_t validate(const rlu_problem_t* pb) {
   if (!pb) return RLU_ERR_INVALID_ARG;
+  const int dt = raw_enum(pb->dtype), pr = raw_enum(pb->precision);
+  if (dt != RLU_F64 && dt != RLU_F32) return RLU_ERR_INVALID_ARG;
+  if (pr < RLU_PREC_FP64 || pr > RLU_PREC_MIXED_FP16) return RLU_ERR_INVALID_ARG;
   if (pb->m < 1 || pb->n < 1 || pb->k < 1 || pb->l < pb->k) return RLU_ERR_INVALID_ARG;
   if (pb->l > std::min(pb->m, pb->n)) return RLU_ERR_INVALID_ARG;
   if (pb->m >= (1LL << 31) || pb->n >= (1LL << 31)) return RLU_ERR_TOO_LARGE;
@@ -208,6 +222,11 @@ rlu_status_t begin_timing(rlu_handle_s* h) {
       if (!t.ev[p][e] && hipEventCreate(&t.ev[p][e]) != hipSuccess) return RLU_ERR_DEVICE;
     t.used[p] = false;
   }
+  t.nk = 0;
+  if (h->timing_mode == 3)
+    for (int k = 0; k < kMaxKernelTimes; ++k)
+      for (int e = 0; e < 2; ++e)
+        if (!t.kev[k][e] && hipEventCreate(&t.kev[k][e]) != hipSuccess) return RLU_ERR_DEVICE;
   t.valid = true;
   h->cur = &t;
   h->ring_next = (h->ring_next + 1) % RLU_TIMING_RING;
@@ -224,20 +243,24 @@ using namespace rlu_detail;
 
 // Pivoted LU of the column-major panel X (nrows x ncols, leading dimension
 // ld), in one launch or in column blocks (BlockedPanel).
-rlu_status_t run_panel(double* X, int64_t ld, int nrows, int ncols, const BlockedPanel& bp,
-                       int* pos, int* rstep, int* piv, int* ipiv, int* info, int* fail,
-                       void* xch, double* u12, hipStream_t s) {
+rlu_status_t run_panel(rlu_handle_s* h, double* X, int64_t ld, int nrows, int ncols,
+                       const BlockedPanel& bp, int* pos, int* rstep, int* piv, int* ipiv,
+                       int* info, int* fail, void* xch, double* u12, long long tmo,
+                       hipStream_t s) {
   for (int b = 0; b < bp.nblocks; ++b) {
     const int c0 = b * bp.width;
     const int wb = b == bp.nblocks - 1 ? ncols - c0 : bp.width;
     PanelDesc d{};
     d.X = X + (int64_t)c0 * ld; d.rs = 1; d.cs = ld; d.nrows = nrows; d.ncols = wb;
     d.pos = pos; d.rstep = rstep; d.piv_row = piv + c0; d.ipiv = ipiv + c0;
-    d.info = info; d.fail = fail; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+    d.info = info; d.fail = fail; d.xch = xch; d.timeout_ticks = tmo;
     d.step0 = c0; d.total_cols = ncols;
     d.pos_in = b ? pos : nullptr;
     d.rstep_in = b ? rstep : nullptr;
-    HIP_TRY(launch_panel_lu(d, b == bp.nblocks - 1 ? bp.last : bp.main, s));
+    {
+      KernelScope ks(h, s);
+      HIP_TRY(launch_panel_lu(d, b == bp.nblocks - 1 ? bp.last : bp.main, s));
+    }
     const int c1 = c0 + wb;
     if (c1 < ncols) {
       // U rows of this block's pivots for the columns to its right ...
@@ -288,6 +311,10 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   const bool diag = (pb.flags & RLU_FLAG_DIAGNOSTICS) != 0;
 
   HIP_TRY(launch_fill_u32((uint32_t*)flags, 16, 0u, s));
+  // a test of the failure path: the exchange starts as if a partner had
+  // already given up
+  if (h->xch_preset_fail) HIP_TRY(launch_fill_u32((uint32_t*)flags + 2, 1, 1u, s));
+  const long long tmo = h->xch_timeout;
 
   // Step 1
   const T* G = (const T*)pb.G;
@@ -349,6 +376,10 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     rlu_status_t st = times_a(G, ldg, PH_SKETCH, PH_SKETCH_SUM);
     if (st != RLU_OK) return st;
   }
+  // the non-finite check the caller asked for: a NaN or infinity in A or G
+  // makes its row of Y non-finite
+  if (pb.flags & RLU_FLAG_CHECK_FINITE)
+    HIP_TRY(launch_check_finite(FiniteTaskDev{Y, m * l, flags + 4}, s));
   // Section 5.2: q power iterations, Y <- A (A^T Y).  Before each product
   // the block is replaced by the unit-lower factor of its pivoted LU in its
   // own row order (bounded entries, same column space).  The normalizations
@@ -361,14 +392,14 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     T* Gz = at<T>(ws, Ly.G);
     double* u12 = at<double>(ws, Ly.u12);
     for (int it = 0; it < pb.power_iters; ++it) {
-      rlu_status_t st = run_panel(Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
-                                  flags + 3, flags + 2, xch, u12, s);
+      rlu_status_t st = run_panel(h, Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
+                                  flags + 3, flags + 2, xch, u12, tmo, s);
       if (st != RLU_OK) return st;
       st = lvt_times_a(Zt, l, -1, -1);  // Z^T = Lv(Y)^T A  (l x n)
       if (st != RLU_OK) return st;
       HIP_TRY(launch_transpose(Zt, l, Z, n, l, n, s));
-      st = run_panel(Z, n, (int)n, (int)l, Ly.pz, pos_b, rstep_b, at<int>(ws, Ly.piv_z),
-                     at<int>(ws, Ly.ipiv_z), flags + 3, flags + 2, xch, u12, s);
+      st = run_panel(h, Z, n, (int)n, (int)l, Ly.pz, pos_b, rstep_b, at<int>(ws, Ly.piv_z),
+                     at<int>(ws, Ly.ipiv_z), flags + 3, flags + 2, xch, u12, tmo, s);
       if (st != RLU_OK) return st;
       HIP_TRY(launch_lv_dense<T>(Z, n, rstep_b, Gz, n, n, l, s));
       st = times_a(Gz, n, -1, -1);      // Y = A Lv(Z)
@@ -382,8 +413,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   // Step 3 (+ Step 4: only the first k columns of the unit-lower factor are used)
   {
     PhaseScope ph(h, PH_PANEL_Y, s);
-    rlu_status_t st = run_panel(Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
-                                flags + 0, flags + 2, xch, at<double>(ws, Ly.u12), s);
+    rlu_status_t st = run_panel(h, Y, m, (int)m, (int)l, Ly.py, pos_y, rstep_y, piv_y, ipiv_y,
+                                flags + 0, flags + 2, xch, at<double>(ws, Ly.u12), tmo, s);
     if (st != RLU_OK) return st;
   }
   if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
@@ -431,14 +462,15 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
       PanelDesc d{};
       d.X = Bst; d.rs = k; d.cs = 1; d.nrows = (int)n; d.ncols = (int)k;
       d.pos = pos_b; d.rstep = rstep_b; d.piv_row = piv_b; d.ipiv = ipiv_b;
-      d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = kTimeoutTicks;
+      d.info = flags + 1; d.fail = flags + 2; d.xch = xch; d.timeout_ticks = tmo;
+      KernelScope ks(h, s);
       HIP_TRY(launch_panel_lu(d, Ly.pb.main, s));
     } else {
       // blocked: on a column-major copy of B^T, then back into B's storage
       double* Bt = at<double>(ws, Ly.bt);
       HIP_TRY(launch_transpose(Bst, k, Bt, n, k, n, s));
-      rlu_status_t st = run_panel(Bt, n, (int)n, (int)k, Ly.pb, pos_b, rstep_b, piv_b, ipiv_b,
-                                  flags + 1, flags + 2, xch, at<double>(ws, Ly.u12), s);
+      rlu_status_t st = run_panel(h, Bt, n, (int)n, (int)k, Ly.pb, pos_b, rstep_b, piv_b, ipiv_b,
+                                  flags + 1, flags + 2, xch, at<double>(ws, Ly.u12), tmo, s);
       if (st != RLU_OK) return st;
       HIP_TRY(launch_transpose(Bt, n, Bst, k, n, k, s));
     }
@@ -477,7 +509,8 @@ rlu_status_t lstsq_validate(const rlu_lstsq_t* ls) {
     return RLU_ERR_INVALID_ARG;
   if (ls->m >= (1LL << 31) || ls->n >= (1LL << 31) || ls->nrhs >= (1LL << 31))
     return RLU_ERR_TOO_LARGE;
-  if (ls->dtype != RLU_F64 && ls->dtype != RLU_F32) return RLU_ERR_INVALID_ARG;
+  const int dt = raw_enum(ls->dtype);
+  if (dt != RLU_F64 && dt != RLU_F32) return RLU_ERR_INVALID_ARG;
   if (ls->ldl < ls->m || ls->ldu < ls->k || ls->ldb < ls->m || ls->ldx < ls->n)
     return RLU_ERR_INVALID_ARG;
   if (ls->nrhs > 0 && (!ls->L || !ls->U || !ls->p || !ls->q || !ls->b || !ls->x))
@@ -608,10 +641,14 @@ rlu_status_t rlu_destroy(rlu_handle_t h) {
   hipSetDevice(h->device);
   hipDeviceSynchronize();
   if (h->ws) hipFree(h->ws);
-  for (auto& t : h->ring)
+  for (auto& t : h->ring) {
     for (int p = 0; p < PH_COUNT; ++p)
       for (int e = 0; e < 2; ++e)
         if (t.ev[p][e]) hipEventDestroy(t.ev[p][e]);
+    for (int k = 0; k < kMaxKernelTimes; ++k)
+      for (int e = 0; e < 2; ++e)
+        if (t.kev[k][e]) hipEventDestroy(t.kev[k][e]);
+  }
   if (h->bgraph.exec) hipGraphExecDestroy(h->bgraph.exec);
   if (h->bgraph.graph) hipGraphDestroy(h->bgraph.graph);
   if (h->bws) hipFree(h->bws);
@@ -685,7 +722,7 @@ rlu_status_t rlu_lstsq(rlu_handle_t h, const rlu_lstsq_t* ls, rlu_stream_t strea
 }
 
 rlu_status_t rlu_set_timing(rlu_handle_t h, int enable) {
-  if (!h || enable < 0 || enable > 2) return RLU_ERR_INVALID_ARG;
+  if (!h || enable < 0 || enable > 3) return RLU_ERR_INVALID_ARG;
   h->timing = enable != 0;
   h->timing_mode = enable;
   if (!h->timing) { h->ring_filled = 0; h->ring_next = 0; }
@@ -708,14 +745,31 @@ rlu_status_t rlu_phase_times(rlu_handle_t h, int back, float* ms, const char** n
     if (ms) ms[p] = v;
     if (names) names[p] = kPhaseNames[p];
   }
-  if (count) *count = PH_COUNT;
+  for (int k = 0; k < t.nk && PH_COUNT + k < cap; ++k) {
+    float v = 0.f;
+    if (hipEventSynchronize(t.kev[k][1]) != hipSuccess ||
+        hipEventElapsedTime(&v, t.kev[k][0], t.kev[k][1]) != hipSuccess)
+      return RLU_ERR_DEVICE;
+    if (ms) ms[PH_COUNT + k] = v;
+    if (names) names[PH_COUNT + k] = "panel_lu_kernel";
+  }
+  if (count) *count = PH_COUNT + t.nk;
   return RLU_OK;
 }
 
 rlu_status_t rlu_check_info(const int32_t info_host[3]) {
   if (!info_host) return RLU_ERR_INVALID_ARG;
+  if (info_host[2] & 1) return RLU_ERR_DEVICE;
+  if (info_host[2] & 2) return RLU_ERR_NONFINITE;
   if (info_host[2] != 0) return RLU_ERR_DEVICE;
   if (info_host[0] != 0 || info_host[1] != 0) return RLU_WARN_ZERO_PIVOT;
+  return RLU_OK;
+}
+
+rlu_status_t rlu_set_exchange_limit(rlu_handle_t h, int64_t timeout_ticks, int preset_failure) {
+  if (!h || preset_failure < 0 || preset_failure > 1) return RLU_ERR_INVALID_ARG;
+  h->xch_timeout = timeout_ticks < 0 ? kTimeoutTicks : (long long)timeout_ticks;
+  h->xch_preset_fail = preset_failure != 0;
   return RLU_OK;
 }
 

@@ -76,6 +76,7 @@ struct Plan {
   std::vector<char> tab;  // host image of the tables
   // launches
   size_t gauss = 0; int n_gauss = 0; int64_t gauss_max = 0;
+  size_t fin = 0; int n_fin = 0; int64_t fin_max = 0;  // non-finite checks of the sketches
   std::vector<GemmLaunch> sketch, gram, project, solve, forml;
   size_t gram_all = 0; int gram_count = 0; int64_t gram_max = 0; bool gram_split = false;
   PanelLaunch py, pbt;
@@ -248,7 +249,19 @@ int schedule_gangs(const std::vector<int>& nwg, const std::vector<int>& ncols, i
   return (int)rounds.size();
 }
 
-rlu_status_t plan_panels(const Plan& P, PanelRun run, int cus, char* base, TableWriter& tw,
+// The workspace base the task tables point into; null while the tables are
+// only being sized, when the addresses they hold are placeholders (a
+// non-null constant plus the offset, never dereferenced) rather than
+// arithmetic on a null pointer.
+struct WsBase {
+  char* p;
+  char* operator+(size_t off) const {
+    return p ? p + off : reinterpret_cast<char*>(uintptr_t{4096} + off);
+  }
+  bool operator==(std::nullptr_t) const { return p == nullptr; }
+};
+
+rlu_status_t plan_panels(const Plan& P, PanelRun run, int cus, WsBase base, TableWriter& tw,
                          PanelLaunch& L) {
   const bool second = run == PanelRun::BT;
   const bool zrun = run == PanelRun::Z;
@@ -402,7 +415,7 @@ rlu_status_t plan_layout(Plan& P, int count, const rlu_problem_t* pbs, const rlu
 }
 
 // Task tables for the workspace at `base` (base may be null to size them).
-rlu_status_t build_tables(Plan& P, char* base, int cus) {
+rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
   P.tab.clear();
   P.sketch.clear(); P.gram.clear(); P.project.clear(); P.solve.clear(); P.forml.clear();
   P.zproj.clear(); P.resketch.clear();
@@ -433,6 +446,19 @@ rlu_status_t build_tables(Plan& P, char* base, int cus) {
       cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Sketch, g.N));
     }
     add_gemm_launches(tw, t, cfg, P.lp, P.sketch);
+  }
+  // the non-finite checks of the problems that ask for one (on Y = A G)
+  {
+    std::vector<FiniteTaskDev> fin;
+    P.fin_max = 0;
+    for (const Item& it : P.items) {
+      if (!(it.pb.flags & RLU_FLAG_CHECK_FINITE)) continue;
+      fin.push_back(FiniteTaskDev{(const double*)(base + it.Y), it.pb.m * it.pb.l,
+                                  (int*)(base + it.flags) + 4});
+      P.fin_max = std::max<int64_t>(P.fin_max, it.pb.m * it.pb.l);
+    }
+    P.n_fin = (int)fin.size();
+    P.fin = tw.put(fin);
   }
   // Section 5.2: the tables of one round of the power iterations
   if (P.power > 0) {
@@ -601,14 +627,15 @@ rlu_status_t enqueue_gemms(const std::vector<GemmLaunch>& ls, char* tab, GemmRol
 // Panel launches keep every workgroup of the device busy; two of them must
 // never run at once (their gangs could hold each other's workgroups), so an
 // optional gate event orders each panel launch after the previous one.
-hipError_t gated_panel(const PanelLaunch& L, char* tab, hipEvent_t gate, hipStream_t s) {
+hipError_t gated_panel(const PanelLaunch& L, char* tab, hipEvent_t gate, long long tmo,
+                       hipStream_t s) {
   if (gate) {
     hipError_t e = hipStreamWaitEvent(s, gate, 0);
     if (e != hipSuccess) return e;
   }
   hipError_t e = launch_panel_lu_batched((const PanelTaskDev*)(tab + L.tasks),
                                          (const int*)(tab + L.sched), L.rounds, L.nslots, L.maxR,
-                                         L.lds, kTimeoutTicks, s);
+                                         L.lds, tmo, s);
   if (e == hipSuccess && gate) e = hipEventRecord(gate, s);
   return e;
 }
@@ -628,17 +655,20 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
     rlu_status_t st = enqueue_gemms(P.sketch, tab, GemmRole::Sketch, OpA::Plain, P.f32, P.fp16, s);
     if (st != RLU_OK) return st;
   }
+  if (P.n_fin > 0)
+    HIP_TRY(launch_check_finite_batched((const FiniteTaskDev*)(tab + P.fin), P.n_fin, P.fin_max, s));
+  const long long tmo = h->xch_timeout;
   if (P.power > 0) {
     PhaseScope ph(h, PH_POWER, s);
     uint32_t* xch = (uint32_t*)(base + P.xch_begin);
     const size_t xwords = (P.zero_bytes - P.xch_begin) / 4;
     for (int r = 0; r < P.power; ++r) {
       HIP_TRY(launch_fill_u32(xch, xwords, 0u, s));
-      HIP_TRY(gated_panel(P.pyn, tab, gate, s));
+      HIP_TRY(gated_panel(P.pyn, tab, gate, tmo, s));
       rlu_status_t st = enqueue_gemms(P.zproj, tab, GemmRole::Project, OpA::LvT, P.f32, P.fp16, s);
       if (st != RLU_OK) return st;
       HIP_TRY(launch_fill_u32(xch, xwords, 0u, s));
-      HIP_TRY(gated_panel(P.pz, tab, gate, s));
+      HIP_TRY(gated_panel(P.pz, tab, gate, tmo, s));
       HIP_TRY(launch_lv_dense_batched<T>((const LvDenseTaskDev*)(tab + P.lvd), count, P.lvd_max,
                                          s));
       st = enqueue_gemms(P.resketch, tab, GemmRole::Sketch, OpA::Plain, P.f32, P.fp16, s);
@@ -648,7 +678,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_PANEL_Y, s);
-    HIP_TRY(gated_panel(P.py, tab, gate, s));
+    HIP_TRY(gated_panel(P.py, tab, gate, tmo, s));
   }
   {
     PhaseScope ph(h, PH_GRAM, s);
@@ -674,7 +704,7 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   }
   {
     PhaseScope ph(h, PH_PANEL_B, s);
-    HIP_TRY(gated_panel(P.pbt, tab, gate, s));
+    HIP_TRY(gated_panel(P.pbt, tab, gate, tmo, s));
   }
   {
     PhaseScope ph(h, PH_ASSEMBLE, s);
@@ -761,9 +791,11 @@ rlu_status_t capture(rlu_handle_s* h, const Plan& P) {
 std::vector<char> signature(rlu_handle_s* h, int count, const rlu_problem_t* pbs,
                             const rlu_buffers_t* ios) {
   std::vector<char> sig(sizeof(int) + sizeof(void*) + sizeof(int) + sizeof(h->tile_override) +
+                        sizeof(long long) +
                         count * (sizeof(rlu_problem_t) + sizeof(rlu_buffers_t)));
   char* p = sig.data();
   std::memcpy(p, h->tile_override, sizeof(h->tile_override)); p += sizeof(h->tile_override);
+  std::memcpy(p, &h->xch_timeout, sizeof(long long)); p += sizeof(long long);
   std::memcpy(p, &count, sizeof(int)); p += sizeof(int);
   std::memcpy(p, &h->bws, sizeof(void*)); p += sizeof(void*);
   std::memcpy(p, &h->cus, sizeof(int)); p += sizeof(int);
@@ -791,7 +823,7 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
   for (int r = 0; r < 5; ++r) P.tile[r] = h->tile_override[r];
   rlu_status_t st = plan_layout(P, count, pbs, ios);
   if (st != RLU_OK) return st;
-  st = build_tables(P, nullptr, h->cus);  // sizes only
+  st = build_tables(P, WsBase{nullptr}, h->cus);  // sizes only
   if (st != RLU_OK) return st;
   st = ensure_bws(h, P.total);
   if (st != RLU_OK) return st;
@@ -804,7 +836,7 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
       return RLU_OK;
     }
     drop_graph(h);
-    st = build_tables(P, (char*)h->bws, h->cus);
+    st = build_tables(P, WsBase{(char*)h->bws}, h->cus);
     if (st != RLU_OK) return st;
     if (P.total > h->bws_bytes) return RLU_ERR_DEVICE;  // the sizing pass bounds it
     st = upload_tables(h, P, (char*)h->bws, s);
@@ -817,7 +849,7 @@ extern "C" rlu_status_t rlu_factor_batched(rlu_handle_t h, int32_t count,
   }
   // timed calls run the same sequence eagerly, with phase events
   drop_graph(h);
-  st = build_tables(P, (char*)h->bws, h->cus);
+  st = build_tables(P, WsBase{(char*)h->bws}, h->cus);
   if (st != RLU_OK) return st;
   if (P.total > h->bws_bytes) return RLU_ERR_DEVICE;  // the sizing pass bounds it
   st = upload_tables(h, P, (char*)h->bws, s);
@@ -857,7 +889,7 @@ rlu_status_t batched_item_bytes(const rlu_problem_t& pb, int cus, size_t* bytes)
   Plan P;
   rlu_status_t st = plan_layout(P, 1, &pb, &io);
   if (st != RLU_OK) return st;
-  st = build_tables(P, nullptr, cus);
+  st = build_tables(P, WsBase{nullptr}, cus);
   if (st != RLU_OK) return st;
   // in a larger batch the same entries, plus alignment and the XCD padding of
   // each tile map (< 8 entries per launch); the sizing pass already reserves
@@ -873,7 +905,7 @@ rlu_status_t batched_ws_bytes(int count, const rlu_problem_t* pbs, const rlu_buf
   Plan P;
   rlu_status_t st = plan_layout(P, count, pbs, ios);
   if (st != RLU_OK) return st;
-  st = build_tables(P, nullptr, cus);
+  st = build_tables(P, WsBase{nullptr}, cus);
   if (st != RLU_OK) return st;
   *bytes = P.total;
   return RLU_OK;
@@ -887,7 +919,7 @@ rlu_status_t batched_enqueue_ws(rlu_handle_s* h, int count, const rlu_problem_t*
   Plan P;
   rlu_status_t st = plan_layout(P, count, pbs, ios);
   if (st != RLU_OK) return st;
-  st = build_tables(P, (char*)ws, h->cus);
+  st = build_tables(P, WsBase{(char*)ws}, h->cus);
   if (st != RLU_OK) return st;
   if (P.total > ws_bytes) return RLU_ERR_INVALID_ARG;
   st = upload_tables(h, P, (char*)ws, s);

@@ -18,9 +18,15 @@ enum Phase {
   PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_SKETCH_SUM, PH_PROJECT_SUM, PH_POWER, PH_COUNT
 };
 
+// Timing mode 3 also times every launch of the pivoted-LU kernel of a call
+// (up to kMaxKernelTimes of them; later launches are not timed).
+constexpr int kMaxKernelTimes = 16;
+
 struct TimingSlot {
   hipEvent_t ev[PH_COUNT][2] = {};
   bool used[PH_COUNT] = {};
+  hipEvent_t kev[kMaxKernelTimes][2] = {};
+  int nk = 0;
   bool valid = false;
 };
 
@@ -35,7 +41,8 @@ struct BatchGraph {
 struct rlu_handle_s {
   int device = 0;
   bool timing = false;
-  int timing_mode = 0;      // 1: every phase, 2: the sketch product only
+  int timing_mode = 0;      // 1: every phase, 2: the sketch product only, 3: the
+                            // sketch product and every pivoted-LU kernel launch
   int ring_next = 0;        // next slot to fill
   int ring_filled = 0;      // number of valid slots
   TimingSlot ring[RLU_TIMING_RING];
@@ -53,6 +60,8 @@ struct rlu_handle_s {
   hipEvent_t ev_panel = nullptr; // last batched panel launch (eager calls)
   BatchGraph bgraph;
   int tile_override[5] = {-1, -1, -1, -1, -1};  // rlu_set_tile
+  long long xch_timeout = 200LL * 1000 * 1000;  // bound on each exchange wait (ticks)
+  bool xch_preset_fail = false;                 // rlu_set_exchange_limit
 };
 
 namespace rlu_detail {
@@ -93,7 +102,7 @@ struct PhaseScope {
   rlu_handle_s* h; int id; hipStream_t s; bool on;
   PhaseScope(rlu_handle_s* h_, int id_, hipStream_t s_)
       : h(h_), id(id_), s(s_),
-        on(id_ >= 0 && h_->timing && h_->cur && (h_->timing_mode != 2 || id_ == PH_SKETCH)) {
+        on(id_ >= 0 && h_->timing && h_->cur && (h_->timing_mode == 1 || id_ == PH_SKETCH)) {
     if (on) {
       h->cur->used[id] = true;
       hipEventRecord(h->cur->ev[id][0], s);
@@ -101,6 +110,20 @@ struct PhaseScope {
   }
   ~PhaseScope() {
     if (on) hipEventRecord(h->cur->ev[id][1], s);
+  }
+};
+
+// Event pair around one launch of the pivoted-LU kernel (timing mode 3).
+struct KernelScope {
+  rlu_handle_s* h; hipStream_t s; int idx;
+  KernelScope(rlu_handle_s* h_, hipStream_t s_) : h(h_), s(s_), idx(-1) {
+    if (h && h->timing && h->timing_mode == 3 && h->cur && h->cur->nk < kMaxKernelTimes) {
+      idx = h->cur->nk++;
+      hipEventRecord(h->cur->kev[idx][0], s);
+    }
+  }
+  ~KernelScope() {
+    if (idx >= 0) hipEventRecord(h->cur->kev[idx][1], s);
   }
 };
 

@@ -212,5 +212,11 @@ hipError_t launch_assemble_batched(const AsmTaskDev* tasks, int count, int64_t m
 // The same for one problem, its task passed by value.
 template <typename TO>
 hipError_t launch_assemble_one(const AsmTaskDev& t, hipStream_t s);
+// flag = 1 if Y (count contiguous FP64 values) holds a NaN or an infinity;
+// the flag is left alone otherwise.
+struct FiniteTaskDev { const double* Y; int64_t count; int* flag; };
+hipError_t launch_check_finite(const FiniteTaskDev& t, hipStream_t s);
+hipError_t launch_check_finite_batched(const FiniteTaskDev* tasks, int count, int64_t max_elems,
+                                       hipStream_t s);
 
 }  // namespace rlu

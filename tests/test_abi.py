@@ -44,6 +44,29 @@ def test_check_info_mapping(rlu):
     assert rlu.check_info([3, 0, 0]) == 2
     assert rlu.check_info([0, 1, 0]) == 2
     assert rlu.check_info([0, 0, 1]) == -3
+    # info[2] bit 1: the requested non-finite check found a NaN / infinity
+    assert rlu.check_info([0, 0, 2]) == -6
+    assert rlu.check_info([4, 0, 2]) == -6
+    # an exchange failure dominates (the outputs are undefined)
+    assert rlu.check_info([0, 0, 3]) == -3
+    # bits this version does not define read as a device failure
+    assert rlu.check_info([0, 0, 4]) == -3
+
+
+def test_check_finite_flag_is_accepted(rlu):
+    # the flag is implemented, not reserved: valid on every precision
+    for dtype, prec in ((0, 0), (1, 1), (1, 2), (1, 3)):
+        assert _ws(rlu, 100, 100, 5, 8, dtype=dtype, prec=prec, flags=rlu.FLAG_CHECK_FINITE)[0] == 0
+        assert _ws(rlu, 100, 100, 5, 8, dtype=dtype, prec=prec,
+                   flags=rlu.FLAG_CHECK_FINITE | rlu.FLAG_DIAGNOSTICS)[0] == 0
+
+
+def test_exchange_limit_argument_checks(rlu):
+    lib = rlu.lib()
+    assert lib.rlu_set_exchange_limit(None, 0, 0) == -1
+    h = ctypes.c_void_p(1)   # never dereferenced: the argument check comes first
+    assert lib.rlu_set_exchange_limit(h, 0, 2) == -1
+    assert lib.rlu_set_exchange_limit(h, 0, -1) == -1
 
 
 def _ws(rlu, m, n, k, l, dtype=0, prec=0, G=None, ldg=0, flags=0, power_iters=0):
