@@ -5,17 +5,21 @@ arXiv 1310.7202) on one MI355X.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 A step is one complete rlu_factor call (Steps 1-8: Gaussian sketch matrix,
-sketch GEMM, pivoted LU of Y, Gram matrix and its inverse, projection GEMM,
-pivoted LU of B^T, assembly of L and U) on a device-resident input; for the
-batched workload a step is one rlu_factor_batched call over 256 problems.
-Prints one JSON line: the main workload (default: 8192 x 8192 FP64) plus,
-under "forms", the same matrix through the FP32 path and with one power
-iteration (Section 5.2), least squares on its factors (Algorithm 4.3),
-the 512 x 512 configuration's p50/p99 latency, the 16384 x 16384
-mixed-precision configuration beside the FP64 path on the same matrix, the
-256-problem batch, and the served request stream (throughput with p50/p99
-latency; disable the extra measurements with --forms none).  Only one GPU is used; --gpus N with
-N > 1 exits with a message.
+sketch product, pivoted LU of Y, Gram matrix and its inverse, projection
+product, pivoted LU of B^T, assembly of L and U) on a device-resident input.
+The default workload is the mixed-precision configuration the metric is
+quoted on: 16384 x 16384, sigma_i = i^-2, k = 500, l = 520, A stored FP32,
+the two products with A on BF16 matrix cores with FP32 accumulation, the
+pivoted LUs and the Gram inverse in FP64; the same matrix in FP64 through the
+FP64 path is timed beside it for the equal-error comparison.  One JSON line:
+the headline with the roofline of its dominant kernel (timed live with HIP
+events around each of its launches), the per-phase table, the step roofline
+and the oracle timed on the host cores, plus, under "forms", the 8192 x 8192
+configuration in FP64 (with its FP32 path, one power iteration of Section 5.2
+and least squares on its factors, Algorithm 4.3), the 512 x 512
+configuration's p50/p99 latency, the 256-problem batch and the served request
+stream (disable the extra measurements with --forms none).  Only one GPU is
+used; --gpus N with N > 1 exits with a message.
 """
 from __future__ import annotations
 
@@ -78,11 +82,30 @@ def make_input(name, torch, kind="spectral"):
     return A, k, l, sseed
 
 
-def power_residual(A, L, U, p, q, iters=30):
-    """||L U - P A Q||_2 / ||A||_2 by power iterations (validation only)."""
+def block_norm(mv, rmv, n, like, iters=40, block=8, seed=1):
+    """Largest singular value of an operator given by its products: subspace
+    iteration with an orthonormalized block of `block` vectors, then the
+    largest singular value on the final block (a lower bound that resolves a
+    cluster of up to `block` leading values; validation only)."""
     import torch
-    gen = torch.Generator(device=A.device)
-    gen.manual_seed(1)
+    gen = torch.Generator(device=like.device)
+    gen.manual_seed(seed)
+    X = torch.randn(n, block, generator=gen, device=like.device, dtype=torch.float64)
+    X, _ = torch.linalg.qr(X)
+    for _ in range(iters):
+        Z = rmv(mv(X))
+        if not bool(torch.any(Z != 0)):
+            return 0.0
+        X, _ = torch.linalg.qr(Z)
+    return float(torch.linalg.svdvals(mv(X))[0])
+
+
+def power_residual(A, L, U, p, q, iters=40):
+    """||L U - P A Q||_2 / ||A||_2 (Section 5.1's relative error) by block
+    subspace iterations on the device, in FP64 (validation only)."""
+    import torch
+    A = A.double()
+    L, U = L.double(), U.double()
     n = A.shape[1]
     qinv = torch.empty_like(q); qinv[q] = torch.arange(q.numel(), device=q.device)
     pinv = torch.empty_like(p); pinv[p] = torch.arange(p.numel(), device=p.device)
@@ -93,27 +116,15 @@ def power_residual(A, L, U, p, q, iters=30):
     def opt(y):
         return U.t() @ (L.t() @ y) - (A.t() @ y[pinv])[q]
 
-    x = torch.randn(n, generator=gen, device=A.device, dtype=A.dtype)
-    x /= x.norm()
-    r = 0.0
-    for _ in range(iters):
-        z = opt(op(x)); nz = z.norm()
-        if nz == 0:
-            break
-        r = math.sqrt(float(nz)); x = z / nz
-    x = torch.randn(n, generator=gen, device=A.device, dtype=A.dtype)
-    x /= x.norm()
-    a = 0.0
-    for _ in range(iters):
-        z = A.t() @ (A @ x); nz = z.norm()
-        a = math.sqrt(float(nz)); x = z / nz
+    r = block_norm(op, opt, n, A, iters)
+    a = block_norm(lambda x: A @ x, lambda y: A.t() @ y, n, A, iters)
     return r / a
 
 
-def traffic_from_profiles(kernel_src):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_sketch_gemm_exp8192.md")
+def traffic_from_profiles(profile, kernel_src):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 counter
+    summary, if it was taken on the current source of that kernel."""
+    path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -125,14 +136,26 @@ def traffic_from_profiles(kernel_src):
     return float(m_b.group(1)) if h == m_h.group(1) else None
 
 
-def cpu_baseline(A_host, k, l, seed, budget_s):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(A_host, k, l, seed, budget_s, one_thread=True):
+    """The FP64 oracle as it stands, timed on the host cores: full
+    factorizations of the workload's own matrix with all BLAS threads (at
+    least one, until `budget_s` has passed), then one with a single BLAS
+    thread.  The oracle's pivoted-LU loops are NumPy vector operations, which
+    run on one core either way."""
     import numpy as np
     from oracle import philox, rlu as orl
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     m, n = A_host.shape
     G = philox.gaussian_matrix(n, l, seed)
     runs, t0 = 0, time.perf_counter()
@@ -144,160 +167,221 @@ def cpu_baseline(A_host, k, l, seed, budget_s):
         log(f"oracle run {runs}: {el:.1f} s")
         if el >= budget_s or runs >= 50:
             break
-    return {"value": runs / el, "unit": "factorizations/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"{runs} full factorization(s) of the same input by the FP64 NumPy oracle "
-                      f"in {el:.1f} s"}, out, G
+    res = {"value": runs / el, "unit": "factorizations/s", "cores": int(cores), "kind": "oracle",
+           "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"{runs} full factorization(s) of the workload's matrix ({m}x{n}, k={k}, "
+                     f"l={l}) by the FP64 NumPy oracle in {el:.1f} s, {cores} BLAS threads"}
+    if one_thread:
+        with threadpool_limits(limits=1):
+            t1 = time.perf_counter()
+            orl.randomized_lu(A_host, k, l, G)
+            e1 = time.perf_counter() - t1
+        res["one_thread"] = {"value": 1.0 / e1, "unit": "factorizations/s", "cores": 1,
+                             "sample": f"1 full factorization, 1 BLAS thread, {e1:.1f} s"}
+        log(f"oracle, 1 thread: {e1:.1f} s")
+    return res, out, G
 
 
-def phase_work(m, n, k, l, s_a, s_out):
-    """Algorithmic flops and HBM bytes of each timed phase for one problem
-    (what the method must do: dense products counted at 2 flops per
+# Peak of each phase: the two products with A run at the MFMA peak of the
+# product precision; the Gram, S^-1 C and L = Lv L_b products are FP64 MFMA
+# in every mode; the pivoted LUs and the sweep inverse are FP64 vector work.
+PROD_PEAK = {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp16": "bf16"}
+
+
+def phase_work(m, n, k, l, s_a, s_out, prod="fp64"):
+    """Algorithmic flops, HBM bytes and peak of each timed phase for one
+    problem (what the method must do: dense products counted at 2 flops per
     multiply-add, operands read once, results written once)."""
+    pk = PROD_PEAK[prod]
     return {
-        "sketch_gemm": (2.0 * m * n * l, s_a * m * n + s_a * n * l + 8.0 * m * l),
-        "panel_lu_y": (m * l * l - l ** 3 / 3.0, 16.0 * m * l),
-        "gram_gemm": (2.0 * m * k * k, 8.0 * m * k),
-        "gram_inverse": (2.0 * k ** 3, 16.0 * k * k),
-        "project_gemm": (2.0 * m * n * k, s_a * m * n + 8.0 * m * k + 8.0 * k * n),
-        "solve_gemm": (2.0 * k * k * n, 16.0 * k * n + 8.0 * k * k),
-        "panel_lu_bt": (n * k * k - k ** 3 / 3.0, 16.0 * k * n),
-        "form_l_gemm": (2.0 * m * k * k, 8.0 * m * k + s_out * m * k),
+        "sketch_gemm": (2.0 * m * n * l, s_a * m * n + s_a * n * l + 8.0 * m * l, pk),
+        "panel_lu_y": (m * l * l - l ** 3 / 3.0, 16.0 * m * l, "f64"),
+        "gram_gemm": (2.0 * m * k * k, 8.0 * m * k, "f64"),
+        "gram_inverse": (2.0 * k ** 3, 16.0 * k * k, "f64"),
+        "project_gemm": (2.0 * m * n * k, s_a * m * n + 8.0 * m * k + 8.0 * k * n, pk),
+        "solve_gemm": (2.0 * k * k * n, 16.0 * k * n + 8.0 * k * k, "f64"),
+        "panel_lu_bt": (n * k * k - k ** 3 / 3.0, 16.0 * k * n, "f64"),
+        "form_l_gemm": (2.0 * m * k * k, 8.0 * m * k + s_out * m * k, "f64"),
     }
 
 
-def kernel_table(phase_ms, works, mfma_peak):
+def kernel_table(phase_ms, works):
     """Per-phase achieved rates against the roofline of that phase: bound =
-    whichever of MFMA time and HBM time is larger; the two pivoted LUs are
-    chains of l (or k) dependent steps and are reported as latency-bound."""
+    whichever of MFMA time (at the phase's own peak) and HBM time is larger;
+    the two pivoted LUs and the sweep inverse are chains of dependent steps
+    and are reported as latency-bound."""
     out = {}
-    for name, (fl, by) in works.items():
+    for name, (fl, by, pk) in works.items():
         t = phase_ms.get(name, 0.0) * 1e-3
         if t <= 0:
             continue
-        t_f, t_b = fl / mfma_peak, by / PEAK["hbm"]
+        t_f, t_b = fl / PEAK[pk], by / PEAK["hbm"]
         if name.startswith("panel") or name == "gram_inverse":
             bound = "latency"
         else:
             bound = "mfma" if t_f >= t_b else "hbm"
         out[name] = {"ms": phase_ms[name], "tflops": fl / t / 1e12, "gbs": by / t / 1e9,
-                     "bound": bound, "roofline_frac": max(t_f, t_b) / t}
+                     "bound": bound, "peak": pk, "roofline_frac": max(t_f, t_b) / t}
     return out
 
 
-def sum_works(shapes, s_a, s_out):
+def sum_works(shapes, s_a, s_out, prod="fp64"):
     tot = {}
     for (m, n, k, l) in shapes:
-        for key, (f, b) in phase_work(m, n, k, l, s_a, s_out).items():
-            a = tot.get(key, (0.0, 0.0))
-            tot[key] = (a[0] + f, a[1] + b)
+        for key, (f, b, pk) in phase_work(m, n, k, l, s_a, s_out, prod).items():
+            a = tot.get(key, (0.0, 0.0, pk))
+            tot[key] = (a[0] + f, a[1] + b, pk)
     return tot
 
 
-def step_roofline(works, mfma_peak, ms_per_step):
-    """T_roof = max(GEMM flops / MFMA peak, GEMM bytes / HBM) + small-kernel
-    flops at the same peak, against the measured step time."""
-    gem = [k for k in works if k.endswith("gemm")]
-    f = sum(works[k][0] for k in gem)
-    b = sum(works[k][1] for k in gem)
-    tail = sum(v[0] for k, v in works.items() if k not in gem)
-    t_roof = max(f / mfma_peak, b / PEAK["hbm"]) + tail / PEAK["f64"]
+def step_roofline(works, ms_per_step):
+    """T_roof = max(flops of the two products with A / their MFMA peak, their
+    bytes / HBM) + every other phase's flops at its own peak, against the
+    measured step time."""
+    big = ("sketch_gemm", "project_gemm")
+    t_f = sum(works[key][0] / PEAK[works[key][2]] for key in big if key in works)
+    b = sum(works[key][1] for key in big if key in works)
+    tail = sum(v[0] / PEAK[v[2]] for key, v in works.items() if key not in big)
+    t_roof = max(t_f, b / PEAK["hbm"]) + tail
     return {"t_roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms_per_step}
 
 
-def run_single(rlu, torch, np, name, steps, warmup, input_kind="spectral", check=True):
-    m, n, k, l = WORKLOADS[name][:4]
-    prec = WORKLOADS[name][7]
-    log(f"generating {WORKLOADS[name][8]}")
-    A, k, l, sseed = make_input(name, torch, input_kind)
-    torch.cuda.synchronize()
-    log("input ready")
+def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_iters=0,
+                 phase_calls=5):
+    """`steps` rlu_factor calls in the timed region (timing mode 3: HIP events
+    around the sketch product and around every pivoted-LU kernel launch, on
+    the stream they run on), then `phase_calls` calls with every phase timed.
+    Returns the outputs, calls/s, ms per call, per-call latencies, the mean
+    phase table, and the live kernel times (sketch ms per call, panel-kernel
+    ms per launch and launches per call)."""
     h = rlu.Handle(0)
-    # the timed region carries one event pair per call, around the sketch
-    # product (the roofline kernel); every phase is timed in a pass after it
-    h.set_timing(2)
-    out = rlu.Factors(torch.empty((k, m), dtype=A.dtype, device="cuda").t(),
-                      torch.empty((n, k), dtype=A.dtype, device="cuda").t(),
-                      torch.empty(m, dtype=torch.int64, device="cuda"),
-                      torch.empty(n, dtype=torch.int64, device="cuda"),
-                      torch.empty(3, dtype=torch.int32, device="cuda"))
-    stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
-    torch.cuda.synchronize()
-    log(f"warmup {warmup} done")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        evs[i][0].record(stream)
-        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
-        evs[i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    log(f"{name}: timed {steps} steps in {wall * 1e3:.1f} ms")
-    lat = np.array([a.elapsed_time(b) for a, b in evs])
-    sketch_timed = float(np.mean([h.phase_times(back)["sketch_gemm"] for back in range(steps)]))
-    # every phase, in a separate pass (its events add ~0.1 ms per call)
-    h.set_timing(True)
-    nph = min(steps, 10)
-    for _ in range(nph):
-        rlu.factor(A, k, l, seed=sseed, handle=h, out=out, stream=stream)
-    torch.cuda.synchronize()
-    phases = [h.phase_times(back) for back in range(nph)]
-    ph = {key: float(np.mean([p[key] for p in phases])) for key in phases[0]}
-    ph["sketch_gemm"] = sketch_timed  # the timed region's own measurement
-    h.set_timing(False)
-    s_a = 4.0 if prec == "fp32" else 8.0
-    peak = PEAK["f32"] if prec == "fp32" else PEAK["f64"]
-    works = phase_work(m, n, k, l, s_a, s_a)
-    res = {
-        "value": steps / wall, "ms_per_step": wall * 1e3 / steps,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "mean": float(lat.mean())},
-        "phase_ms": ph,
-        "kernels": kernel_table(ph, works, peak),
-        "step_roofline": step_roofline(works, peak, wall * 1e3 / steps),
-        "info": out.info.cpu().tolist(),
-    }
-    if check:
-        res["rel_residual"] = power_residual(A.double() if prec == "fp32" else A,
-                                             out.L.double(), out.U.double(), out.p, out.q)
-        log(f"{name}: relative residual {res['rel_residual']:.3e}")
-    return res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works)
-
-
-def timed_calls(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_iters=0):
-    h = rlu.Handle(0)
-    h.set_timing(2)  # one event pair per call in the timed region (the sketch product)
+    h.set_timing(3)
     st = torch.cuda.current_stream()
     out = None
     for _ in range(warmup):
-        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st,
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
                          power_iters=power_iters)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         evs[i][0].record(st)
-        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st,
+        out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
                          power_iters=power_iters)
         evs[i][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     lat = np.array([a.elapsed_time(b) for a, b in evs])
-    sk = float(np.mean([h.phase_times(b)["sketch_gemm"] for b in range(steps)]))
+    live = [h.phase_times(b) for b in range(steps)]
+    sketch = [p["sketch_gemm"] for p in live]
+    panels = [p.get("panel_lu_kernel", []) for p in live]
     h.set_timing(True)  # every phase, in a pass after the timed region
-    nph = min(steps, 5)
-    for _ in range(nph):
+    for _ in range(phase_calls):
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
                          power_iters=power_iters)
     torch.cuda.synchronize()
-    ph = [h.phase_times(b) for b in range(nph)]
-    ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0]}
-    ph["sketch_gemm"] = sk
-    return out, steps / wall, wall * 1e3 / steps, lat, ph
+    ph = [h.phase_times(b) for b in range(phase_calls)]
+    ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0] if key != "panel_lu_kernel"}
+    ph["sketch_gemm"] = float(np.mean(sketch))   # the timed region's own measurement
+    kern = {"sketch_ms": float(np.mean(sketch)),
+            "panel_ms_per_launch": float(np.mean([x for p in panels for x in p])) if panels[0] else 0.0,
+            "panel_launches_per_call": len(panels[0]),
+            "panel_ms_per_call": float(np.mean([sum(p) for p in panels]))}
+    h.close()
+    return out, steps / wall, wall * 1e3 / steps, lat, ph, kern
+
+
+def dominant_roofline(m, n, k, l, works, ph, kern, kernel_names, traffic):
+    """The roofline object of the kernel that takes the most time per call:
+    the pivoted-LU kernel (all its launches of Steps 3 and 6), the sketch
+    product or the projection product."""
+    panel_fl = works["panel_lu_y"][0] + works["panel_lu_bt"][0]
+    panel_by = works["panel_lu_y"][1] + works["panel_lu_bt"][1]
+    cand = {"panel_lu_kernel": kern["panel_ms_per_call"], "sketch_gemm": kern["sketch_ms"],
+            "project_gemm": ph.get("project_gemm", 0.0)}
+    dom = max(cand, key=cand.get)
+    if dom == "panel_lu_kernel":
+        nl = max(1, kern["panel_launches_per_call"])
+        t = kern["panel_ms_per_launch"] * 1e-3
+        fl, by = panel_fl / nl, panel_by / nl
+        steps = l + k
+        roof = {"bound": "alu", "achieved": fl / t / 1e12, "peak": PEAK["f64"] / 1e12,
+                "unit": "TFLOP/s", "frac": fl / t / PEAK["f64"],
+                "traffic": traffic.get("panel_lu_kernel"),
+                "kernel": kernel_names["panel_lu_kernel"],
+                "launches_per_call": nl, "ms_per_launch": kern["panel_ms_per_launch"],
+                "us_per_pivot_step": kern["panel_ms_per_call"] * 1e3 / steps,
+                "pivot_steps_per_call": steps,
+                "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by}
+    else:
+        fl, by, pk = works[dom]
+        t = cand[dom] * 1e-3
+        hbm = by / PEAK["hbm"] >= fl / PEAK[pk]
+        roof = ({"bound": "hbm", "achieved": by / t / 1e9, "peak": PEAK["hbm"] / 1e9,
+                 "unit": "GB/s", "frac": by / t / PEAK["hbm"]} if hbm else
+                {"bound": "mfma", "achieved": fl / t / 1e12, "peak": PEAK[pk] / 1e12,
+                 "unit": "TFLOP/s", "frac": fl / t / PEAK[pk]})
+        roof.update({"traffic": traffic.get(dom), "kernel": kernel_names[dom],
+                     "launches_per_call": 1, "ms_per_launch": cand[dom],
+                     "algorithmic_flops_per_launch": fl, "algorithmic_bytes_per_launch": by})
+    roof["per_call_ms"] = {key: v for key, v in cand.items()}
+    return roof
+
+
+KERNEL_NAMES = {
+    "fp64": {"panel_lu_kernel": "panel_lu_kernel (partial-pivot LU of Y, Step 3, and of B^T, "
+                                "Step 6; one persistent launch per column block)",
+             "sketch_gemm": "gemm_kernel, Y = A G (Step 2), FP64 MFMA 16x16x4",
+             "project_gemm": "gemm_kernel, C = Lv^T A (Step 5), FP64 MFMA 16x16x4"},
+    "fp32": {"panel_lu_kernel": "panel_lu_kernel (partial-pivot LU of Y, Step 3, and of B^T, "
+                                "Step 6; one persistent launch per column block)",
+             "sketch_gemm": "gemm_kernel, Y = A G (Step 2), FP32 MFMA 16x16x4",
+             "project_gemm": "gemm_kernel, C = Lv^T A (Step 5), FP32 MFMA 16x16x4"},
+    "bf16": {"panel_lu_kernel": "panel_lu_kernel (partial-pivot LU of Y, Step 3, and of B^T, "
+                                "Step 6; one persistent launch per column block)",
+             "sketch_gemm": "gemm_lp2_kernel, Y = A G (Step 2), BF16 MFMA 16x16x32, FP32 A",
+             "project_gemm": "gemm_lp2_kernel, C = Lv^T A (Step 5), BF16 MFMA 16x16x32, "
+                             "FP64 Lv as a hi + lo pair"},
+}
+SRC = os.path.join(ROOT, "paper_1310_7202_amd", "csrc")
+
+
+def measured_traffic(workload, prod):
+    """HBM bytes per launch from the committed counter summaries of this
+    workload (None where none was taken on the current kernel source)."""
+    out = {"panel_lu_kernel": traffic_from_profiles(f"traffic_panel_lu_{workload}.md",
+                                                    os.path.join(SRC, "panel_lu.hip"))}
+    gsrc = os.path.join(SRC, "gemm_lp.hip" if prod in ("bf16", "fp16") else "gemm.hip")
+    out["sketch_gemm"] = traffic_from_profiles(f"traffic_sketch_gemm_{workload}.md", gsrc)
+    out["project_gemm"] = traffic_from_profiles(f"traffic_project_gemm_{workload}.md", gsrc)
+    return out
+
+
+def measure(rlu, torch, np, A, k, l, sseed, prec, steps, warmup, workload, check_A=None,
+            power_iters=0):
+    """One configuration: timed calls, phase table, step roofline, the
+    dominant kernel's roofline and (with check_A) the relative residual."""
+    m, n = A.shape
+    precision = {"fp64": rlu.PREC_FP64, "fp32": rlu.PREC_FP32, "bf16": rlu.PREC_MIXED_BF16,
+                 "fp16": rlu.PREC_MIXED_FP16}[prec]
+    out, v, ms, lat, ph, kern = timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps,
+                                             warmup, power_iters)
+    s_a = 8.0 if prec == "fp64" else 4.0
+    works = phase_work(m, n, k, l, s_a, s_a, prec)
+    res = {"value": v, "unit": "factorizations/s", "ms_per_step": ms,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                          "p99": float(np.percentile(lat, 99)), "mean": float(lat.mean())},
+           "phase_ms": ph, "kernels": kernel_table(ph, works),
+           "step_roofline": step_roofline(works, ms),
+           "roofline": dominant_roofline(m, n, k, l, works, ph, kern,
+                                         KERNEL_NAMES["bf16" if prec == "fp16" else prec],
+                                         measured_traffic(workload, prec)),
+           "info": out.info.cpu().tolist()}
+    if check_A is not None:
+        res["rel_residual"] = power_residual(check_A, out.L, out.U, out.p, out.q)
+    return res, out
 
 
 def run_small(rlu, torch, np, calls=1000, warm=50):
@@ -368,58 +452,7 @@ def run_lstsq(rlu, torch, np, A, f, k, steps=20):
     return res
 
 
-def run_mixed(rlu, torch, np, steps):
-    import workloads
-
-    name, m, n, k, l, dseed, sseed, desc = MIXED
-    log(f"generating {name}")
-    A64 = workloads.spectral_matrix_torch(m, n, workloads.inv_square(min(m, n)), dseed,
-                                          device="cuda", dtype=torch.float64)
-    A64 = A64.t().contiguous().t()
-    A32 = A64.float().t().contiguous().t()
-    torch.cuda.synchronize()
-    o16, v16, ms16, lat16, ph16 = timed_calls(rlu, torch, np, A32, k, l, sseed,
-                                              rlu.PREC_MIXED_BF16, steps, 2)
-    r16 = power_residual(A64, o16.L.double(), o16.U.double(), o16.p, o16.q)
-    log(f"mixed bf16: {v16:.1f}/s residual {r16:.3e}")
-    del o16
-    o64, v64, ms64, lat64, ph64 = timed_calls(rlu, torch, np, A64, k, l, sseed,
-                                              rlu.PREC_FP64, max(3, steps // 2), 1)
-    r64 = power_residual(A64, o64.L, o64.U, o64.p, o64.q)
-    log(f"fp64 path: {v64:.1f}/s residual {r64:.3e}")
-    info64 = o64.info.cpu().tolist()
-    del o64
-    works16 = phase_work(m, n, k, l, 4.0, 4.0)
-    works64 = phase_work(m, n, k, l, 8.0, 8.0)
-    f_sk, b_sk = works16["sketch_gemm"]
-    t_sk = ph16["sketch_gemm"] * 1e-3
-    hbm_bound = b_sk / PEAK["hbm"] >= f_sk / PEAK["bf16"]
-    roof = ({"bound": "hbm", "achieved": b_sk / t_sk / 1e9, "peak": PEAK["hbm"] / 1e9,
-             "unit": "GB/s", "frac": b_sk / t_sk / PEAK["hbm"]} if hbm_bound else
-            {"bound": "mfma", "achieved": f_sk / t_sk / 1e12, "peak": PEAK["bf16"] / 1e12,
-             "unit": "TFLOP/s", "frac": f_sk / t_sk / PEAK["bf16"]})
-    roof.update({"traffic": None, "kernel": "sketch GEMM (Step 2), BF16 MFMA 16x16x32, FP32 A",
-                 "algorithmic_flops_per_launch": f_sk, "algorithmic_bytes_per_launch": b_sk})
-    del A32, A64
-    torch.cuda.empty_cache()
-    return {
-        "workload": desc, "value": v16, "unit": "factorizations/s", "ms_per_step": ms16,
-        "latency_ms": {"p50": float(np.percentile(lat16, 50)),
-                       "p99": float(np.percentile(lat16, 99))},
-        "phase_ms": ph16,
-        "kernels": kernel_table(ph16, works16, PEAK["bf16"]),
-        "step_roofline": step_roofline(works16, PEAK["bf16"], ms16),
-        "roofline": roof,
-        "rel_residual": r16,
-        "fp64_path": {"value": v64, "ms_per_step": ms64, "rel_residual": r64, "phase_ms": ph64,
-                      "kernels": kernel_table(ph64, works64, PEAK["f64"]), "info": info64},
-        "speedup_vs_fp64": v16 / v64,
-        "residual_excess_vs_fp64": r16 - r64,
-        "equal_error": bool(r16 <= r64 + 1e-3),
-    }
-
-
-SERVE = ("serve", 64, 105, 7206,
+SERVE = ("serve", 256, 105, 7206,
          "request stream: m log-uniform [512, 32768], n log-uniform [512, 8192], "
          "k ~ U{16..256}, l = k + 10, A = U_R diag(exp(-i/k)) V_R^T with R = min(m, n, 24 k), "
          "FP32 storage, BF16 products with FP32 accumulation; Poisson arrivals at 0.7 x the "
@@ -447,7 +480,7 @@ def make_serve_pool(torch, count, seed):
     return pool
 
 
-def run_serve(rlu, torch, np, n_req=2048, warm=256):
+def run_serve(rlu, torch, np, n_req=4096, warm=256):
     name, pool_n, dseed, sseed, desc = SERVE
     log(f"generating serving pool of {pool_n} matrices")
     pool = make_serve_pool(torch, pool_n, dseed)
@@ -506,6 +539,7 @@ def run_serve(rlu, torch, np, n_req=2048, warm=256):
                 time.sleep(min(wait, 1e-3))
     span = max(done_t) - arrive[warm] if done_t else float("nan")
     srv.close()
+    del srv
     lat = np.array(lat)
     fp = [rlu.serve_footprint(A.shape[0], A.shape[1], k, l, rlu.F32, rlu.PREC_MIXED_BF16)
           for A, k, l in pool]
@@ -567,10 +601,10 @@ def run_batch(rlu, torch, np, steps, warmup):
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
     dims = [(m, n, r, r + 8) for (m, n, r, s) in shapes]
-    works = sum_works(dims, 4.0, 4.0)
+    works = sum_works(dims, 4.0, 4.0, "fp32")
     ms = wall * 1e3 / steps
-    # dominant kernel of the batch: the grouped sketch GEMM
-    f_sk, b_sk = works["sketch_gemm"]
+    # the grouped sketch GEMM of the batch
+    f_sk, b_sk, _ = works["sketch_gemm"]
     t_sk = ph["sketch_gemm"] * 1e-3
     hbm_bound = b_sk / PEAK["hbm"] >= f_sk / PEAK["f32"]
     roof = ({"bound": "hbm", "achieved": b_sk / t_sk / 1e9, "peak": PEAK["hbm"] / 1e9,
@@ -584,30 +618,105 @@ def run_batch(rlu, torch, np, steps, warmup):
         "ms_per_call": ms, "steps": steps,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "phase_ms_eager": ph,
-        "kernels": kernel_table(ph, works, PEAK["f32"]),
-        "step_roofline": step_roofline(works, PEAK["f32"], ms),
-        "roofline": roof,
+        "kernels": kernel_table(ph, works),
+        "step_roofline": step_roofline(works, ms),
+        "roofline_sketch": roof,
         "sequential_rlu_factor": {"factorizations_per_s": count / seq, "ms_total": seq * 1e3},
         "exchange_failures": int((infos[:, 2] != 0).sum()),
         "graph": "one captured HIP graph per batch, replayed",
     }
 
 
+def make_mixed_input(torch, kind="spectral"):
+    """The 16384 x 16384 configuration: A (FP64) = U diag(i^-2) V^T with Haar
+    U, V generated on the device, and its FP32 copy (the stored input of the
+    mixed form); both column-major."""
+    import workloads
+
+    name, m, n, k, l, dseed, sseed, desc = MIXED
+    if kind == "gaussian":
+        g = torch.Generator(device="cuda")
+        g.manual_seed(dseed)
+        A64 = torch.randn(n, m, generator=g, device="cuda", dtype=torch.float64).t()
+    else:
+        A64 = workloads.spectral_matrix_torch(m, n, workloads.inv_square(min(m, n)), dseed,
+                                              device="cuda", dtype=torch.float64)
+        A64 = A64.t().contiguous().t()
+    A32 = A64.float().t().contiguous().t()
+    torch.cuda.synchronize()
+    return A64, A32, k, l, sseed
+
+
+def run_exp8192_form(rlu, torch, np, steps, warmup, forms, input_kind, check, cpu_s):
+    """The 8192 x 8192 FP64 configuration, with its FP32 path, one power
+    iteration (Section 5.2) and least squares on its factors (Algorithm 4.3)
+    when asked, the oracle timed beside it and a full-size parity check."""
+    name = "exp8192"
+    log(f"generating {WORKLOADS[name][8]}")
+    A, k, l, sseed = make_input(name, torch, input_kind)
+    torch.cuda.synchronize()
+    res, out = measure(rlu, torch, np, A, k, l, sseed, "fp64", steps, warmup, name,
+                       A if check else None)
+    res["workload"] = WORKLOADS[name][8]
+    log(f"exp8192 fp64: {res['value']:.1f}/s, residual {res.get('rel_residual')}")
+    if "fp32" in forms:
+        A32 = A.float().t().contiguous().t()
+        r32, o32 = measure(rlu, torch, np, A32, k, l, sseed, "fp32", max(5, steps // 2), 3,
+                           name + "_fp32", A if check else None)
+        r32["workload"] = WORKLOADS["exp8192_fp32"][8]
+        r32["speedup_vs_fp64"] = r32["value"] / res["value"]
+        res["fp32"] = r32
+        log(f"exp8192 fp32: {r32['value']:.1f}/s, residual {r32.get('rel_residual')}")
+        del A32, o32
+    if "power" in forms:
+        rp, op = measure(rlu, torch, np, A, k, l, sseed, "fp64", max(5, steps // 3), 2,
+                         name + "_q1", A if check else None, power_iters=1)
+        rp["workload"] = WORKLOADS[name][8] + ", q = 1 power iteration (Section 5.2)"
+        r0 = res.get("rel_residual")
+        rp["error_ratio_vs_q0"] = rp["rel_residual"] / r0 if (r0 and check) else None
+        res["power_q1"] = rp
+        log(f"exp8192 q=1: {rp['value']:.1f}/s, residual {rp.get('rel_residual')}")
+        del op
+    if "lstsq" in forms:
+        res["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
+    if cpu_s > 0:
+        A_host = A.cpu().numpy()
+        base, o, G = cpu_baseline(A_host, k, l, sseed, cpu_s, one_thread=False)
+        res["cpu_baseline"] = base
+        L, U = out.L.double().cpu().numpy(), out.U.double().cpu().numpy()
+        p, q = out.p.cpu().numpy(), out.q.cpu().numpy()
+        Lu = np.empty_like(L); Lu[p] = L
+        Lo = np.empty_like(o["L"]); Lo[o["p"]] = o["L"]
+        Uu = np.empty_like(U); Uu[:, q] = U
+        Uo = np.empty_like(o["U"]); Uo[:, o["q"]] = o["U"]
+        res["max_rel_diff_vs_oracle"] = {
+            "L_unpermuted": float(np.abs(Lu - Lo).max() / np.abs(Lo).max()),
+            "U_unpermuted": float(np.abs(Uu - Uo).max() / np.abs(Uo).max()),
+            "q_equal": bool(np.array_equal(q, o["q"])), "p_equal": bool(np.array_equal(p, o["p"]))}
+        del A_host, o
+    del A, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="exp8192", choices=sorted(WORKLOADS))
-    ap.add_argument("--forms", default="fp32,power,lstsq,small,batch,mixed,serve",
-                    help="extra measurements in the same line: comma list of fp32, power, lstsq, small, batch, "
-                         "mixed, serve, or none")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="mixed16384",
+                    choices=["mixed16384"] + sorted(WORKLOADS))
+    ap.add_argument("--forms", default="exp8192,fp32,power,lstsq,small,batch,serve",
+                    help="extra measurements in the same line: comma list of exp8192, fp32, "
+                         "power, lstsq (the last three with exp8192), small, batch, serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
     ap.add_argument("--no-check", action="store_true",
-                    help="skip the residual check after the timed steps")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+                    help="skip the residual checks after the timed steps")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=0,
+                    help="timed calls of the FP64 comparison path (0: steps / 2, at least 3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy a 256 MiB buffer once (a plain copy "
                          "kernel of known traffic, to scale hardware byte counters)")
@@ -632,21 +741,47 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
 
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    check = not args.no_check
     name = args.workload
-    res, A, out, (m, n, k, l, sseed, prec, s_a, peak, works) = run_single(
-        rlu, torch, np, name, args.steps, args.warmup, args.input, not args.no_check)
-
-    flops_sketch = works["sketch_gemm"][0]
-    t_sketch = res["phase_ms"]["sketch_gemm"] * 1e-3
-    achieved = flops_sketch / t_sketch
-    kernel_src = os.path.join(ROOT, "paper_1310_7202_amd", "csrc", "gemm.hip")
-    roofline = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": traffic_from_profiles(kernel_src) if name == "exp8192" else None,
-                "kernel": "sketch GEMM Y = A G (Step 2), "
-                          + ("FP32" if prec == "fp32" else "FP64") + " MFMA 16x16x4",
-                "algorithmic_flops_per_launch": flops_sketch,
-                "algorithmic_bytes_per_launch": works["sketch_gemm"][1]}
+    if name == "mixed16384":
+        _, m, n, k, l, dseed, sseed, desc = MIXED
+        log(f"generating {desc}")
+        A64, A32, k, l, sseed = make_mixed_input(torch, args.input)
+        log("input ready")
+        head, o16 = measure(rlu, torch, np, A32, k, l, sseed, "bf16", args.steps, args.warmup,
+                            name, A64 if check else None)
+        log(f"mixed bf16: {head['value']:.1f}/s ({head['ms_per_step']:.2f} ms), residual "
+            f"{head.get('rel_residual')}")
+        del o16
+        fsteps = args.fp64_steps or max(3, args.steps // 2)
+        f64, o64 = measure(rlu, torch, np, A64, k, l, sseed, "fp64", fsteps, 1, name + "_fp64",
+                           A64 if check else None)
+        log(f"fp64 path: {f64['value']:.1f}/s ({f64['ms_per_step']:.2f} ms), residual "
+            f"{f64.get('rel_residual')}")
+        del o64
+        dtype = "bf16"
+        config = {"workload": desc, "m": m, "n": n, "k": k, "l": l,
+                  "precision": "bf16 products (FP32 accumulation), FP64 pivoted LUs and Gram inverse",
+                  "sketch": "Philox4x32-10 Gaussian on device", "input": args.input}
+        comparison = {"fp64_path": f64, "speedup_vs_fp64": head["value"] / f64["value"]}
+        if check:
+            comparison["residual_excess_vs_fp64"] = head["rel_residual"] - f64["rel_residual"]
+            comparison["equal_error"] = bool(head["rel_residual"] <= f64["rel_residual"] + 1e-3)
+        A_check = A64
+    else:
+        m, n, k, l, _, _, sseed, prec, desc = WORKLOADS[name]
+        log(f"generating {desc}")
+        A, k, l, sseed = make_input(name, torch, args.input)
+        torch.cuda.synchronize()
+        head, oh = measure(rlu, torch, np, A, k, l, sseed, prec, args.steps, args.warmup, name,
+                           (A.double() if prec == "fp32" else A) if check else None)
+        del oh
+        dtype = "f32" if prec == "fp32" else "f64"
+        config = {"workload": desc, "m": m, "n": n, "k": k, "l": l, "precision": prec,
+                  "sketch": "Philox4x32-10 Gaussian on device", "input": args.input}
+        comparison = {}
+        A_check = A.double() if prec == "fp32" else A
 
     if args.calibrate_copy:
         src = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -657,88 +792,46 @@ def main():
         log("copy calibration: 256 MiB read + 256 MiB written")
         del src, dst
 
-    flops_total = sum(v[0] for v in works.values())
+    works_total = head["kernels"]
     result = {
         "metric": METRIC,
-        "value": res["value"],
+        "value": head["value"],
         "unit": "factorizations/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": res["ms_per_step"],
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": WORKLOADS[name][8], "m": m, "n": n, "k": k, "l": l,
-                   "precision": prec, "sketch": "Philox4x32-10 Gaussian on device",
-                   "input": args.input},
-        "latency_ms": res["latency_ms"],
-        "phase_ms": res["phase_ms"],
-        "tflops_effective": flops_total / (res["ms_per_step"] * 1e-3) / 1e12,
-        "roofline": roofline,
-        "kernels": res["kernels"],
-        "step_roofline": res["step_roofline"],
-        "check": {"rel_residual": res.get("rel_residual"), "info": res["info"]},
+        "dtype": dtype, "data": "synthetic",
+        "config": config,
+        "latency_ms": head["latency_ms"],
+        "roofline": head["roofline"],
+        "phase_ms": head["phase_ms"],
+        "kernels": works_total,
+        "step_roofline": head["step_roofline"],
+        "check": {"rel_residual": head.get("rel_residual"), "info": head["info"]},
     }
+    result.update(comparison)
 
-    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    if not args.no_cpu_baseline:
+        A_host = A_check.cpu().numpy()
+        base, _, _ = cpu_baseline(A_host, k, l, sseed, args.cpu_seconds)
+        result["cpu_baseline"] = base
+        del A_host
+    else:
+        result["cpu_baseline"] = None
+    del A_check
+    if name == "mixed16384":
+        del A64, A32
+    else:
+        del A
+    torch.cuda.empty_cache()
+
     result["forms"] = {}
-    if "fp32" in forms and name == "exp8192":
-        A32 = A.float()
-        A32 = A32.t().contiguous().t()
-        h32 = rlu.Handle(0)
-        h32.set_timing(2)
-        st = torch.cuda.current_stream()
-        o32 = None
-        for _ in range(3):
-            o32 = rlu.factor(A32, k, l, seed=sseed, handle=h32, stream=st, out=o32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        n32 = max(5, args.steps // 2)
-        for _ in range(n32):
-            o32 = rlu.factor(A32, k, l, seed=sseed, handle=h32, stream=st, out=o32)
-        torch.cuda.synchronize()
-        w32 = time.perf_counter() - t0
-        sk32 = float(np.mean([h32.phase_times(b)["sketch_gemm"] for b in range(n32)]))
-        h32.set_timing(True)  # every phase, in a pass after the timed region
-        for _ in range(5):
-            o32 = rlu.factor(A32, k, l, seed=sseed, handle=h32, stream=st, out=o32)
-        torch.cuda.synchronize()
-        ph32 = [h32.phase_times(b) for b in range(5)]
-        ph32 = {key: float(np.mean([p[key] for p in ph32])) for key in ph32[0]}
-        ph32["sketch_gemm"] = sk32
-        works32 = phase_work(m, n, k, l, 4.0, 4.0)
-        r32 = power_residual(A, o32.L.double(), o32.U.double(), o32.p, o32.q)
-        result["forms"]["fp32"] = {
-            "workload": WORKLOADS["exp8192_fp32"][8], "value": n32 / w32,
-            "unit": "factorizations/s", "ms_per_step": w32 * 1e3 / n32, "phase_ms": ph32,
-            "kernels": kernel_table(ph32, works32, PEAK["f32"]),
-            "step_roofline": step_roofline(works32, PEAK["f32"], w32 * 1e3 / n32),
-            "rel_residual": r32,
-            "rel_residual_fp64_path": res.get("rel_residual"),
-            "speedup_vs_fp64": (n32 / w32) / res["value"]}
-        log(f"fp32 form: {n32 / w32:.1f}/s residual {r32:.3e}")
-        del A32, o32
-    if "power" in forms and name == "exp8192":
-        # Section 5.2: one power iteration, Y = (A A^T) A G with the LU
-        # normalization, on the same matrix and sketch seed
-        outp, vp, msp, latp, php = timed_calls(rlu, torch, np, A, k, l, sseed, None,
-                                               max(5, args.steps // 3), 2, power_iters=1)
-        rp = power_residual(A, outp.L, outp.U, outp.p, outp.q)
-        r0 = res.get("rel_residual")
-        result["forms"]["power_q1"] = {
-            "workload": WORKLOADS["exp8192"][8] + ", q = 1 power iteration",
-            "value": vp, "unit": "factorizations/s", "ms_per_step": msp,
-            "latency_ms": {"p50": float(np.percentile(latp, 50)),
-                           "p99": float(np.percentile(latp, 99))},
-            "phase_ms": php, "rel_residual": rp, "rel_residual_q0": r0,
-            "error_ratio_vs_q0": rp / r0 if r0 else None,
-            "info": outp.info.cpu().tolist()}
-        log(f"power form: {vp:.1f}/s ({msp:.2f} ms), residual {rp:.3e} against {r0}")
-        del outp
+    if "exp8192" in forms and name == "mixed16384":
+        result["forms"]["exp8192"] = run_exp8192_form(
+            rlu, torch, np, max(5, args.steps), 2, forms, args.input, check,
+            0.0 if args.no_cpu_baseline else args.cpu_seconds)
     if "small" in forms:
         result["forms"]["small512"] = run_small(rlu, torch, np)
-    if "lstsq" in forms and name == "exp8192":
-        result["forms"]["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
-    if "mixed" in forms:
-        result["forms"]["mixed16384"] = run_mixed(rlu, torch, np, 8)
     if "batch" in forms:
         result["forms"]["batch256"] = run_batch(rlu, torch, np, max(5, args.steps // 2), 2)
         log(f"batch form: {result['forms']['batch256']['value']:.0f} factorizations/s")
@@ -747,25 +840,7 @@ def main():
         sv = result["forms"]["serve"]
         log(f"serve form: {sv['value']:.0f} requests/s, p50 {sv['latency_ms']['p50']:.2f} ms, "
             f"p99 {sv['latency_ms']['p99']:.2f} ms")
-
-    if not args.no_cpu_baseline:
-        A_host = A.double().cpu().numpy() if prec == "fp32" else A.cpu().numpy()
-        base, o, G = cpu_baseline(A_host, k, l, sseed, args.cpu_seconds)
-        result["cpu_baseline"] = base
-        # parity at full size: same G up to libm rounding on the two sides
-        L, U = out.L.double().cpu().numpy(), out.U.double().cpu().numpy()
-        p, q = out.p.cpu().numpy(), out.q.cpu().numpy()
-        Lu = np.empty_like(L); Lu[p] = L
-        Lo = np.empty_like(o["L"]); Lo[o["p"]] = o["L"]
-        Uu = np.empty_like(U); Uu[:, q] = U
-        Uo = np.empty_like(o["U"]); Uo[:, o["q"]] = o["U"]
-        result["check"]["max_rel_diff_vs_oracle"] = {
-            "L_unpermuted": float(np.abs(Lu - Lo).max() / np.abs(Lo).max()),
-            "U_unpermuted": float(np.abs(Uu - Uo).max() / np.abs(Uo).max()),
-            "q_equal": bool(np.array_equal(q, o["q"])),
-            "p_equal": bool(np.array_equal(p, o["p"]))}
-    else:
-        result["cpu_baseline"] = None
+    rlu.close_default_handles()
     print(json.dumps(result), flush=True)
 
 

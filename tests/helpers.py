@@ -52,3 +52,19 @@ def rel_maxdiff(a: np.ndarray, b: np.ndarray) -> float:
     if den == 0:
         return float(np.abs(a - b).max())
     return float(np.abs(a - b).max() / den)
+
+
+def power_references(orl, A, k, l, G, q):
+    """Oracle results for an FP64 comparison of the power scheme (Section
+    5.2): the normalized reading, which the element-by-element rule compares
+    with, and the plain product (A A^T)^q A G of the definition, with the
+    distance d between the two readings' unpermuted L (the plain product's
+    own rounding, which grows like (sigma_1 / sigma_k)^(2q+1) u).  A correct
+    normalized result is held to 1e-10 of the normalized reading and to
+    1e-10 + 2 d of the definition."""
+    o_n = orl.randomized_lu(A, k, l, G, q=q, scheme="normalized")
+    if q > orl.PLAIN_POWER_MAX_Q:
+        return o_n, o_n, 0.0
+    o_p = orl.randomized_lu(A, k, l, G, q=q, scheme="plain")
+    d = rel_maxdiff(unpermute_rows(o_p["L"], o_p["p"]), unpermute_rows(o_n["L"], o_n["p"]))
+    return o_n, o_p, d

@@ -14,7 +14,8 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.helpers import (ensure_built, rel_maxdiff, to_dev_colmajor, to_host, unpermute_rows)
+from tests.helpers import (ensure_built, power_references, rel_maxdiff, to_dev_colmajor, to_host,
+                           unpermute_rows)
 from oracle import rlu as orl
 import workloads
 
@@ -302,9 +303,14 @@ def test_batched_power_iterations(rlu, q):
     singles = [rlu.factor(Ad, k, l, G=Gd, power_iters=q) for Ad, k, l, _, Gd in items]
     torch.cuda.synchronize()
     for (A, k, l, G), fb, fs in zip(probs, outs, singles):
-        o = orl.randomized_lu(A, k, l, G, q=q)
+        o, o_plain, d = power_references(orl, A, k, l, G, q)
         _check_f64(A, k, l, G, to_host(fb.L), to_host(fb.U), to_host(fb.p), to_host(fb.q),
                    to_host(fb.info), o=o, label=f"{A.shape} k={k} q={q}")
+        # and the definition (A A^T)^q A G within the two readings' distance
+        e = rel_maxdiff(unpermute_rows(to_host(fb.L), to_host(fb.p)),
+                        unpermute_rows(o_plain["L"], o_plain["p"]))
+        print(f"  {A.shape} k={k}: vs plain {e:.2e} (readings differ by {d:.2e})", flush=True)
+        assert e < TOL + 2 * d
         np.testing.assert_array_equal(to_host(fb.q), to_host(fs.q))
         assert rel_maxdiff(to_host(fb.U), to_host(fs.U)) < TOL
     outs = batch.run()  # graph replay

@@ -15,7 +15,8 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from tests.helpers import (ensure_built, rel_maxdiff, to_dev_colmajor, to_host, unpermute_cols,
+from tests.helpers import (ensure_built, power_references, rel_maxdiff, to_dev_colmajor, to_host,
+                           unpermute_cols,
                            unpermute_rows)
 from oracle import philox, rlu as orl
 import workloads
@@ -40,7 +41,13 @@ def run_and_compare(rlu, A, k, l, G, label="", power=0):
     out = rlu.factor(to_dev_colmajor(A), k, l, G=to_dev_colmajor(G), diagnostics=True,
                      power_iters=power)
     torch.cuda.synchronize()
-    o = orl.randomized_lu(A, k, l, G, q=power)
+    if power == 0:
+        o = orl.randomized_lu(A, k, l, G)
+    else:
+        # the element-by-element rule against the normalized reading of
+        # Section 5.2, and the definition (A A^T)^q A G within the distance
+        # of the two readings (the plain product's own rounding)
+        o, o_plain, d = power_references(orl, A, k, l, G, power)
     info = to_host(out.info)
     assert info[2] == 0, "pivot exchange failed"
     assert (int(info[0]), int(info[1])) == o["info"]
@@ -79,6 +86,10 @@ def run_and_compare(rlu, A, k, l, G, label="", power=0):
     if gy == l and gb == k:
         np.testing.assert_array_equal(p, o["p"])
         assert rel_maxdiff(L, o["L"]) < TOL
+    if power and gb == k:
+        e = rel_maxdiff(unpermute_rows(L, p), unpermute_rows(o_plain["L"], o_plain["p"]))
+        print(f"  vs plain (A A^T)^q A G: {e:.2e} (readings differ by {d:.2e})", flush=True)
+        assert e < TOL + 2 * d
     return out, o
 
 
