@@ -176,6 +176,25 @@ rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
 rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb,
                         const rlu_buffers_t* io, rlu_stream_t stream);
 
+/* rlu_factor for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launch sequence and results as rlu_factor, with its workspace in a
+ * fixed device scratch array of RLU_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every device it runs on until the process ends (located once per
+ * device by rlu_create).  The call allocates nothing and leaves the handle's
+ * own workspace alone; phase timing does not apply.  Problems whose
+ * workspace (rlu_workspace_size) exceeds the scratch return
+ * RLU_ERR_TOO_LARGE before any device work (8192 x 8192 with k = 200, l =
+ * 210 fits; 16384 x 16384 with k = 500 does not).  Every call on a device
+ * shares that device's scratch, which keeps the last call's contents (each
+ * call clears what must start at zero): calls that overlap on one device,
+ * from any handle, thread or stream, race and give undefined results, so
+ * order them (one stream, or events).  RLU_ERR_DEVICE if the scratch could
+ * not be located on the handle's device. */
+#define RLU_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+rlu_status_t rlu_factor_noalloc(rlu_handle_t h, const rlu_problem_t* pb,
+                                const rlu_buffers_t* io, rlu_stream_t stream);
+
 /* Many independent problems (Algorithm 4.1 for each), enqueued on `stream`
  * as one launch per kernel of the method for the whole batch.
  *

@@ -39,7 +39,7 @@ EXPORTED_SYMBOLS = ["rlu_create", "rlu_destroy", "rlu_workspace_size", "rlu_fact
                     "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
                     "rlu_set_timing", "rlu_phase_times", "rlu_check_info",
                     "rlu_status_string", "rlu_version", "rlu_lstsq",
-                    "rlu_lstsq_workspace_size", "rlu_set_exchange_limit"]
+                    "rlu_lstsq_workspace_size", "rlu_set_exchange_limit", "rlu_factor_noalloc"]
 
 
 class RluError(RuntimeError):
@@ -109,6 +109,8 @@ def lib() -> ctypes.CDLL:
         L.rlu_workspace_size.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t)]
         L.rlu_factor.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
                                  ctypes.POINTER(Buffers), ctypes.c_void_p]
+        L.rlu_factor_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem),
+                                         ctypes.POINTER(Buffers), ctypes.c_void_p]
         L.rlu_factor_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(Problem),
                                          ctypes.POINTER(Buffers), ctypes.c_void_p]
         L.rlu_check_info.argtypes = [ctypes.POINTER(ctypes.c_int32)]
@@ -144,7 +146,8 @@ def lib() -> ctypes.CDLL:
                      "rlu_phase_times", "rlu_serve_create", "rlu_serve_submit",
                      "rlu_serve_poll", "rlu_serve_copy", "rlu_serve_release",
                      "rlu_serve_footprint", "rlu_serve_stats", "rlu_serve_destroy",
-                     "rlu_lstsq", "rlu_lstsq_workspace_size", "rlu_set_exchange_limit"):
+                     "rlu_lstsq", "rlu_lstsq_workspace_size", "rlu_set_exchange_limit",
+                     "rlu_factor_noalloc"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib

@@ -26,6 +26,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 
@@ -604,6 +605,35 @@ rlu_status_t lstsq_path(rlu_handle_s* h, const rlu_lstsq_t& ls, hipStream_t s,
 
 }  // namespace
 
+// ----- Device scratch of rlu_factor_noalloc ----------------------------------
+// A file-scope device array that the loader places on every device the
+// library runs on, held until the process ends.  Host code never uses its
+// name as an address: rlu_create looks up each device's copy once, with
+// that device current, and rlu_factor_noalloc passes that address on.
+constexpr size_t kStaticScratchBytes = RLU_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Once per device, with `device` current: the address of its scratch copy.
+void lookup_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) g_scratch_ptr[device] = p;
+}
+
+void* scratch_of(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 using namespace rlu_detail;
 
 extern "C" {
@@ -629,6 +659,7 @@ rlu_status_t rlu_create(rlu_handle_t* out, int device) {
     delete h;
     return RLU_ERR_DEVICE;
   }
+  lookup_scratch(device);  // set-up of rlu_factor_noalloc on this device
   hipSetDevice(prev);
   *out = h;
   return RLU_OK;
@@ -691,6 +722,41 @@ rlu_status_t rlu_factor(rlu_handle_t h, const rlu_problem_t* pb, const rlu_buffe
     else
       st = factor_path<float>(h, *pb, *io, (hipStream_t)stream, L);
   }
+  if (prev != h->device) hipSetDevice(prev);
+  return st;
+}
+
+rlu_status_t rlu_factor_noalloc(rlu_handle_t h, const rlu_problem_t* pb,
+                                const rlu_buffers_t* io, rlu_stream_t stream) {
+  if (!h) return RLU_ERR_INVALID_ARG;
+  rlu_status_t st = validate(pb);
+  if (st != RLU_OK) return st;
+  st = validate_io(pb, io);
+  if (st != RLU_OK) return st;
+  Layout L;
+  if (!plan_layout(*pb, h->cus, L)) return RLU_ERR_UNSUPPORTED;
+  if (L.total > kStaticScratchBytes) return RLU_ERR_TOO_LARGE;
+  void* ws = scratch_of(h->device);
+  if (!ws) return RLU_ERR_DEVICE;
+  int prev = 0;
+  hipGetDevice(&prev);
+  if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RLU_ERR_DEVICE;
+  // the handle's own workspace and timing are left alone: a view of the
+  // handle whose workspace is the device scratch, with timing off
+  void* const ws_own = h->ws;
+  const size_t ws_own_bytes = h->ws_bytes;
+  const bool timing = h->timing;
+  h->ws = ws;
+  h->ws_bytes = kStaticScratchBytes;
+  h->timing = false;
+  h->cur = nullptr;
+  if (pb->precision == RLU_PREC_FP64)
+    st = factor_path<double>(h, *pb, *io, (hipStream_t)stream, L);
+  else
+    st = factor_path<float>(h, *pb, *io, (hipStream_t)stream, L);
+  h->ws = ws_own;
+  h->ws_bytes = ws_own_bytes;
+  h->timing = timing;
   if (prev != h->device) hipSetDevice(prev);
   return st;
 }
