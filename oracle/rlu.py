@@ -84,6 +84,63 @@ def lu_partial_pivot(Y: np.ndarray):
     return LU, ipiv, p, info, {"piv_abs": piv_abs, "gap": gap, "max_abs": ymax}
 
 
+def column_pivoted_qr(Y: np.ndarray):
+    """Householder QR with column pivoting (Businger and Golub), the column
+    choice of the rank-revealing Step 3 (Algorithm 4.1 as listed, with the
+    RRLU of Section 3.1, Theorem 3.1).
+
+    At step j the remaining column whose part on rows j.. has the largest
+    2-norm (lowest current position on ties; norms recomputed at every
+    step) is exchanged into position j, and a Householder reflection zeroes
+    it below the diagonal and is applied to the columns on its right.
+
+    Returns (R, qy, diag): R (w x w upper triangular) with Y[:, qy] = Q R,
+    the column order qy, and per-step diagnostics (largest remaining norm,
+    relative gap to the runner-up, and the largest column norm of Y)."""
+    W = np.array(Y, dtype=np.float64, copy=True)
+    m, w = W.shape
+    if w > m:
+        raise ValueError("column_pivoted_qr expects a tall matrix (m >= w)")
+    qy = np.arange(w, dtype=np.int64)
+    top = np.zeros(w)
+    gap = np.zeros(w)
+    ymax = float(np.max(np.linalg.norm(W, axis=0))) if W.size else 0.0
+    for j in range(w):
+        norms = np.linalg.norm(W[j:, j:], axis=0)
+        c = j + int(np.argmax(norms))
+        top[j] = norms[c - j]
+        if norms.size > 1:
+            second = np.partition(norms, norms.size - 2)[norms.size - 2]
+            gap[j] = (top[j] - second) / top[j] if top[j] > 0 else 0.0
+        else:
+            gap[j] = 1.0
+        if c != j:
+            W[:, [j, c]] = W[:, [c, j]]
+            qy[[j, c]] = qy[[c, j]]
+        x = W[j:, j]
+        nx = np.linalg.norm(x)
+        if nx == 0.0:
+            continue
+        alpha = -nx if x[0] >= 0 else nx
+        v = x.copy()
+        v[0] -= alpha
+        v /= np.linalg.norm(v)
+        W[j:, j:] -= 2.0 * np.outer(v, v @ W[j:, j:])
+    R = np.triu(W[:w, :w])
+    return R, qy, {"piv_abs": top, "gap": gap, "max_abs": ymax}
+
+
+def rrlu(Y: np.ndarray):
+    """The rank-revealing Step 3 of Algorithm 4.1 as listed: P Y Q_y =
+    L_y U_y with the column permutation Q_y of ``column_pivoted_qr`` and
+    the partial-pivot LU (``lu_partial_pivot``) of Y Q_y, all columns
+    factored.  Returns (LU, ipiv, p, info, diag, qy, qdiag) with LU the
+    packed factors of Y[:, qy]."""
+    _, qy, qdiag = column_pivoted_qr(Y)
+    LU, ipiv, p, info, diag = lu_partial_pivot(np.asarray(Y)[:, qy])
+    return LU, ipiv, p, info, diag, qy, qdiag
+
+
 def unit_lower(LU: np.ndarray, k: int) -> np.ndarray:
     """Step 4 of Algorithm 4.1: L_y <- L_y(:, 1:k), the unit-lower part of
     the first k columns of the packed factor."""
@@ -208,14 +265,16 @@ def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
 
 
 def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
-                  scheme: str = "auto") -> dict:
+                  scheme: str = "auto", step3: str = "partial") -> dict:
     """Algorithm 4.1 of the paper, Steps 2-8, for a given Gaussian G (Step 1).
 
     Inputs: A (m x n), k (target rank), l (number of sketch columns,
     k <= l <= min(m, n)), G (n x l) and the number q of power iterations
     of Section 5.2 (0: the plain Step 2).  ``scheme`` picks how the power
     sketch is formed: "plain", "normalized", or "auto" (plain up to
-    PLAIN_POWER_MAX_Q, normalized above).  Returns a dict with the outputs
+    PLAIN_POWER_MAX_Q, normalized above).  ``step3`` is "partial" (the LU
+    with partial pivoting the Remark after Algorithm 4.1 allows) or "rrlu"
+    (the rank-revealing LU of the listing, ``rrlu``).  Returns a dict with the outputs
     L (m x k unit lower trapezoidal), U (k x n upper trapezoidal), p, q and
     the intermediates (Y, packed LU of Y, ipiv, L_y, B, L_b, qpiv, info words
     and pivot diagnostics).
@@ -230,17 +289,25 @@ def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
     make = {"auto": power_sketch, "plain": power_sketch_plain,
             "normalized": power_sketch_normalized}[scheme]
     Y = make(A, G, q)                                  # Step 2 (Section 5.2)
-    return randomized_lu_from_sketch(A, k, Y)
+    return randomized_lu_from_sketch(A, k, Y, step3)
 
 
-def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray) -> dict:
-    """Steps 3-8 of Algorithm 4.1 for a given sketch Y (m x l)."""
+def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray,
+                              step3: str = "partial") -> dict:
+    """Steps 3-8 of Algorithm 4.1 for a given sketch Y (m x l); ``step3`` as
+    in ``randomized_lu``."""
     A = np.asarray(A, dtype=np.float64)
     Y = np.asarray(Y, dtype=np.float64)
     m, n = A.shape
     if Y.shape[0] != m or not (1 <= k <= Y.shape[1] <= min(m, n)):
         raise ValueError("need an m x l sketch with 1 <= k <= l <= min(m, n)")
-    LUy, ipiv, p, info_y, diag_y = lu_partial_pivot(Y)  # Step 3
+    qy, qdiag = None, None
+    if step3 == "rrlu":
+        LUy, ipiv, p, info_y, diag_y, qy, qdiag = rrlu(Y)      # Step 3, P Y Q_y = L_y U_y
+    elif step3 == "partial":
+        LUy, ipiv, p, info_y, diag_y = lu_partial_pivot(Y)     # Step 3 (Remark)
+    else:
+        raise ValueError("step3 must be 'partial' or 'rrlu'")
     Ly = unit_lower(LUy, k)                            # Step 4
     B = pinv_apply(Ly, A[p, :])                        # Step 5
     Lb, Ub, qpiv, q, info_b, diag_b = lu_col_pivot(B)  # Step 6
@@ -252,6 +319,7 @@ def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray) -> dict:
         "Lb": Lb, "Ub": Ub, "qpiv": qpiv,
         "info": (info_y, info_b),
         "diag_y": diag_y, "diag_b": diag_b,
+        "qy": qy, "diag_qy": qdiag,
     }
 
 

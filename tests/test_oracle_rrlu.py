@@ -1,0 +1,175 @@
+"""Pins of the rank-revealing Step 3 (Algorithm 4.1 as listed: RRLU of the
+sketch, Section 3.1, Theorem 3.1): the column choice by column-pivoted QR
+and the pipeline built on it.
+
+  * the column choice equals LAPACK's column-pivoted QR (geqp3) and has
+    its defining property (each pivot is the largest remaining column);
+  * P Y Q_y = L_y U_y satisfies the inequalities of Theorem 3.1 (Pan) for
+    every k: sigma_k >= sigma_min(L11 U11) >= sigma_k / (k(l-k)+1) and
+    sigma_{k+1} <= ||U22|| <= (k(l-k)+1) sigma_{k+1};
+  * an exactly rank-k sketch leaves U22 = 0 and the pipeline exact;
+  * with l = k the choice only reorders the sketch columns, so the
+    residual equals partial pivoting's (the projection of the proof of
+    Theorem 4.1 depends on range(L_y) only); with l > k the error falls,
+    on average over draws, below partial pivoting's, which ignores the
+    extra columns;
+  * the reconstruction is the projection of A onto range(Y Q_y(:, 1:k));
+  * planted mistakes in the column choice fail these pins.
+"""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import rlu
+import workloads
+
+
+def _inputs():
+    return [workloads.spectral_matrix(300, 60, workloads.exp_decay(60, 6.0), 980),
+            workloads.gaussian((200, 40), 981),
+            workloads.spectral_matrix(150, 50, workloads.inv_square(50), 982)]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_column_choice_equals_lapack_geqp3(case):
+    Y = _inputs()[case]
+    R, qy, d = rlu.column_pivoted_qr(Y)
+    Q2, R2, P2 = scipy.linalg.qr(Y, mode="economic", pivoting=True)
+    np.testing.assert_array_equal(qy, P2)
+    np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(R2)), rtol=1e-10, atol=0)
+    # Y Q_y = Q R with orthonormal Q
+    Q = Y[:, qy] @ np.linalg.inv(R)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(Y.shape[1]), atol=1e-8)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_each_pivot_is_the_largest_remaining_column(case):
+    Y = _inputs()[case]
+    R, qy, d = rlu.column_pivoted_qr(Y)
+    w = R.shape[0]
+    for j in range(w):
+        # |R_jj| = largest norm of the remaining parts R(j:, c), c >= j
+        rem = np.linalg.norm(R[j:, j:], axis=0)
+        assert abs(R[j, j]) >= rem.max() * (1 - 1e-12)
+    assert np.all(np.diff(np.abs(np.diag(R))) <= 1e-12 * abs(R[0, 0]))
+
+
+def _rrlu_blocks(Y, k):
+    LU, ipiv, p, info, diag, qy, qd = rlu.rrlu(Y)
+    w = Y.shape[1]
+    L = np.tril(LU[:, :w], -1) + np.eye(LU.shape[0], w)
+    U = np.triu(LU[:w, :w])
+    L11U11 = L[:k, :k] @ U[:k, :k]
+    Yp = Y[np.ix_(p, qy)]
+    U22 = Yp[k:, k:] - L[k:, :k] @ U[:k, k:]     # the Schur complement after k steps
+    return L11U11, U22, Yp, L, U
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_theorem_3_1_inequalities(case):
+    Y = _inputs()[case]
+    w = Y.shape[1]
+    s = np.linalg.svd(Y, compute_uv=False)
+    for k in (1, 3, w // 4, w // 2, w - 1):
+        L11U11, U22, Yp, L, U = _rrlu_blocks(Y, k)
+        c = k * (w - k) + 1
+        smin = np.linalg.svd(L11U11, compute_uv=False)[-1]
+        n22 = np.linalg.norm(U22, 2)
+        assert s[k - 1] * (1 + 1e-10) >= smin >= s[k - 1] / c, (k, s[k - 1], smin)
+        assert s[k] * (1 - 1e-10) <= n22 <= c * s[k], (k, s[k], n22)
+        np.testing.assert_allclose(L @ U, Yp, atol=1e-12 * np.abs(Y).max())
+
+
+def test_exact_rank_k_sketch_leaves_no_schur_complement():
+    X = workloads.gaussian((120, 7), 983)
+    Y = X @ workloads.gaussian((7, 15), 984)
+    _, U22, _, _, _ = _rrlu_blocks(Y, 7)
+    assert np.abs(U22).max() <= 1e-12 * np.abs(Y).max()
+    A = workloads.low_rank_plus_noise(120, 90, 7, 0.0, 985)
+    out = rlu.randomized_lu(A, 7, 15, workloads.gaussian((90, 15), 986), step3="rrlu")
+    assert rlu.relative_residual(A, out) < 1e-12
+
+
+def test_l_equal_k_gives_the_residual_of_partial_pivoting():
+    A = workloads.spectral_matrix(260, 200, workloads.exp_decay(200, 8.0), 987)
+    G = workloads.gaussian((200, 18), 988)
+    a = rlu.randomized_lu(A, 18, 18, G)
+    b = rlu.randomized_lu(A, 18, 18, G, step3="rrlu")
+    ra, rb = rlu.relative_residual(A, a), rlu.relative_residual(A, b)
+    assert abs(ra - rb) <= 1e-10 * ra
+
+
+@pytest.mark.parametrize("l_over_k,bound", [(2, 0.85), (3, 0.75)])
+def test_oversampling_lowers_the_error_with_the_rank_revealing_step(l_over_k, bound):
+    # partial pivoting keeps the first k sketch columns whatever l is; the
+    # column-pivoted choice uses the extra ones.  A greedy choice is not
+    # better on every draw, so the pin is the mean ratio over eight draws
+    # (measured 0.72 at l = 2k and 0.60 at l = 3k), and every error stays
+    # above sigma_{k+1} (Eckart-Young)
+    k = 20
+    ratios = []
+    for seed in range(990, 998):
+        A = workloads.spectral_matrix(400, 300, workloads.exp_decay(300, 6.0), seed)
+        G = workloads.gaussian((300, l_over_k * k), seed + 1)
+        part = rlu.relative_residual(A, rlu.randomized_lu(A, k, l_over_k * k, G))
+        rr = rlu.relative_residual(A, rlu.randomized_lu(A, k, l_over_k * k, G, step3="rrlu"))
+        s = np.linalg.svd(A, compute_uv=False)
+        assert rr >= s[k] / s[0] * (1 - 1e-9)
+        ratios.append(rr / part)
+    assert np.mean(ratios) < bound, ratios
+
+
+def test_reconstruction_is_the_projection_onto_the_chosen_columns():
+    A = workloads.spectral_matrix(150, 120, workloads.exp_decay(120, 7.0), 993)
+    k, l = 10, 16
+    G = workloads.gaussian((120, l), 994)
+    out = rlu.randomized_lu(A, k, l, G, step3="rrlu")
+    Yk = (A @ G)[:, out["qy"][:k]]
+    Qk, _ = np.linalg.qr(Yk)
+    p, q = out["p"], out["q"]
+    LU = np.empty_like(A)
+    LU[np.ix_(p, q)] = out["L"] @ out["U"]
+    np.testing.assert_allclose(LU, Qk @ (Qk.T @ A), atol=1e-10 * np.abs(A).max())
+
+
+def test_structure_with_the_rank_revealing_step():
+    A = workloads.spectral_matrix(90, 140, workloads.exp_decay(90, 5.0), 995)
+    out = rlu.randomized_lu(A, 9, 14, workloads.gaussian((140, 14), 996), step3="rrlu")
+    L, U = out["L"], out["U"]
+    assert np.all(np.diag(L[:9]) == 1.0) and np.all(np.triu(L[:9], 1) == 0.0)
+    assert np.all(np.tril(U, -1) == 0.0)
+    np.testing.assert_array_equal(np.sort(out["p"]), np.arange(90))
+    np.testing.assert_array_equal(np.sort(out["q"]), np.arange(140))
+    np.testing.assert_array_equal(np.sort(out["qy"]), np.arange(14))
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+@pytest.mark.parametrize("variant", ["smallest_norm", "full_column_norms", "no_reflection"])
+def test_planted_column_choice_mistakes(variant, monkeypatch):
+    def broken(Y):
+        W = np.array(Y, float)
+        m, w = W.shape
+        qy = np.arange(w)
+        for j in range(w):
+            norms = np.linalg.norm(W[(0 if variant == "full_column_norms" else j):, j:], axis=0)
+            c = j + int(np.argmin(norms) if variant == "smallest_norm" else np.argmax(norms))
+            W[:, [j, c]] = W[:, [c, j]]
+            qy[[j, c]] = qy[[c, j]]
+            if variant == "no_reflection":
+                continue
+            x = W[j:, j]
+            alpha = -np.linalg.norm(x) if x[0] >= 0 else np.linalg.norm(x)
+            v = x.copy(); v[0] -= alpha; v /= np.linalg.norm(v)
+            W[j:, j:] -= 2.0 * np.outer(v, v @ W[j:, j:])
+        return np.triu(W[:w, :w]), qy, {"piv_abs": np.ones(w), "gap": np.ones(w), "max_abs": 1.0}
+
+    monkeypatch.setattr(rlu, "column_pivoted_qr", broken)
+    assert (_fails(test_column_choice_equals_lapack_geqp3, 0)
+            or _fails(test_each_pivot_is_the_largest_remaining_column, 0))
