@@ -1,5 +1,6 @@
 """Plain FP64 CPU oracle for the randomized LU decomposition (Shabat et al.,
-arXiv 1310.7202, Section 4, Algorithm 4.1).
+arXiv 1310.7202, Section 4: Algorithm 4.1 in ``rlu``, Algorithm 4.4 in
+``fast``).
 
 TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 ``cpu_baseline`` leg of ``bench.py`` may import anything from this package.
@@ -43,6 +44,15 @@ Pinned by (see ``tests/test_oracle_*.py``):
     gated prefix.
   * ``rlu.kappa``              -- closed forms (diagonal, orthogonal, SVD
     construction) and the Gram-route accuracy it predicts.
+  * ``rlu.column_pivoted_qr``, ``rlu.rrlu`` -- the rank-revealing Step 3:
+    LAPACK geqp3's column order, each pivot the largest remaining column,
+    the inequalities of Theorem 3.1, exact rank, the projection identity,
+    the mean error below partial pivoting's when l > k.
+  * ``fast.*`` (Algorithm 4.4) -- the SRFT draws (balanced signs, uniform
+    distinct selection), the Hartley transform against NumPy's FFT, the
+    ID's defining properties and the inequality of its lemma's proof,
+    exact rank, Eckart-Young, Step 6 against NumPy least squares.
+  * ``philox.srft_signs``, ``philox.srft_selection`` -- with the pins above.
   * ``bounds.xi``              -- Table 4.1 of the paper, 9 of 9 rows.
   * ``philox.philox4x32_10``   -- Random123 known-answer vectors.
   * ``philox.gaussian_matrix`` -- Box-Muller closed form on fixed uniforms and

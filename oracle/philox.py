@@ -94,3 +94,48 @@ def gaussian_matrix(n: int, l: int, seed: int) -> np.ndarray:
     flat[0::2] = z0
     flat[1::2] = z1
     return flat[:total].reshape(l, n).T.copy()
+
+
+# ---------------------------------------------------------------------------
+# The draws of the SRFT of Algorithm 4.4 (Section 3.3), R = D F S: the signs
+# of D and the column selection of S, from the same generator and key with
+# the third counter word set apart from Step 1's (which is 0):
+#   * signs: for element i the 128 output bits of the counter
+#     (i div 128, 0, 1, 0); bit t = i mod 128 is bit (t mod 32) of word
+#     (t div 32); d_i = +1 if that bit is 0, -1 if it is 1.
+#   * selection: a partial Fisher-Yates shuffle of idx = 0..n-1: for
+#     j = 0..l-1, with (x1:x0) of the counter (j, 0, 2, 0) as a 64-bit u,
+#     t = j + (u mod (n - j)) and idx[j], idx[t] are exchanged; S selects
+#     the columns idx[0..l-1], in that order (l distinct indices).
+# ---------------------------------------------------------------------------
+
+
+def srft_signs(n: int, seed: int) -> np.ndarray:
+    """d (length n) of D = diag(d), entries +1 / -1."""
+    k0 = np.uint64(seed & 0xFFFFFFFF)
+    k1 = np.uint64((seed >> 32) & 0xFFFFFFFF)
+    blocks = np.arange((n + 127) // 128, dtype=np.uint64)
+    zero = np.zeros_like(blocks)
+    words = philox4x32_10(blocks, zero, zero + np.uint64(1), zero, k0, k1)
+    i = np.arange(n)
+    b, t = i // 128, i % 128
+    w = np.stack(words)[t // 32, b]
+    bit = (w >> (t % 32).astype(np.uint64)) & np.uint64(1)
+    return np.where(bit == 0, 1.0, -1.0)
+
+
+def srft_selection(n: int, l: int, seed: int) -> np.ndarray:
+    """The l distinct column indices of S, in draw order."""
+    if not 0 <= l <= n:
+        raise ValueError("need 0 <= l <= n")
+    k0 = np.uint64(seed & 0xFFFFFFFF)
+    k1 = np.uint64((seed >> 32) & 0xFFFFFFFF)
+    j = np.arange(l, dtype=np.uint64)
+    zero = np.zeros_like(j)
+    x0, x1, _, _ = philox4x32_10(j, zero, zero + np.uint64(2), zero, k0, k1)
+    idx = np.arange(n, dtype=np.int64)
+    for jj in range(l):
+        u = (int(x1[jj]) << 32) | int(x0[jj])
+        t = jj + u % (n - jj)
+        idx[jj], idx[t] = idx[t], idx[jj]
+    return idx[:l].copy()
