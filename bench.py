@@ -247,7 +247,7 @@ def step_roofline(works, ms_per_step):
 
 
 def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_iters=0,
-                 phase_calls=5):
+                 phase_calls=5, rrlu=False):
     """`steps` rlu_factor calls in the timed region (timing mode 3: HIP events
     around the sketch product and around every pivoted-LU kernel launch, on
     the stream they run on), then `phase_calls` calls with every phase timed.
@@ -260,7 +260,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     out = None
     for _ in range(warmup):
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters)
+                         power_iters=power_iters, rrlu=rrlu)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
@@ -269,7 +269,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     for i in range(steps):
         evs[i][0].record(st)
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters)
+                         power_iters=power_iters, rrlu=rrlu)
         evs[i][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -280,7 +280,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     h.set_timing(True)  # every phase, in a pass after the timed region
     for _ in range(phase_calls):
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters)
+                         power_iters=power_iters, rrlu=rrlu)
     torch.cuda.synchronize()
     ph = [h.phase_times(b) for b in range(phase_calls)]
     ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0] if key != "panel_lu_kernel"}
@@ -360,14 +360,14 @@ def measured_traffic(workload, prod):
 
 
 def measure(rlu, torch, np, A, k, l, sseed, prec, steps, warmup, workload, check_A=None,
-            power_iters=0):
+            power_iters=0, rrlu=False):
     """One configuration: timed calls, phase table, step roofline, the
     dominant kernel's roofline and (with check_A) the relative residual."""
     m, n = A.shape
     precision = {"fp64": rlu.PREC_FP64, "fp32": rlu.PREC_FP32, "bf16": rlu.PREC_MIXED_BF16,
                  "fp16": rlu.PREC_MIXED_FP16}[prec]
     out, v, ms, lat, ph, kern = timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps,
-                                             warmup, power_iters)
+                                             warmup, power_iters, rrlu=rrlu)
     s_a = 8.0 if prec == "fp64" else 4.0
     works = phase_work(m, n, k, l, s_a, s_a, prec)
     res = {"value": v, "unit": "factorizations/s", "ms_per_step": ms,
@@ -677,6 +677,29 @@ def run_exp8192_form(rlu, torch, np, steps, warmup, forms, input_kind, check, cp
         res["power_q1"] = rp
         log(f"exp8192 q=1: {rp['value']:.1f}/s, residual {rp.get('rel_residual')}")
         del op
+    if "rrlu" in forms:
+        # Step 3 as Algorithm 4.1 lists it (rank-revealing), at l = k + 10 and
+        # with more oversampling, which only the rank-revealing step uses
+        rr = {}
+        for l2 in (l, k + 40):
+            rq, oq = measure(rlu, torch, np, A, k, l2, sseed, "fp64", max(5, steps // 2), 2,
+                             name + "_rrlu", A if check else None, rrlu=True)
+            rq["workload"] = f"{WORKLOADS[name][8]}, l={l2}, rank-revealing Step 3 (RRLU)"
+            if l2 != l:
+                rp_, op_ = measure(rlu, torch, np, A, k, l2, sseed, "fp64", max(5, steps // 2), 2,
+                                   name, A if check else None)
+                rq["partial_pivoting_same_l"] = {"value": rp_["value"],
+                                                 "ms_per_step": rp_["ms_per_step"],
+                                                 "rel_residual": rp_.get("rel_residual")}
+                del op_
+            else:
+                rq["partial_pivoting_same_l"] = {"value": res["value"],
+                                                 "ms_per_step": res["ms_per_step"],
+                                                 "rel_residual": res.get("rel_residual")}
+            rr[f"l{l2}"] = rq
+            log(f"exp8192 rrlu l={l2}: {rq['value']:.1f}/s, residual {rq.get('rel_residual')}")
+            del oq
+        res["rrlu"] = rr
     if "lstsq" in forms:
         res["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
     if cpu_s > 0:
@@ -706,9 +729,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed16384",
                     choices=["mixed16384"] + sorted(WORKLOADS))
-    ap.add_argument("--forms", default="exp8192,fp32,power,lstsq,small,batch,serve",
+    ap.add_argument("--forms", default="exp8192,fp32,power,rrlu,lstsq,small,batch,serve",
                     help="extra measurements in the same line: comma list of exp8192, fp32, "
-                         "power, lstsq (the last three with exp8192), small, batch, serve, or none")
+                         "power, rrlu, lstsq (the last four with exp8192), small, batch, serve, "
+                         "or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
     ap.add_argument("--no-check", action="store_true",

@@ -95,7 +95,12 @@ enum {
   RLU_FLAG_CHECK_FINITE = 1u, /* scan the sketch for NaN / infinity: info[2]
                                  bit 1, status RLU_ERR_NONFINITE (one pass
                                  over the m x l sketch, no pass over A)   */
-  RLU_FLAG_DIAGNOSTICS = 2u   /* fill the optional diagnostic outputs      */
+  RLU_FLAG_DIAGNOSTICS = 2u,  /* fill the optional diagnostic outputs      */
+  RLU_FLAG_RRLU = 4u          /* Step 3 as Algorithm 4.1 lists it: a
+                                 rank-revealing LU P Y Q_y = L_y U_y, Q_y
+                                 the column order of a column-pivoted QR of
+                                 Y (see rlu_factor); rlu_factor only,
+                                 l <= 1024                                  */
 };
 
 /* Problem description (Algorithm 4.1, Input): A is m x n, k the target rank,
@@ -142,6 +147,8 @@ typedef struct {
   void* B; int64_t ldb;        /* out k x n: B = L_y^+ P A (before Step 6)      */
   int32_t* ipiv;               /* out length l: Step 3 swap sequence (LAPACK)   */
   int32_t* qpiv;               /* out length k: Step 6 swap sequence            */
+  int32_t* qy;                 /* out length l: Step 3 column order Q_y, with
+                                  RLU_FLAG_RRLU ((Y Q_y)(:, j) = Y(:, qy[j]))  */
 } rlu_buffers_t;
 
 typedef struct rlu_handle_s* rlu_handle_t;
@@ -168,6 +175,18 @@ rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
  * the plain (A A^T)^q A G.  A zero pivot inside such a normalization is not
  * reported (Step 3 reports the rank of the final sketch).  The optional
  * diagnostic Y is the final sketch.
+ *
+ * Rank-revealing Step 3 (pb->flags & RLU_FLAG_RRLU, Algorithm 4.1 as listed
+ * with the RRLU of Section 3.1): the sketch's columns are first put in the
+ * order Q_y of a column-pivoted QR of Y (Businger-Golub: at each step the
+ * remaining column with the largest norm orthogonal to those chosen, lowest
+ * current position on ties), computed as a pivoted Cholesky of the Gram
+ * matrix Y^T Y (the same order in exact arithmetic); then P (Y Q_y) =
+ * L_y U_y by partial pivoting, and Steps 4-8 as usual.  With partial
+ * pivoting alone only the first k sketch columns reach the result; here
+ * the k columns of the l that the column-pivoted QR ranks first do.
+ * Requires l <= 1024; rlu_factor_batched and the server reject the flag
+ * (RLU_ERR_UNSUPPORTED).
  *
  * Zero pivots: in Step 3 the LAPACK getf2 convention holds (no scaling, no
  * update, info[0] = first such step); in Step 6, column j of L_b below the

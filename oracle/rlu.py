@@ -84,7 +84,7 @@ def lu_partial_pivot(Y: np.ndarray):
     return LU, ipiv, p, info, {"piv_abs": piv_abs, "gap": gap, "max_abs": ymax}
 
 
-def column_pivoted_qr(Y: np.ndarray):
+def column_pivoted_qr(Y: np.ndarray, order=None):
     """Householder QR with column pivoting (Businger and Golub), the column
     choice of the rank-revealing Step 3 (Algorithm 4.1 as listed, with the
     RRLU of Section 3.1, Theorem 3.1).
@@ -96,7 +96,12 @@ def column_pivoted_qr(Y: np.ndarray):
 
     Returns (R, qy, diag): R (w x w upper triangular) with Y[:, qy] = Q R,
     the column order qy, and per-step diagnostics (largest remaining norm,
-    relative gap to the runner-up, and the largest column norm of Y)."""
+    relative gap to the runner-up, and the largest column norm of Y).
+
+    With ``order`` (a column order computed elsewhere) the same steps are
+    taken with that order's column at each step instead of the largest, and
+    diag["ratio"][j] records its remaining norm over the largest: an order
+    is a valid column-pivoted order where every ratio is 1 up to rounding."""
     W = np.array(Y, dtype=np.float64, copy=True)
     m, w = W.shape
     if w > m:
@@ -104,10 +109,15 @@ def column_pivoted_qr(Y: np.ndarray):
     qy = np.arange(w, dtype=np.int64)
     top = np.zeros(w)
     gap = np.zeros(w)
+    ratio = np.ones(w)
     ymax = float(np.max(np.linalg.norm(W, axis=0))) if W.size else 0.0
     for j in range(w):
         norms = np.linalg.norm(W[j:, j:], axis=0)
         c = j + int(np.argmax(norms))
+        if order is not None:
+            best = norms[c - j]
+            c = j + int(np.nonzero(qy[j:] == order[j])[0][0])
+            ratio[j] = norms[c - j] / best if best > 0 else 1.0
         top[j] = norms[c - j]
         if norms.size > 1:
             second = np.partition(norms, norms.size - 2)[norms.size - 2]
@@ -127,16 +137,16 @@ def column_pivoted_qr(Y: np.ndarray):
         v /= np.linalg.norm(v)
         W[j:, j:] -= 2.0 * np.outer(v, v @ W[j:, j:])
     R = np.triu(W[:w, :w])
-    return R, qy, {"piv_abs": top, "gap": gap, "max_abs": ymax}
+    return R, qy, {"piv_abs": top, "gap": gap, "max_abs": ymax, "ratio": ratio}
 
 
-def rrlu(Y: np.ndarray):
+def rrlu(Y: np.ndarray, order=None):
     """The rank-revealing Step 3 of Algorithm 4.1 as listed: P Y Q_y =
     L_y U_y with the column permutation Q_y of ``column_pivoted_qr`` and
     the partial-pivot LU (``lu_partial_pivot``) of Y Q_y, all columns
     factored.  Returns (LU, ipiv, p, info, diag, qy, qdiag) with LU the
-    packed factors of Y[:, qy]."""
-    _, qy, qdiag = column_pivoted_qr(Y)
+    packed factors of Y[:, qy].  ``order`` as in ``column_pivoted_qr``."""
+    _, qy, qdiag = column_pivoted_qr(Y, order)
     LU, ipiv, p, info, diag = lu_partial_pivot(np.asarray(Y)[:, qy])
     return LU, ipiv, p, info, diag, qy, qdiag
 
@@ -265,7 +275,7 @@ def power_sketch(A: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
 
 
 def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
-                  scheme: str = "auto", step3: str = "partial") -> dict:
+                  scheme: str = "auto", step3: str = "partial", order=None) -> dict:
     """Algorithm 4.1 of the paper, Steps 2-8, for a given Gaussian G (Step 1).
 
     Inputs: A (m x n), k (target rank), l (number of sketch columns,
@@ -274,7 +284,8 @@ def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
     sketch is formed: "plain", "normalized", or "auto" (plain up to
     PLAIN_POWER_MAX_Q, normalized above).  ``step3`` is "partial" (the LU
     with partial pivoting the Remark after Algorithm 4.1 allows) or "rrlu"
-    (the rank-revealing LU of the listing, ``rrlu``).  Returns a dict with the outputs
+    (the rank-revealing LU of the listing, ``rrlu``; ``order`` fixes its
+    column order, see ``column_pivoted_qr``).  Returns a dict with the outputs
     L (m x k unit lower trapezoidal), U (k x n upper trapezoidal), p, q and
     the intermediates (Y, packed LU of Y, ipiv, L_y, B, L_b, qpiv, info words
     and pivot diagnostics).
@@ -289,11 +300,11 @@ def randomized_lu(A: np.ndarray, k: int, l: int, G: np.ndarray, q: int = 0,
     make = {"auto": power_sketch, "plain": power_sketch_plain,
             "normalized": power_sketch_normalized}[scheme]
     Y = make(A, G, q)                                  # Step 2 (Section 5.2)
-    return randomized_lu_from_sketch(A, k, Y, step3)
+    return randomized_lu_from_sketch(A, k, Y, step3, order)
 
 
 def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray,
-                              step3: str = "partial") -> dict:
+                              step3: str = "partial", order=None) -> dict:
     """Steps 3-8 of Algorithm 4.1 for a given sketch Y (m x l); ``step3`` as
     in ``randomized_lu``."""
     A = np.asarray(A, dtype=np.float64)
@@ -303,7 +314,7 @@ def randomized_lu_from_sketch(A: np.ndarray, k: int, Y: np.ndarray,
         raise ValueError("need an m x l sketch with 1 <= k <= l <= min(m, n)")
     qy, qdiag = None, None
     if step3 == "rrlu":
-        LUy, ipiv, p, info_y, diag_y, qy, qdiag = rrlu(Y)      # Step 3, P Y Q_y = L_y U_y
+        LUy, ipiv, p, info_y, diag_y, qy, qdiag = rrlu(Y, order)  # Step 3, P Y Q_y = L_y U_y
     elif step3 == "partial":
         LUy, ipiv, p, info_y, diag_y = lu_partial_pivot(Y)     # Step 3 (Remark)
     else:

@@ -17,13 +17,14 @@ from dataclasses import dataclass
 __all__ = ["RluError", "Handle", "factor", "factor_batched", "lstsq", "Batch", "Server",
            "serve_footprint", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
-           "FLAG_CHECK_FINITE", "FLAG_DIAGNOSTICS", "EXPORTED_SYMBOLS", "close_default_handles"]
+           "FLAG_CHECK_FINITE", "FLAG_DIAGNOSTICS", "FLAG_RRLU", "EXPORTED_SYMBOLS",
+           "close_default_handles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librlu.so")
 
 F64, F32 = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_FP16 = 0, 1, 2, 3
-FLAG_CHECK_FINITE, FLAG_DIAGNOSTICS = 1, 2
+FLAG_CHECK_FINITE, FLAG_DIAGNOSTICS, FLAG_RRLU = 1, 2, 4
 
 STATUS = {
     0: "RLU_OK", 1: "RLU_PENDING", 2: "RLU_WARN_ZERO_PIVOT", -1: "RLU_ERR_INVALID_ARG",
@@ -76,7 +77,7 @@ class Buffers(ctypes.Structure):
                 ("p", ctypes.c_void_p), ("q", ctypes.c_void_p), ("info", ctypes.c_void_p),
                 ("Y", ctypes.c_void_p), ("ldy", ctypes.c_int64),
                 ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
-                ("ipiv", ctypes.c_void_p), ("qpiv", ctypes.c_void_p)]
+                ("ipiv", ctypes.c_void_p), ("qpiv", ctypes.c_void_p), ("qy", ctypes.c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -273,6 +274,7 @@ class Factors:
     B: "object" = None
     ipiv: "object" = None
     qpiv: "object" = None
+    qy: "object" = None
 
 
 def _ptr(t):
@@ -312,6 +314,7 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters=0):
             out.B = torch.empty((n, k), dtype=ytype, device=dev).t()
             out.ipiv = torch.empty(l, dtype=torch.int32, device=dev)
             out.qpiv = torch.empty(k, dtype=torch.int32, device=dev)
+            out.qy = torch.empty(l, dtype=torch.int32, device=dev)
     pb = Problem(m, n, k, l, dtype, prec, seed, None, 0, FLAG_DIAGNOSTICS if diagnostics else 0,
                  power_iters)
     if G is not None:
@@ -328,26 +331,31 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters=0):
                  out.B.data_ptr() if out.B is not None else None,
                  (max(out.B.stride(1), k) if n > 1 else k) if out.B is not None else 0,
                  out.ipiv.data_ptr() if out.ipiv is not None else None,
-                 out.qpiv.data_ptr() if out.qpiv is not None else None)
+                 out.qpiv.data_ptr() if out.qpiv is not None else None,
+                 out.qy.data_ptr() if out.qy is not None else None)
     return pb, io, out
 
 
 def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
            diagnostics: bool = False, handle: Handle | None = None, stream=None,
            out: Factors | None = None, power_iters: int = 0,
-           check_finite: bool = False) -> Factors:
+           check_finite: bool = False, rrlu: bool = False) -> Factors:
     """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
     float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
     tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
     p, q (int64) and info (int32[3]); the work is enqueued on ``stream`` (the
     current torch stream by default) and not synchronized.  ``power_iters``
     is q of the power scheme, Y = (A A^T)^q A G (Section 5.2).
-    ``check_finite`` asks for the scan for NaN / infinity (info[2] bit 1)."""
+    ``check_finite`` asks for the scan for NaN / infinity (info[2] bit 1);
+    ``rrlu`` for the rank-revealing Step 3 as Algorithm 4.1 lists it (the
+    sketch columns in column-pivoted QR order before partial pivoting)."""
     import torch
 
     pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters)
     if check_finite:
         pb.flags |= FLAG_CHECK_FINITE
+    if rrlu:
+        pb.flags |= FLAG_RRLU
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     h = handle or default_handle(A.device.index or 0, s)
     st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),

@@ -33,7 +33,7 @@
 static const char* const kPhaseNames[PH_COUNT] = {
     "gaussian", "sketch_gemm", "panel_lu_y", "gram_gemm", "gram_inverse", "project_gemm",
     "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm", "sketch_splitk_sum",
-    "project_splitk_sum", "power_iterations"};
+    "project_splitk_sum", "power_iterations", "column_choice"};
 
 namespace rlu_detail {
 
@@ -80,6 +80,7 @@ struct Layout {
   size_t total = 0;
   size_t u12 = 0, bt = 0;
   size_t zt = 0, z = 0, piv_z = 0, ipiv_z = 0;  // power iterations (Section 5.2)
+  size_t sy = 0, rq = 0, qy = 0, yq = 0;        // rank-revealing Step 3
   BlockedPanel py{}, pb{}, pz{};
 };
 
@@ -103,6 +104,8 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   part = std::max(part, gemm_auto_partial_elems(k, n, k, OpA::Plain));
   part = std::max(part, gemm_auto_partial_elems(m, k, k, OpA::Lv));
   if (power) part = std::max(part, gemm_auto_partial_elems(l, n, m, OpA::LvT));
+  const bool rr = (pb.flags & RLU_FLAG_RRLU) != 0;
+  if (rr) part = std::max(part, gemm_auto_partial_elems(l, l, m, OpA::LvT));
   if (pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16) {
     part = std::max(part, gemm_lp_partial_elems(m, l, n));
     part = std::max(part, gemm_lp_partial_elems(k, n, m));
@@ -127,6 +130,10 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   take(L.z, power ? (size_t)n * l * d : 0);
   take(L.piv_z, power ? (size_t)l * 4 : 0);
   take(L.ipiv_z, power ? (size_t)l * 4 : 0);
+  take(L.sy, rr ? (size_t)l * l * d : 0);
+  take(L.rq, rr ? (size_t)l * l * d : 0);
+  take(L.qy, rr ? (size_t)l * 4 : 0);
+  take(L.yq, rr ? (size_t)m * l * d : 0);
   L.py = plan_blocked((int)m, (int)l, cus);
   L.pb = plan_blocked((int)n, (int)k, cus);
   if (!L.py.ok || !L.pb.ok) return false;
@@ -181,8 +188,9 @@ rlu_status_t validate(const rlu_problem_t* pb) {
       return RLU_ERR_INVALID_ARG;
   }
   if (pb->G && pb->ldg < pb->n) return RLU_ERR_INVALID_ARG;
-  if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS))
+  if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS | RLU_FLAG_RRLU))
     return RLU_ERR_INVALID_ARG;
+  if ((pb->flags & RLU_FLAG_RRLU) && pb->l > kSpdColPivMax) return RLU_ERR_UNSUPPORTED;
   if (pb->power_iters < 0 || pb->power_iters > RLU_MAX_POWER_ITERS) return RLU_ERR_INVALID_ARG;
   if (!spd_inverse_supported(pb->k)) return RLU_ERR_UNSUPPORTED;
   return RLU_OK;
@@ -294,7 +302,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   const bool kF32 = pb.precision == RLU_PREC_FP32;   // diagnostics stored in FP32
   const int64_t m = pb.m, n = pb.n, k = pb.k, l = pb.l;
   void* ws = h->ws;
-  double* Y = at<double>(ws, Ly.Y);
+  double* Y = at<double>(ws, Ly.Y);   // the sketch; Y Q_y from Step 3 on with RLU_FLAG_RRLU
   double* S = at<double>(ws, Ly.S);
   double* C = at<double>(ws, Ly.C);
   double* Bst = at<double>(ws, Ly.Bst);
@@ -410,6 +418,28 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   if (diag && io.Y) {
     if (kF32) HIP_TRY((launch_convert2d<double, float>(Y, m, (float*)io.Y, io.ldy, m, l, s)));
     else HIP_TRY(launch_copy2d<double>(Y, m, (double*)io.Y, io.ldy, m, l, s));
+  }
+  // Step 3 as listed (RRLU): the column order Q_y of a column-pivoted QR of
+  // Y from its Gram matrix (pivoted Cholesky), then Y Q_y replaces Y
+  if (pb.flags & RLU_FLAG_RRLU) {
+    PhaseScope ph(h, PH_COLPIV, s);
+    double* Sy = at<double>(ws, Ly.sy);
+    int* qy = at<int>(ws, Ly.qy);
+    // S_y = Y^T Y through the Lv operand forms with every row step l (all
+    // entries stored); the row steps are rewritten by Step 3's panel
+    HIP_TRY(launch_fill_u32((uint32_t*)rstep_y, (size_t)m, (uint32_t)l, s));
+    GemmDesc d{};
+    d.M = l; d.N = l; d.K = m;
+    d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
+    d.B = Y; d.ldb = m; d.opb = OpB::Lv; d.bstep = rstep_y;
+    d.C = Sy; d.ldc = l;
+    d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    HIP_TRY(launch_gemm<double>(d, s));
+    HIP_TRY(launch_colpiv_gram(Sy, l, (int)l, at<double>(ws, Ly.rq), qy, s));
+    double* Yq = at<double>(ws, Ly.yq);
+    HIP_TRY(launch_gather_cols(Y, m, qy, Yq, m, m, (int)l, s));
+    if (diag && io.qy) HIP_TRY(launch_copy_i32(qy, io.qy, l, s));
+    Y = Yq;
   }
   // Step 3 (+ Step 4: only the first k columns of the unit-lower factor are used)
   {

@@ -156,6 +156,17 @@ hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_
 // One matrix.
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
 
+// ----- Rank-revealing Step 3 (rrlu.hip) --------------------------------------
+// Column order of a column-pivoted QR of Y from its Gram matrix S = Y^T Y
+// (l x l, FP64, ld lds): pivoted Cholesky in one workgroup, l <= kSpdColPivMax;
+// R is l x l FP64 scratch, qy (length l) receives the order.
+constexpr int kSpdColPivMax = 1024;
+hipError_t launch_colpiv_gram(const double* S, int64_t lds, int l, double* R, int* qy,
+                              hipStream_t s);
+// Yq(:, j) = Y(:, qy[j]) for j < l (m rows).
+hipError_t launch_gather_cols(const double* Y, int64_t ldy, const int* qy, double* Yq,
+                              int64_t ldq, int64_t m, int l, hipStream_t s);
+
 // ----- Rank-deficient least squares, Algorithm 4.3 (lstsq.hip) -------------
 constexpr int kLsMaxK = 1024;   // largest k of the back substitution (= kSpdMaxK)
 // Ld (m x k, FP64, ld m) with row p[i] = row i of L (entries of p outside

@@ -61,6 +61,22 @@ def test_check_finite_flag_is_accepted(rlu):
                    flags=rlu.FLAG_CHECK_FINITE | rlu.FLAG_DIAGNOSTICS)[0] == 0
 
 
+def test_rrlu_flag_workspace_and_limits(rlu):
+    st, plain = _ws(rlu, 3000, 2500, 50, 80)
+    st2, rr = _ws(rlu, 3000, 2500, 50, 80, flags=rlu.FLAG_RRLU)
+    assert st == 0 and st2 == 0
+    # the Gram matrix, R and the column order (l x l, l x l, l) and Y Q_y (m x l)
+    # (each absent area already holds one 256-byte aligned slot)
+    assert rr - plain >= 8 * (2 * 80 * 80 + 3000 * 80) - 4 * 256
+    assert _ws(rlu, 4000, 4000, 10, 1024, flags=rlu.FLAG_RRLU)[0] == 0
+    assert _ws(rlu, 4000, 4000, 10, 1025, flags=rlu.FLAG_RRLU)[0] == -8
+    assert _ws(rlu, 4000, 4000, 10, 1025)[0] == 0
+    # the batched form (and so the server) does not take the flag
+    pb = rlu.Problem(300, 200, 5, 8, 0, 0, 0, None, 0, rlu.FLAG_RRLU, 0)
+    out = ctypes.c_size_t()
+    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -8
+
+
 def test_exchange_limit_argument_checks(rlu):
     lib = rlu.lib()
     assert lib.rlu_set_exchange_limit(None, 0, 0) == -1

@@ -55,6 +55,14 @@ def test_exp_spectrum_8192_fp64(rlu, exp8192, q):
         assert e1 < e0
 
 
+def test_exp_spectrum_8192_rrlu(rlu, exp8192):
+    """The rank-revealing Step 3 (Algorithm 4.1 as listed) at the full size,
+    element by element under the rule of test_gpu_rrlu."""
+    from tests.test_gpu_rrlu import compare_rrlu
+    A, k, l, G = exp8192
+    compare_rrlu(rlu, A, k, l, G, "8192^2 exp(-i/50)")
+
+
 def test_exp_spectrum_8192_lstsq(rlu, exp8192):
     """Algorithm 4.3 on the full-size factors, as the least-squares form of
     the benchmark runs it (b = A x0): the GPU solve on the GPU factors

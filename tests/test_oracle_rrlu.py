@@ -54,6 +54,22 @@ def test_each_pivot_is_the_largest_remaining_column(case):
     assert np.all(np.diff(np.abs(np.diag(R))) <= 1e-12 * abs(R[0, 0]))
 
 
+@pytest.mark.parametrize("case", range(3))
+def test_a_given_column_order_is_followed_and_judged(case):
+    Y = _inputs()[case]
+    R, qy, d = rlu.column_pivoted_qr(Y)
+    R2, qy2, d2 = rlu.column_pivoted_qr(Y, order=qy)
+    np.testing.assert_array_equal(qy2, qy)
+    np.testing.assert_array_equal(R2, R)
+    assert np.all(d2["ratio"] == 1.0)
+    # exchanging the first two columns of the order is not a valid choice
+    bad = qy.copy()
+    bad[[0, 1]] = bad[[1, 0]]
+    _, qy3, d3 = rlu.column_pivoted_qr(Y, order=bad)
+    np.testing.assert_array_equal(qy3, bad)
+    assert d3["ratio"][0] < 1.0 - 1e-6
+
+
 def _rrlu_blocks(Y, k):
     LU, ipiv, p, info, diag, qy, qd = rlu.rrlu(Y)
     w = Y.shape[1]
