@@ -247,7 +247,7 @@ def step_roofline(works, ms_per_step):
 
 
 def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power_iters=0,
-                 phase_calls=5, rrlu=False):
+                 phase_calls=5, rrlu=False, fast=False):
     """`steps` rlu_factor calls in the timed region (timing mode 3: HIP events
     around the sketch product and around every pivoted-LU kernel launch, on
     the stream they run on), then `phase_calls` calls with every phase timed.
@@ -260,7 +260,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     out = None
     for _ in range(warmup):
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters, rrlu=rrlu)
+                         power_iters=power_iters, rrlu=rrlu, fast=fast)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
@@ -269,7 +269,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     for i in range(steps):
         evs[i][0].record(st)
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters, rrlu=rrlu)
+                         power_iters=power_iters, rrlu=rrlu, fast=fast)
         evs[i][1].record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -280,7 +280,7 @@ def timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps, warmup, power
     h.set_timing(True)  # every phase, in a pass after the timed region
     for _ in range(phase_calls):
         out = rlu.factor(A, k, l, seed=sseed, precision=precision, handle=h, stream=st, out=out,
-                         power_iters=power_iters, rrlu=rrlu)
+                         power_iters=power_iters, rrlu=rrlu, fast=fast)
     torch.cuda.synchronize()
     ph = [h.phase_times(b) for b in range(phase_calls)]
     ph = {key: float(np.mean([p[key] for p in ph])) for key in ph[0] if key != "panel_lu_kernel"}
@@ -360,14 +360,14 @@ def measured_traffic(workload, prod):
 
 
 def measure(rlu, torch, np, A, k, l, sseed, prec, steps, warmup, workload, check_A=None,
-            power_iters=0, rrlu=False):
+            power_iters=0, rrlu=False, fast=False):
     """One configuration: timed calls, phase table, step roofline, the
     dominant kernel's roofline and (with check_A) the relative residual."""
     m, n = A.shape
     precision = {"fp64": rlu.PREC_FP64, "fp32": rlu.PREC_FP32, "bf16": rlu.PREC_MIXED_BF16,
                  "fp16": rlu.PREC_MIXED_FP16}[prec]
     out, v, ms, lat, ph, kern = timed_factor(rlu, torch, np, A, k, l, sseed, precision, steps,
-                                             warmup, power_iters, rrlu=rrlu)
+                                             warmup, power_iters, rrlu=rrlu, fast=fast)
     s_a = 8.0 if prec == "fp64" else 4.0
     works = phase_work(m, n, k, l, s_a, s_a, prec)
     res = {"value": v, "unit": "factorizations/s", "ms_per_step": ms,
@@ -700,6 +700,19 @@ def run_exp8192_form(rlu, torch, np, steps, warmup, forms, input_kind, check, cp
             log(f"exp8192 rrlu l={l2}: {rq['value']:.1f}/s, residual {rq.get('rel_residual')}")
             del oq
         res["rrlu"] = rr
+    if "fast" in forms:
+        # Algorithm 4.4 (Section 4.5): SRFT sketch and interpolative
+        # decomposition; the paper notes it needs a larger l for the same
+        # error, so l = k + 10 and l = 2k
+        fr = {}
+        for l2 in (l, 2 * k):
+            rf, of = measure(rlu, torch, np, A, k, l2, sseed, "fp64", max(5, steps // 2), 2,
+                             name + "_fast", A if check else None, fast=True)
+            rf["workload"] = f"{WORKLOADS[name][8]}, l={l2}, Algorithm 4.4 (fast randomized LU)"
+            fr[f"l{l2}"] = rf
+            log(f"exp8192 fast l={l2}: {rf['value']:.1f}/s, residual {rf.get('rel_residual')}")
+            del of
+        res["fast"] = fr
     if "lstsq" in forms:
         res["lstsq"] = run_lstsq(rlu, torch, np, A, out, k)
     if cpu_s > 0:
@@ -729,10 +742,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="mixed16384",
                     choices=["mixed16384"] + sorted(WORKLOADS))
-    ap.add_argument("--forms", default="exp8192,fp32,power,rrlu,lstsq,small,batch,serve",
+    ap.add_argument("--forms", default="exp8192,fp32,power,rrlu,fast,lstsq,small,batch,serve",
                     help="extra measurements in the same line: comma list of exp8192, fp32, "
-                         "power, rrlu, lstsq (the last four with exp8192), small, batch, serve, "
-                         "or none")
+                         "power, rrlu, fast, lstsq (the last five with exp8192), small, batch, "
+                         "serve, or none")
     ap.add_argument("--input", default="spectral", choices=["spectral", "gaussian"],
                     help="gaussian: i.i.d. values of the same shape (hardware-counter runs)")
     ap.add_argument("--no-check", action="store_true",

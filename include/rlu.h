@@ -96,11 +96,15 @@ enum {
                                  bit 1, status RLU_ERR_NONFINITE (one pass
                                  over the m x l sketch, no pass over A)   */
   RLU_FLAG_DIAGNOSTICS = 2u,  /* fill the optional diagnostic outputs      */
-  RLU_FLAG_RRLU = 4u          /* Step 3 as Algorithm 4.1 lists it: a
+  RLU_FLAG_RRLU = 4u,         /* Step 3 as Algorithm 4.1 lists it: a
                                  rank-revealing LU P Y Q_y = L_y U_y, Q_y
                                  the column order of a column-pivoted QR of
                                  Y (see rlu_factor); rlu_factor only,
                                  l <= 1024                                  */
+  RLU_FLAG_FAST = 8u          /* Algorithm 4.4, fast randomized LU: SRFT
+                                 sketch and interpolative decomposition (see
+                                 rlu_factor); rlu_factor only, FP64 / FP32,
+                                 G = NULL, no power iterations, l <= 1024  */
 };
 
 /* Problem description (Algorithm 4.1, Input): A is m x n, k the target rank,
@@ -187,6 +191,20 @@ rlu_status_t rlu_workspace_size(const rlu_problem_t* pb, size_t* bytes);
  * the k columns of the l that the column-pivoted QR ranks first do.
  * Requires l <= 1024; rlu_factor_batched and the server reject the flag
  * (RLU_ERR_UNSUPPORTED).
+ *
+ * Fast randomized LU (pb->flags & RLU_FLAG_FAST, Section 4.5, Algorithm
+ * 4.4): Step 1 draws the SRFT R = D F S (Section 3.3) from pb->seed instead
+ * of G -- F the orthonormal discrete Hartley transform (real, so a real A
+ * keeps real factors), D = diag(+1 / -1), S l distinct columns in a random
+ * order; the draws use the Philox4x32-10 key of Step 1 with counters
+ * (i div 128, 0, 1, 0) for the sign of row i (bit i mod 128 of the four
+ * words, bit 0 = +1) and (j, 0, 2, 0) for step j of a partial Fisher-Yates
+ * shuffle of 0..n-1 that exchanges positions j and j + ((x1:x0) mod (n-j)).
+ * Y = A R; Step 3 as above (partial pivoting, or RRLU with RLU_FLAG_RRLU);
+ * the full-rank ID Y = X Y(J, :) comes from Step 3's LU (J = the l rows its
+ * steps chose, X = Y Y(J, :)^{-1}); B = L_y^+ P X A(J, :), which reads only
+ * the l rows J of A; Steps 7-9 as in Algorithm 4.1.  With diagnostics, Y is
+ * A R and B this B.
  *
  * Zero pivots: in Step 3 the LAPACK getf2 convention holds (no scaling, no
  * update, info[0] = first such step); in Step 6, column j of L_b below the

@@ -17,14 +17,14 @@ from dataclasses import dataclass
 __all__ = ["RluError", "Handle", "factor", "factor_batched", "lstsq", "Batch", "Server",
            "serve_footprint", "lib", "status_string", "LIB_PATH",
            "F64", "F32", "PREC_FP64", "PREC_FP32", "PREC_MIXED_BF16", "PREC_MIXED_FP16",
-           "FLAG_CHECK_FINITE", "FLAG_DIAGNOSTICS", "FLAG_RRLU", "EXPORTED_SYMBOLS",
+           "FLAG_CHECK_FINITE", "FLAG_DIAGNOSTICS", "FLAG_RRLU", "FLAG_FAST", "EXPORTED_SYMBOLS",
            "close_default_handles"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librlu.so")
 
 F64, F32 = 0, 1
 PREC_FP64, PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_FP16 = 0, 1, 2, 3
-FLAG_CHECK_FINITE, FLAG_DIAGNOSTICS, FLAG_RRLU = 1, 2, 4
+FLAG_CHECK_FINITE, FLAG_DIAGNOSTICS, FLAG_RRLU, FLAG_FAST = 1, 2, 4, 8
 
 STATUS = {
     0: "RLU_OK", 1: "RLU_PENDING", 2: "RLU_WARN_ZERO_PIVOT", -1: "RLU_ERR_INVALID_ARG",
@@ -339,7 +339,7 @@ def _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters=0):
 def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=None,
            diagnostics: bool = False, handle: Handle | None = None, stream=None,
            out: Factors | None = None, power_iters: int = 0,
-           check_finite: bool = False, rrlu: bool = False) -> Factors:
+           check_finite: bool = False, rrlu: bool = False, fast: bool = False) -> Factors:
     """Randomized LU of the device matrix A (torch tensor, m x n, float64 or
     float32, column-major: pass ``X.t()`` of a contiguous n x m tensor, or any
     tensor with stride (1, lda)).  Returns device tensors L (m x k), U (k x n),
@@ -348,7 +348,9 @@ def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=
     is q of the power scheme, Y = (A A^T)^q A G (Section 5.2).
     ``check_finite`` asks for the scan for NaN / infinity (info[2] bit 1);
     ``rrlu`` for the rank-revealing Step 3 as Algorithm 4.1 lists it (the
-    sketch columns in column-pivoted QR order before partial pivoting)."""
+    sketch columns in column-pivoted QR order before partial pivoting);
+    ``fast`` for Algorithm 4.4 (SRFT sketch drawn from ``seed`` and the
+    interpolative decomposition; G must be None)."""
     import torch
 
     pb, io, out = _prepare(A, k, l, precision, seed, G, diagnostics, out, power_iters)
@@ -356,6 +358,8 @@ def factor(A, k: int, l: int, *, precision: int | None = None, seed: int = 0, G=
         pb.flags |= FLAG_CHECK_FINITE
     if rrlu:
         pb.flags |= FLAG_RRLU
+    if fast:
+        pb.flags |= FLAG_FAST
     s = stream if stream is not None else torch.cuda.current_stream(A.device)
     h = handle or default_handle(A.device.index or 0, s)
     st = lib().rlu_factor(h.ptr, ctypes.byref(pb), ctypes.byref(io),

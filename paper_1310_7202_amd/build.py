@@ -35,7 +35,7 @@ HIP_FLAGS = [
 ]
 
 SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
-           "lstsq.hip", "rrlu.hip",
+           "lstsq.hip", "rrlu.hip", "fast_lu.hip",
            "rlu_api.cpp", "rlu_batch.cpp", "rlu_serve.cpp"]
 HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
 SAN_LIB = os.path.join(BUILD_DIR, "librlu_san.so")

@@ -33,7 +33,7 @@
 static const char* const kPhaseNames[PH_COUNT] = {
     "gaussian", "sketch_gemm", "panel_lu_y", "gram_gemm", "gram_inverse", "project_gemm",
     "solve_gemm", "panel_lu_bt", "assemble_u_lb", "form_l_gemm", "sketch_splitk_sum",
-    "project_splitk_sum", "power_iterations", "column_choice"};
+    "project_splitk_sum", "power_iterations", "column_choice", "id_solve"};
 
 namespace rlu_detail {
 
@@ -81,6 +81,7 @@ struct Layout {
   size_t u12 = 0, bt = 0;
   size_t zt = 0, z = 0, piv_z = 0, ipiv_z = 0;  // power iterations (Section 5.2)
   size_t sy = 0, rq = 0, qy = 0, yq = 0;        // rank-revealing Step 3
+  size_t sel = 0, gk = 0, tb = 0, wb = 0, aj = 0;  // Algorithm 4.4
   BlockedPanel py{}, pb{}, pz{};
 };
 
@@ -106,6 +107,11 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   if (power) part = std::max(part, gemm_auto_partial_elems(l, n, m, OpA::LvT));
   const bool rr = (pb.flags & RLU_FLAG_RRLU) != 0;
   if (rr) part = std::max(part, gemm_auto_partial_elems(l, l, m, OpA::LvT));
+  const bool fast = (pb.flags & RLU_FLAG_FAST) != 0;
+  if (fast) {
+    part = std::max(part, gemm_auto_partial_elems(k, l, m, OpA::LvT));
+    part = std::max(part, gemm_auto_partial_elems(k, n, l, OpA::Plain));
+  }
   if (pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16) {
     part = std::max(part, gemm_lp_partial_elems(m, l, n));
     part = std::max(part, gemm_lp_partial_elems(k, n, m));
@@ -134,6 +140,11 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
   take(L.rq, rr ? (size_t)l * l * d : 0);
   take(L.qy, rr ? (size_t)l * 4 : 0);
   take(L.yq, rr ? (size_t)m * l * d : 0);
+  take(L.sel, fast ? (size_t)l * 4 : 0);
+  take(L.gk, fast ? (size_t)k * l * d : 0);
+  take(L.tb, fast ? (size_t)k * std::max<int64_t>(l - k, 1) * d : 0);
+  take(L.wb, fast ? (size_t)k * l * d : 0);
+  take(L.aj, fast ? (size_t)l * n * sa : 0);
   L.py = plan_blocked((int)m, (int)l, cus);
   L.pb = plan_blocked((int)n, (int)k, cus);
   if (!L.py.ok || !L.pb.ok) return false;
@@ -188,9 +199,16 @@ rlu_status_t validate(const rlu_problem_t* pb) {
       return RLU_ERR_INVALID_ARG;
   }
   if (pb->G && pb->ldg < pb->n) return RLU_ERR_INVALID_ARG;
-  if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS | RLU_FLAG_RRLU))
+  if (pb->flags & ~(uint32_t)(RLU_FLAG_CHECK_FINITE | RLU_FLAG_DIAGNOSTICS | RLU_FLAG_RRLU |
+                              RLU_FLAG_FAST))
     return RLU_ERR_INVALID_ARG;
   if ((pb->flags & RLU_FLAG_RRLU) && pb->l > kSpdColPivMax) return RLU_ERR_UNSUPPORTED;
+  if (pb->flags & RLU_FLAG_FAST) {
+    // Algorithm 4.4 draws its own sketch matrix and has no power scheme
+    if (pb->G || pb->power_iters != 0) return RLU_ERR_INVALID_ARG;
+    if (pr != RLU_PREC_FP64 && pr != RLU_PREC_FP32) return RLU_ERR_UNSUPPORTED;
+    if (pb->l > 1024 || id_solve_rows((int)pb->l) < 1) return RLU_ERR_UNSUPPORTED;
+  }
   if (pb->power_iters < 0 || pb->power_iters > RLU_MAX_POWER_ITERS) return RLU_ERR_INVALID_ARG;
   if (!spd_inverse_supported(pb->k)) return RLU_ERR_UNSUPPORTED;
   return RLU_OK;
@@ -325,10 +343,17 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   if (h->xch_preset_fail) HIP_TRY(launch_fill_u32((uint32_t*)flags + 2, 1, 1u, s));
   const long long tmo = h->xch_timeout;
 
-  // Step 1
+  // Step 1 (Algorithm 4.4: the SRFT R = D F S in the place of G)
+  const bool fast = (pb.flags & RLU_FLAG_FAST) != 0;
   const T* G = (const T*)pb.G;
   int64_t ldg = pb.ldg;
-  if (!G) {
+  if (fast) {
+    T* R = at<T>(ws, Ly.G);
+    PhaseScope ph(h, PH_GAUSSIAN, s);
+    HIP_TRY(launch_srft<T>(R, n, n, (int)l, pb.seed, at<int>(ws, Ly.sel), s));
+    G = R;
+    ldg = n;
+  } else if (!G) {
     T* Gw = at<T>(ws, Ly.G);
     PhaseScope ph(h, PH_GAUSSIAN, s);
     HIP_TRY(launch_gaussian<T>(Gw, n, n, l, pb.seed, s));
@@ -449,6 +474,54 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     if (st != RLU_OK) return st;
   }
   if (diag && io.ipiv) HIP_TRY(launch_copy_i32(ipiv_y, io.ipiv, l, s));
+  if (fast) {
+    // Algorithm 4.4, Steps 5-6: the ID Y = X Y(J, :) from Step 3's LU (J =
+    // the rows its steps chose, X = Lv L11^{-1}) and B = L_y^+ P X A(J, :)
+    // = W A(J, :) with W = [I_k, T] L11^{-1}, T = S^{-1} Lv_k^T Lv(:, k:l)
+    double* Gk = at<double>(ws, Ly.gk);
+    {
+      GemmDesc d{};  // [S, C2] = Lv_k^T Lv  (k x l)
+      d.M = k; d.N = l; d.K = m;
+      d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
+      d.B = Y; d.ldb = m; d.opb = OpB::Lv; d.bstep = rstep_y;
+      d.C = Gk; d.ldc = k;
+      d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+      PhaseScope ph(h, PH_GRAM, s);
+      HIP_TRY(launch_gemm<double>(d, s));
+    }
+    {
+      PhaseScope ph(h, PH_GRAM_INV, s);
+      HIP_TRY(launch_spd_inverse_scratch(Gk, k, at<double>(ws, Ly.gj), s));
+    }
+    double* Tb = at<double>(ws, Ly.tb);
+    if (l > k) {
+      GemmDesc d{};  // T = S^{-1} C2
+      d.M = k; d.N = l - k; d.K = k;
+      d.A = Gk; d.lda = k; d.opa = OpA::Plain;
+      d.B = Gk + k * k; d.ldb = k; d.opb = OpB::Plain;
+      d.C = Tb; d.ldc = k;
+      d.ksplit = 1;
+      PhaseScope ph(h, PH_SOLVE, s);
+      HIP_TRY(launch_gemm<double>(d, s));
+    }
+    double* Wb = at<double>(ws, Ly.wb);
+    {
+      PhaseScope ph(h, PH_ID_SOLVE, s);
+      HIP_TRY(launch_id_solve(Tb, k, Y, m, piv_y, (int)k, (int)l, Wb, k, s));
+    }
+    {
+      T* AJ = at<T>(ws, Ly.aj);
+      PhaseScope ph(h, PH_PROJECT, s);
+      HIP_TRY(launch_gather_rows<T>((const T*)io.A, io.lda, piv_y, (int)l, n, AJ, l, s));
+      GemmDesc d{};  // B = W A(J, :)
+      d.M = k; d.N = n; d.K = l;
+      d.A = Wb; d.lda = k; d.opa = OpA::Plain;
+      d.B = AJ; d.ldb = l; d.opb = OpB::Plain;
+      d.C = Bst; d.ldc = k;
+      d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+      HIP_TRY((launch_gemm_t<double, T, T, double>(d, s)));
+    }
+  } else {
   // Step 5: S = Lv^T Lv, S <- S^{-1}, C = Lv^T A
   {
     GemmDesc d{};
@@ -482,6 +555,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     PhaseScope ph(h, PH_SOLVE, s);
     HIP_TRY(launch_gemm<double>(d, s));
   }
+  }  // Step 5 of Algorithm 4.1
   if (diag && io.B) {
     if (kF32) HIP_TRY((launch_convert2d<double, float>(Bst, k, (float*)io.B, io.ldb, k, n, s)));
     else HIP_TRY(launch_copy2d<double>(Bst, k, (double*)io.B, io.ldb, k, n, s));

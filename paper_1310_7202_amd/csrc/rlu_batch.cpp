@@ -873,7 +873,7 @@ rlu_status_t batched_validate(int count, const rlu_problem_t* pbs, const rlu_buf
       if (st != RLU_OK) return st;
     }
     if (pbs[i].flags & RLU_FLAG_DIAGNOSTICS) return RLU_ERR_INVALID_ARG;
-    if (pbs[i].flags & RLU_FLAG_RRLU) return RLU_ERR_UNSUPPORTED;
+    if (pbs[i].flags & (RLU_FLAG_RRLU | RLU_FLAG_FAST)) return RLU_ERR_UNSUPPORTED;
     if (pbs[i].power_iters != pbs[0].power_iters) return RLU_ERR_INVALID_ARG;
     if (pbs[i].dtype != pbs[0].dtype || pbs[i].precision != pbs[0].precision)
       return RLU_ERR_INVALID_ARG;

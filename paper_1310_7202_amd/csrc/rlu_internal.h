@@ -16,7 +16,7 @@
 enum Phase {
   PH_GAUSSIAN = 0, PH_SKETCH, PH_PANEL_Y, PH_GRAM, PH_GRAM_INV, PH_PROJECT, PH_SOLVE,
   PH_PANEL_B, PH_ASSEMBLE, PH_FORM_L, PH_SKETCH_SUM, PH_PROJECT_SUM, PH_POWER, PH_COLPIV,
-  PH_COUNT
+  PH_ID_SOLVE, PH_COUNT
 };
 
 // Timing mode 3 also times every launch of the pivoted-LU kernel of a call

@@ -17,6 +17,13 @@ template <typename T>
 hipError_t launch_gaussian_batched(const GaussTaskDev* tasks, int count, int64_t max_elems,
                                    hipStream_t s);
 
+// Step 1 of Algorithm 4.4: the SRFT R = D F S (n x l, storage T, ld ldr)
+// drawn from `seed`; sel (length l, device) receives S's column indices.
+// l <= 1024, l <= n < 2^31.
+template <typename T>
+hipError_t launch_srft(T* R, int64_t ldr, int64_t n, int l, uint64_t seed, int* sel,
+                       hipStream_t s);
+
 // ----- MFMA GEMM (gemm.hip) -----------------------------------------------
 // C(M x N) = op(A)(M x K) * op(B)(K x N), all column-major with leading
 // dimensions.  Operand forms:
@@ -155,6 +162,17 @@ hipError_t launch_spd_inverse_batched(const SpdTaskDev* tasks, int count, int64_
                                      hipStream_t s);
 // One matrix.
 hipError_t launch_spd_inverse_scratch(double* S, int64_t k, double* scratch, hipStream_t s);
+
+// ----- Steps 5-6 of Algorithm 4.4 (fast_lu.hip) ------------------------------
+// W (k x l) with W L11 = [I_k, T], L11(c', c) = Y[J[c'] + c ldy] (c < c') the
+// unit-lower factor of Step 3 on the rows J it chose; T is k x (l - k).
+int id_solve_rows(int l);   // rows of W per workgroup (0: l too large)
+hipError_t launch_id_solve(const double* T, int64_t ldt, const double* Y, int64_t ldy,
+                           const int* J, int k, int l, double* W, int64_t ldw, hipStream_t s);
+// AJ (l x n, ld ldaj) = A(J, :)
+template <typename T>
+hipError_t launch_gather_rows(const T* A, int64_t lda, const int* J, int l, int64_t n, T* AJ,
+                              int64_t ldaj, hipStream_t s);
 
 // ----- Rank-revealing Step 3 (rrlu.hip) --------------------------------------
 // Column order of a column-pivoted QR of Y from its Gram matrix S = Y^T Y

@@ -1,5 +1,6 @@
 // Step 1 of Algorithm 4.1 (Shabat et al., Section 4): the n x l test matrix G
-// of i.i.d. zero-mean, unit-variance Gaussian entries.
+// of i.i.d. zero-mean, unit-variance Gaussian entries; and Step 1 of
+// Algorithm 4.4 (Section 4.5): the SRFT R = D F S of Section 3.3.
 //
 // Generator (the paper names none): Philox4x32-10 (Salmon, Moraes, Dror and
 // Shaw, SC'11) keyed by the 64-bit seed, one counter per pair of elements in
@@ -70,7 +71,96 @@ __global__ void __launch_bounds__(256) gaussian_batched_kernel(const GaussTaskDe
                    (uint32_t)(t.seed >> 32));
 }
 
+// ---------------------------------------------------------------------------
+// The SRFT R = D F S (n x l) of Algorithm 4.4, with F the orthonormal
+// discrete Hartley transform, F(i, c) = (cos + sin)(2 pi i c / n) / sqrt(n),
+// D = diag(+1 / -1) and S selecting l distinct columns in a random order.
+// Draws (same generator and key as Step 1, third counter word 1 and 2):
+//   sign of row i: bit i mod 128 of the four words of counter
+//     (i div 128, 0, 1, 0), as bit (i mod 32) of word ((i mod 128) div 32);
+//     the bit 0 gives +1.
+//   selection: a partial Fisher-Yates shuffle of 0..n-1; step j takes u =
+//     (x1:x0) of counter (j, 0, 2, 0) and exchanges positions j and
+//     j + (u mod (n - j)); S's column j is the index left at position j.
+// ---------------------------------------------------------------------------
+constexpr int kSelMax = 1024;          // largest l of the selection kernel
+constexpr int kSelSlots = 4 * kSelMax; // open-addressing map of moved positions (<= l used)
+
+__device__ __forceinline__ int sel_find(const int* keys, int pos) {
+  unsigned h = ((unsigned)pos * 2654435761u) & (kSelSlots - 1);
+  while (keys[h] != pos && keys[h] != -1) h = (h + 1) & (kSelSlots - 1);
+  return (int)h;
+}
+
+// One wave: the lanes draw the l words, lane 0 runs the shuffle over a map
+// of the (at most l) positions beyond the current step that it has moved;
+// untouched positions hold themselves.  Position j is final once step j is
+// done (later steps only touch positions above it), so it is never stored.
+__global__ void __launch_bounds__(64) srft_select_kernel(int64_t n, int l, uint32_t k0,
+                                                         uint32_t k1, int* __restrict__ sel) {
+  __shared__ unsigned long long u[kSelMax];
+  __shared__ int keys[kSelSlots];
+  __shared__ int vals[kSelSlots];
+  const int lane = threadIdx.x;
+  for (int j = lane; j < l; j += 64) {
+    const Words w = philox10((uint32_t)j, 0u, 2u, 0u, k0, k1);
+    u[j] = ((unsigned long long)w.x1 << 32) | w.x0;
+  }
+  for (int h = lane; h < kSelSlots; h += 64) keys[h] = -1;
+  __syncthreads();
+  if (lane == 0) {
+    for (int j = 0; j < l; ++j) {
+      const int t = j + (int)(u[j] % (unsigned long long)(n - j));
+      const int hj = sel_find(keys, j);
+      const int vj = keys[hj] == j ? vals[hj] : j;
+      const int ht = sel_find(keys, t);
+      const int vt = keys[ht] == t ? vals[ht] : t;
+      keys[ht] = t; vals[ht] = vj;   // position j is never read again: not stored
+      sel[j] = vt;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) srft_matrix_kernel(int64_t n, int l, uint32_t k0,
+                                                          uint32_t k1, const int* __restrict__ sel,
+                                                          T* __restrict__ R, int64_t ldr) {
+  const double scale = 1.0 / sqrt((double)n);
+  const int64_t total = n * (int64_t)l;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % n, j = e / n;
+    const Words w = philox10((uint32_t)(i >> 7), 0u, 1u, 0u, k0, k1);
+    const int t = (int)(i & 127);
+    const uint32_t word = t < 32 ? w.x0 : t < 64 ? w.x1 : t < 96 ? w.x2 : w.x3;
+    const double d = ((word >> (t & 31)) & 1u) ? -1.0 : 1.0;
+    const int64_t r = (i * (int64_t)sel[j]) % n;
+    double sn, cs;
+    sincospi(2.0 * (double)r / (double)n, &sn, &cs);
+    R[i + j * ldr] = (T)(d * (cs + sn) * scale);
+  }
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_srft(T* R, int64_t ldr, int64_t n, int l, uint64_t seed, int* sel,
+                       hipStream_t s) {
+  if (n <= 0 || l <= 0) return hipSuccess;
+  if (l > kSelMax || l > n || n >= (1LL << 31)) return hipErrorInvalidValue;
+  const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+  hipLaunchKernelGGL(srft_select_kernel, dim3(1), dim3(64), 0, s, n, l, k0, k1, sel);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n * l + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(srft_matrix_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, n, l, k0, k1,
+                     sel, R, ldr);
+  return hipGetLastError();
+}
+template hipError_t launch_srft<double>(double*, int64_t, int64_t, int, uint64_t, int*,
+                                        hipStream_t);
+template hipError_t launch_srft<float>(float*, int64_t, int64_t, int, uint64_t, int*, hipStream_t);
 
 template <typename T>
 hipError_t launch_gaussian(T* G, int64_t ldg, int64_t n, int64_t l, uint64_t seed,

@@ -77,6 +77,24 @@ def test_rrlu_flag_workspace_and_limits(rlu):
     assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -8
 
 
+def test_fast_flag_validation(rlu):
+    F = rlu.FLAG_FAST
+    st, plain = _ws(rlu, 3000, 2500, 50, 80)
+    st2, fast = _ws(rlu, 3000, 2500, 50, 80, flags=F)
+    assert st == 0 and st2 == 0
+    # the ID's A(J, :) (l x n) and the k x l Gram, T and W matrices
+    assert fast - plain >= 8 * (80 * 2500 + 3 * 50 * 30)
+    assert _ws(rlu, 3000, 2500, 50, 80, dtype=1, prec=1, flags=F)[0] == 0
+    assert _ws(rlu, 3000, 2500, 50, 80, flags=F | rlu.FLAG_RRLU)[0] == 0
+    assert _ws(rlu, 3000, 2500, 50, 80, G=1, ldg=2500, flags=F)[0] == -1        # caller's G
+    assert _ws(rlu, 3000, 2500, 50, 80, flags=F, power_iters=1)[0] == -1        # power scheme
+    assert _ws(rlu, 3000, 2500, 50, 80, dtype=1, prec=2, flags=F)[0] == -8      # BF16 products
+    assert _ws(rlu, 4000, 4000, 10, 1025, flags=F)[0] == -8
+    pb = rlu.Problem(300, 200, 5, 8, 0, 0, 0, None, 0, F, 0)
+    out = ctypes.c_size_t()
+    assert rlu.lib().rlu_serve_footprint(ctypes.byref(pb), ctypes.byref(out)) == -8
+
+
 def test_exchange_limit_argument_checks(rlu):
     lib = rlu.lib()
     assert lib.rlu_set_exchange_limit(None, 0, 0) == -1

@@ -63,6 +63,14 @@ def test_exp_spectrum_8192_rrlu(rlu, exp8192):
     compare_rrlu(rlu, A, k, l, G, "8192^2 exp(-i/50)")
 
 
+def test_exp_spectrum_8192_fast(rlu, exp8192):
+    """Algorithm 4.4 (fast randomized LU) at the full size, element by
+    element under the rule of test_gpu_fast."""
+    from tests.test_gpu_fast import compare_fast
+    A, k, l, _ = exp8192
+    compare_fast(rlu, A, k, l, 7208, "8192^2 exp(-i/50)")
+
+
 def test_exp_spectrum_8192_lstsq(rlu, exp8192):
     """Algorithm 4.3 on the full-size factors, as the least-squares form of
     the benchmark runs it (b = A x0): the GPU solve on the GPU factors
