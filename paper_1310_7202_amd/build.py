@@ -34,8 +34,8 @@ HIP_FLAGS = [
     "-Wno-unused-result", f"-I{INCLUDE}", f"-I{CSRC}",
 ]
 
-SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "panel_lu.hip", "spd_inverse.hip", "finish.hip",
-           "lstsq.hip", "rrlu.hip", "fast_lu.hip",
+SOURCES = ["rng.hip", "gemm.hip", "gemm_lp.hip", "gemm_lp_stream.hip", "panel_lu.hip",
+           "spd_inverse.hip", "finish.hip", "lstsq.hip", "rrlu.hip", "fast_lu.hip",
            "rlu_api.cpp", "rlu_batch.cpp", "rlu_serve.cpp"]
 HOST_SOURCES = [s for s in SOURCES if s.endswith(".cpp")]
 SAN_LIB = os.path.join(BUILD_DIR, "librlu_san.so")

@@ -489,12 +489,16 @@ size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K) {
   int ks2 = 1;
   while (t2 * ks2 < 512 && K / (ks2 * 2) >= 2048 && ks2 < 16) ks2 *= 2;
   ks = std::max(ks, ks2);
-  return ks > 1 ? (size_t)ks * (size_t)M * (size_t)N : 0;
+  size_t elems = ks > 1 ? (size_t)ks * (size_t)M * (size_t)N : 0;
+  elems = std::max(elems, stream_sketch_partial_elems(M, N, K));
+  return std::max(elems, stream_project_partial_elems(M, N, K));
 }
 
 hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   if (d.opb != OpB::Plain) return hipErrorInvalidValue;
+  if (stream_sketch_applies(d)) return launch_sketch_stream_lp(d, fp16, s);
+  if (stream_project_applies(d)) return launch_project_stream_lp(d, fp16, s);
   const bool bvec = d.ldb % 4 == 0 && aligned16(d.B);
   if (d.opa == OpA::Plain && d.K >= 1024 && d.M >= 1024 && bvec && d.lda % 4 == 0 &&
       aligned16(d.A)) {

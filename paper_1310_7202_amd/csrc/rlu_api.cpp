@@ -82,6 +82,7 @@ struct Layout {
   size_t zt = 0, z = 0, piv_z = 0, ipiv_z = 0;  // power iterations (Section 5.2)
   size_t sy = 0, rq = 0, qy = 0, yq = 0;        // rank-revealing Step 3
   size_t sel = 0, gk = 0, tb = 0, wb = 0, aj = 0;  // Algorithm 4.4
+  size_t lpw = 0;                                   // 16-bit copies of G / Lv
   BlockedPanel py{}, pb{}, pz{};
 };
 
@@ -112,12 +113,17 @@ bool plan_layout(const rlu_problem_t& pb, int cus, Layout& L) {
     part = std::max(part, gemm_auto_partial_elems(k, l, m, OpA::LvT));
     part = std::max(part, gemm_auto_partial_elems(k, n, l, OpA::Plain));
   }
-  if (pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16) {
+  const bool lp = pb.precision == RLU_PREC_MIXED_BF16 || pb.precision == RLU_PREC_MIXED_FP16;
+  size_t lpw = 0;
+  if (lp) {
     part = std::max(part, gemm_lp_partial_elems(m, l, n));
     part = std::max(part, gemm_lp_partial_elems(k, n, m));
     if (power) part = std::max(part, gemm_lp_partial_elems(l, n, m));
+    lpw = std::max(stream_sketch_ws_bytes(n, l), stream_project_ws_bytes(m, k));
+    if (power) lpw = std::max(lpw, stream_project_ws_bytes(m, l));
   }
   take(L.part, part * d);
+  take(L.lpw, lpw);
   take(L.S, (size_t)k * k * d);
   take(L.gj, spd_inverse_scratch_elems(k) * d);
   take(L.C, (size_t)k * n * d);
@@ -369,6 +375,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.B = X; d.ldb = ldx; d.opb = OpB::Plain;
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    if (lp) d.lp_ws = at<void>(ws, Ly.lpw);
     int ks = 1;
     d.no_sum = true; d.ksplit_out = &ks;
     {
@@ -391,6 +398,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.B = io.A; d.ldb = io.lda; d.opb = OpB::Plain;
     d.C = Out; d.ldc = rows;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
+    if (lp) d.lp_ws = at<void>(ws, Ly.lpw);
     int ks = 1;
     d.no_sum = true; d.ksplit_out = &ks;
     {

@@ -51,6 +51,8 @@ struct GemmDesc {
   int* ksplit_out;     // optional: receives the split used (1 = none)
   int acol0;           // LvStrict: global index of the first column of A
   bool csub;           // C -= op(A) op(B) instead of C = ... (requires ksplit 1)
+  void* lp_ws;         // low-precision products: room for the pre-converted small
+                       // operand (stream_sketch_ws_bytes / stream_project_ws_bytes)
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
@@ -70,6 +72,22 @@ hipError_t launch_splitk_sum_f64(int64_t M, int64_t N, int ksplit, const double*
 // A).  ksplit is chosen internally when `partial` is given.
 hipError_t launch_gemm_lp(const GemmDesc& d, bool fp16, hipStream_t s);
 size_t gemm_lp_partial_elems(int64_t M, int64_t N, int64_t K);
+// Streaming forms of the two low-precision passes over A (gemm_lp_stream.hip),
+// taken by launch_gemm_lp when d.lp_ws is given and the shape fits: a
+// workgroup owns 64 rows (Y = A G) or 64 columns (C = Lv^T A) of A over the
+// whole of the small dimension, so A is read once; the small operand is
+// rounded once into lp_ws.  npad / rpad: the padded small dimension (-1 when
+// it exceeds the compiled widths).
+int64_t stream_sketch_npad(int64_t N);
+size_t stream_sketch_ws_bytes(int64_t K, int64_t N);
+size_t stream_sketch_partial_elems(int64_t M, int64_t N, int64_t K);
+bool stream_sketch_applies(const GemmDesc& d);
+hipError_t launch_sketch_stream_lp(const GemmDesc& d, bool fp16, hipStream_t s);
+int64_t stream_project_rpad(int64_t R);
+size_t stream_project_ws_bytes(int64_t K, int64_t R);
+size_t stream_project_partial_elems(int64_t R, int64_t N, int64_t K);
+bool stream_project_applies(const GemmDesc& d);
+hipError_t launch_project_stream_lp(const GemmDesc& d, bool fp16, hipStream_t s);
 // Tuning override of the tile shape (index into the compiled shapes; -1 = automatic).
 void gemm_force_config(int id);
 // Grouped form: many independent products in one launch.  Each workgroup
