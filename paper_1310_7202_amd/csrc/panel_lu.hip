@@ -14,13 +14,14 @@
 //     lowest-position tie break) and the step that chose it.
 //   * step j: wave 0 brings column j up to date, finds the workgroup's best
 //     candidate (largest magnitude, lowest current position on ties) and
-//     publishes its key (magnitude, position, row) and a short header: its
-//     value in column j, its multiplier of step j-1 and its value in column
-//     j+1 *one update behind* (through step j-2); the bulk waves publish the
-//     rest of the candidate's row, also one update behind.  Every workgroup
-//     polls the dense array of keys, selects the same winner, reads only the
-//     winner's header, fetches the winner's row into LDS by the next step
-//     and completes the winner's row itself,
+//     publishes its key: the candidate's value in column j (whose magnitude
+//     ranks it), position and row, its multiplier of step j-1 and its value
+//     in column j+1 *one update behind* (through step j-2); the bulk waves
+//     publish the rest of the candidate's row, also one update behind.
+//     Every workgroup polls the dense array of keys, selects the same
+//     winner (whose key already carries everything the step needs from it,
+//     so one device round trip decides the step); at the next step the bulk
+//     waves fetch the winner's row and complete it themselves,
 //         U(j, c) = row(c) - l(j-1) U(j-1, c),
 //     with the same fused multiply-add the winner's own workgroup applies to
 //     its copy, so all copies agree bitwise.  Publishing the row one update
@@ -31,13 +32,13 @@
 //     in its upper half and 32 bits of payload in its lower half (a double
 //     takes two words).  Words are written and read with device-coherent
 //     (agent-scope) relaxed atomic accesses, whose 64-bit single-copy
-//     atomicity is all the protocol relies on: a reader accepts a key, header
+//     atomicity is all the protocol relies on: a reader accepts a key
 //     or row entry only when every word it needs shows the current tag, so no
 //     store ordering, fence or cache maintenance is needed and the writer
 //     never waits.  Buffers rotate by step mod 3: a workgroup publishes step
 //     j+3 only after the exchange of step j+2, which needs every workgroup's
 //     step j+2 key, which each publishes only after it finished reading the
-//     buffers of step j (keys and header in its exchange, the winner's row in
+//     buffers of step j (the keys in its exchange, the winner's row in
 //     its bulk update of step j+1).
 //   * every wait is bounded by a wall-clock limit of its own (the clock
 //     starts at the wait's first unsuccessful poll, so a long batched launch
@@ -46,45 +47,57 @@
 #include "rlu_device.h"
 #include "rlu_kernels.h"
 
+#include <algorithm>
 #include <climits>
+#include <cstdlib>
 
 namespace rlu {
 namespace {
 
 // Threads per workgroup: 16 waves (one pivot wave, 15 bulk waves) when a
-// lane holds at most two rows (four waves per SIMD fit the registers), else 8.
+// lane holds one row (four waves per SIMD fit the registers), else 8 (two
+// per SIMD, room for a whole poll of the exchange in flight).
 template <int RPL>
-constexpr int threads_for() { return RPL <= 2 ? 1024 : 512; }
-inline int threads_for_rows(int R) { return R <= 128 ? 1024 : 512; }
+constexpr int threads_for() { return RPL <= 1 ? 1024 : 512; }
+inline int threads_for_rows(int R) { return R <= 64 ? 1024 : 512; }
 constexpr int kNone = INT_MAX;
 
-// Exchange buffer of a step: first a dense key area, 4 words per workgroup
-// ([0,1] candidate magnitude, [2] current position, [3] original row or -1),
-// which every workgroup polls; then one record per workgroup: 6 header
-// words ([0,1] value in column j, [2,3] multiplier of step j-1, [4,5] value
-// in column j+1, one update behind like the row), read for the winner only,
-// and 2 words per column of the candidate's row (entries from column j+2 on,
-// written at step j by the bulk waves).
-constexpr int kKeyWords = 4;
-constexpr int kHdrWords = 6;
+// Exchange buffer of a step: first a dense key area, 8 words per workgroup
+// ([0,1] the candidate's value in column j, [2] its current position, [3]
+// its original row or -1 for none, [4,5] its multiplier of step j-1, [6,7]
+// its value in column j+1, one update behind like the row), which every
+// workgroup polls; then one record per workgroup: 2 words per column of the
+// candidate's row (entries from column j+2 on, written at step j by the
+// bulk waves), read for the winner only.
+constexpr int kKeyWords = 8;
+constexpr int kHdrWords = 0;
 
 __host__ __device__ __forceinline__ int64_t key_area_bytes(int nwg) {
   return (8 * (int64_t)kKeyWords * nwg + 127) / 128 * 128;
 }
 
-__device__ __forceinline__ void put32(unsigned long long* w, unsigned tag, unsigned v) {
-  st_agent(w, ((unsigned long long)tag << 32) | v);
+// Two tagged words (16 bytes, word index w) of an exchange buffer, moved
+// with one device-coherent (sc1) buffer access, as the relaxed agent-scope
+// 8-byte accesses are: half the requests.  Each 8-byte half is moved whole
+// and carries its own tag, so a reader may pair halves of different steps
+// only to reject them.  In a loaded value, .x/.y are the first word's
+// payload and tag, .z/.w the second's.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kCoherent = 16;  // sc1
+__device__ __forceinline__ Rsrc rsrc_of(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0,
+                                           (int)(bytes < INT_MAX ? bytes : INT_MAX), 0x00020000);
 }
-__device__ __forceinline__ void put64(unsigned long long* w, unsigned tag, unsigned long long v) {
-  st_agent(w, ((unsigned long long)tag << 32) | (v & 0xffffffffull));
-  st_agent(w + 1, ((unsigned long long)tag << 32) | (v >> 32));
+__device__ __forceinline__ u32x4 ld_words2(Rsrc r, int w) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, w * 8, 0, kCoherent);
 }
-__device__ __forceinline__ bool tagged(unsigned long long x, unsigned tag) {
-  return (unsigned)(x >> 32) == tag;
+__device__ __forceinline__ void st_words2(Rsrc r, int w, unsigned tag, unsigned p0, unsigned p1) {
+  __builtin_amdgcn_raw_buffer_store_b128(u32x4{p0, tag, p1, tag}, r, w * 8, 0, kCoherent);
 }
-__device__ __forceinline__ unsigned long long join64(unsigned long long lo,
-                                                     unsigned long long hi) {
-  return (lo & 0xffffffffull) | (hi << 32);
+__device__ __forceinline__ bool tagged2(u32x4 v, unsigned tag) { return v.y == tag && v.w == tag; }
+__device__ __forceinline__ unsigned long long payload2(u32x4 v) {
+  return ((unsigned long long)v.z << 32) | v.x;
 }
 
 __device__ __forceinline__ unsigned long long dbits(double x) {
@@ -164,19 +177,20 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 //
 // Step j, with U(i, .) the U row of step i (the winner's row through step
 // i-1) kept in a two-slot ring urow[i & 1]:
-//   wave 0      U(j-1, j) from the step j-1 header; column j brought up to
-//               date; local candidate; header and key published; the
-//               step j-1 winner's row (loads issued at step j-1) into
-//               LDS                                                   | B1 |
-//               wait for all keys, select the winner, read its header,
-//               issue the loads of its row, bookkeeping, multipliers
-//               of step j                                             | B0 |
-//   bulk waves  publish their columns of the local candidate's row,  | B1 |
+//   wave 0      U(j-1, j) from the step j-1 key; column j brought up to
+//               date; local candidate; its key published          | B1 |
+//               wait for all keys, select the winner (its key holds
+//               everything wave 0 needs from it), bookkeeping,
+//               multipliers of step j                                 | B0 |
+//   bulk waves  start loading their columns of the step j-1 winner's
+//               row                                                   | B1 |
+//               publish their columns of the local candidate's row,
 //               complete U(j-1, c) for their own columns c > j from
-//               LDS, then the rank-one update of step j-1 on them     | B0 |
-// so the only device round trips on wave 0's path are the key exchange and
-// one header read; the row fetch spans a whole step, and the bulk waves
-// touch no device memory but their own publication.
+//               the loaded row, then the rank-one update of step j-1
+//               on them                                               | B0 |
+// so the only device round trip on wave 0's path is the key exchange; the
+// bulk waves' own round trip (the winner's row) overlaps wave 0's work
+// before B1 and its exchange after it.
 // A bound on one wait: its clock starts at the wait's first unsuccessful
 // poll (so a wait that succeeds at once never reads the clock) and the wait
 // gives up once more than `tmo` ticks have passed since then.
@@ -192,7 +206,7 @@ struct WaitLimit {
   }
 };
 
-template <int RPL>
+template <int RPL, int kThreads>
 __device__ __forceinline__ void panel_body(
     double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols, int R, int nwg,
     int* __restrict__ pos_out, int* __restrict__ rstep_out, int* __restrict__ piv_row_out,
@@ -200,7 +214,6 @@ __device__ __forceinline__ void panel_body(
     char* __restrict__ xch, int64_t rec_stride, long long timeout_ticks, int w, double* smem,
     int step0, int total_cols, const int* __restrict__ pos_in,
     const int* __restrict__ rstep_in) {
-  constexpr int kThreads = threads_for<RPL>();
   double* Ts = smem;                        // R x ncols, column-major (ld R)
   double* urow = Ts + (int64_t)R * ncols;   // 2 x ncols: U rows by step parity
   double* lbody = urow + 2 * ncols;         // 2 x ncols: single-workgroup "records"
@@ -276,12 +289,14 @@ __device__ __forceinline__ void panel_body(
   int info = 0;
   __syncthreads();
 
-  // wave 0: words of the last winner's row (columns from two past its
-  // step), loaded after its exchange and landed in LDS at the next step
+  constexpr int kBW = kThreads / 64 - 1;  // bulk waves
+  // wave 0: the last winner's row (columns from two past its step), 16
+  // bytes (two tagged words) per column, loaded after its exchange and
+  // landed in LDS at the next step
   constexpr int kPF = 4;
-  unsigned long long bl[kPF], bh[kPF];
+  u32x4 brow_w[kPF];
 #pragma unroll
-  for (int t = 0; t < kPF; ++t) bl[t] = bh[t] = 0;
+  for (int t = 0; t < kPF; ++t) brow_w[t] = u32x4{0u, 0u, 0u, 0u};
   for (int j = 0; j < ncols; ++j) {
     const int sj = j & 1, sp = sj ^ 1;
     double* Uj = urow + sj * ncols;   // U(j, .); until overwritten it still holds U(j-2, .)
@@ -303,7 +318,7 @@ __device__ __forceinline__ void panel_body(
         uj = upd2 ? __fma_rn(-sh_lm[sp], Uj[j], sh_v1[sp]) : sh_v1[sp];
         if (lane == 0) Up[j] = uj;
       }
-      // each lane's best row, with what the header needs from it
+      // each lane's best row, with what its key carries
       double a = -1.0, bv = 0.0, blm = 0.0, bn = 0.0;
       int p = INT_MAX, r = -1;
       // (straight-line: loads for every lane, clamped to the stored rows,
@@ -348,15 +363,12 @@ __device__ __forceinline__ void panel_body(
       // waves after B1, before they update it)
       if (lane == 0) sh_cr = r;
       if (nwg > 1) {
-        if (lane == 0) {
-          unsigned long long* rec = (unsigned long long*)(recs + (int64_t)w * rec_stride);
-          unsigned long long* key = (unsigned long long*)base + kKeyWords * w;
-          put64(rec + 0, tag, dbits(cpiv));
-          put64(rec + 2, tag, dbits(lm));
-          put64(rec + 4, tag, dbits(cv1));
-          put64(key + 0, tag, dbits(a));
-          put32(key + 2, tag, (unsigned)p);
-          put32(key + 3, tag, (unsigned)(r >= 0 ? row0 + r : -1));
+        // the key: lanes 0-3 store its four word pairs in one instruction
+        if (lane < 4) {
+          const unsigned long long b = lane == 0 ? dbits(cpiv) : lane == 2 ? dbits(lm) : dbits(cv1);
+          const unsigned p0 = lane == 1 ? (unsigned)p : (unsigned)b;
+          const unsigned p1 = lane == 1 ? (unsigned)(r >= 0 ? row0 + r : -1) : (unsigned)(b >> 32);
+          st_words2(rsrc_of(base, key_area_bytes(nwg)), kKeyWords * w + 2 * lane, tag, p0, p1);
         }
       } else {
         if (lane == 0) {
@@ -366,41 +378,38 @@ __device__ __forceinline__ void panel_body(
       }
       if (nwg > 1 && upd1) {
         // ---- (1b) the step j-1 winner's row, columns j+1 on, into LDS for
-        // the bulk waves (fetched after that step's exchange; one poll per
-        // word normally finds it there)
-        const unsigned long long* pbody =
-            (const unsigned long long*)(precs + (int64_t)sh_bw[sp] * rec_stride) + kHdrWords;
+        // the bulk waves (loaded after that step's exchange; one poll per
+        // column normally finds it there)
+        const Rsrc pb = rsrc_of(precs + (int64_t)sh_bw[sp] * rec_stride, rec_stride);
         bool stop = false;
 #pragma unroll
         for (int t = 0; t < kPF; ++t) {
           const int c = j + 1 + lane + 64 * t;
           if (c < ncols && !stop) {
-            unsigned long long lo = bl[t], hi = bh[t];
+            u32x4 v = brow_w[t];
             WaitLimit wl;
-            while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
+            while (!tagged2(v, (unsigned)j)) {
               if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
                 stop = true;
                 break;
               }
-              lo = ld_agent(pbody + 2 * c);
-              hi = ld_agent(pbody + 2 * c + 1);
+              v = ld_words2(pb, kHdrWords + 2 * c);
             }
-            lbody[sp * ncols + c] = bitsd(join64(lo, hi));
+            lbody[sp * ncols + c] = bitsd(payload2(v));
           }
         }
         // columns past the prefetched ones (panels wider than 64 kPF)
         for (int c = j + 1 + 64 * kPF + lane; c < ncols && !stop; c += 64) {
-          unsigned long long lo = ld_agent(pbody + 2 * c), hi = ld_agent(pbody + 2 * c + 1);
+          u32x4 v = ld_words2(pb, kHdrWords + 2 * c);
           WaitLimit wl;
-          while (!(tagged(lo, (unsigned)j) && tagged(hi, (unsigned)j))) {
+          while (!tagged2(v, (unsigned)j)) {
             if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
               stop = true;
               break;
             }
-            lo = ld_agent(pbody + 2 * c);
-            hi = ld_agent(pbody + 2 * c + 1);
+            v = ld_words2(pb, kHdrWords + 2 * c);
           }
-          lbody[sp * ncols + c] = bitsd(join64(lo, hi));
+          lbody[sp * ncols + c] = bitsd(payload2(v));
         }
         if (__any(stop)) {
           if (lane == 0) { st_agent_i(fail, 1); sh_stop = 1; }
@@ -411,59 +420,75 @@ __device__ __forceinline__ void panel_body(
     if (sh_stop) break;
 
     if (wave == 0) {
-      // ---- (3) exchange: wait for every header, select the winner ---------------
+      // ---- (3) exchange: wait for every key, select the winner ------------------
       int win_row = -1, win_pos = INT_MAX, bw = -1;
       double piv = 0.0, wlm = 0.0, wv1 = 0.0;
       bool stop = false;
       if (nwg > 1) {
         // every lane polls the keys of workgroups lane, lane + 64, ...
-        // (nwg <= 256), then all read the winner's header words
-        const int nq = (nwg + 63) / 64;
-        double qa[4];
-        int qp[4], qrow[4];
-        unsigned seen = 0, need = 0;
+        // (nwg <= 256) and folds each into its running best as it arrives
+        // (candidates' positions differ, so the order of arrival does not
+        // change the result)
+        const int nq = __builtin_amdgcn_readfirstlane((nwg + 63) / 64);
+        double ba = -1.0, bv = 0.0, blm = 0.0, bv1 = 0.0;
+        int bp = INT_MAX, brow = -1;
+        // done: slots read (or with nothing to read) by this lane
+        unsigned done = 0xFu;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          qa[q] = -1.0; qp[q] = INT_MAX; qrow[q] = -1;
-          if (q < nq && lane + 64 * q < nwg) need |= 1u << q;
-        }
+        for (int q = 0; q < 4; ++q)
+          if (q < nq && lane + 64 * q < nwg) done &= ~(1u << q);
         WaitLimit wl;
         while (true) {
+          // the loads of a poll are issued before any is examined, two
+          // slots at a time (what the registers hold beside the rest): one
+          // round trip per poll up to 128 workgroups
+          constexpr int kCh = kThreads == 512 && RPL <= 4 ? 4 : 2;
+          const Rsrc kr = rsrc_of(base, key_area_bytes(nwg));
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if ((need >> q & 1u) && !(seen >> q & 1u)) {
-              const unsigned long long* k =
-                  (const unsigned long long*)base + kKeyWords * (lane + 64 * q);
-              unsigned long long x[kKeyWords];
+          for (int c0 = 0; c0 < 4; c0 += kCh) {
+            u32x4 x[kCh][kKeyWords / 2];
+            bool poll[kCh];
 #pragma unroll
-              for (int t = 0; t < kKeyWords; ++t) x[t] = ld_agent(k + t);
-              bool ok = true;
+            for (int i = 0; i < kCh; ++i) {
+              const int q = c0 + i;
+              poll[i] = q < nq && !__all((done >> q) & 1u);  // uniform
+              if (poll[i]) {
+                const int wq = min(lane + 64 * q, nwg - 1);
 #pragma unroll
-              for (int t = 0; t < kKeyWords; ++t) ok = ok && tagged(x[t], tag);
-              if (ok) {
-                seen |= 1u << q;
-                qa[q] = bitsd(join64(x[0], x[1]));
-                qp[q] = (int)(unsigned)x[2];
-                qrow[q] = (int)(unsigned)x[3];
+                for (int t = 0; t < kKeyWords / 2; ++t) x[i][t] = ld_words2(kr, kKeyWords * wq + 2 * t);
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < kCh; ++i) {
+              const int q = c0 + i;
+              if (poll[i]) {
+                bool ok = !((done >> q) & 1u);
+#pragma unroll
+                for (int t = 0; t < kKeyWords / 2; ++t) ok = ok && tagged2(x[i][t], tag);
+                done |= ok ? 1u << q : 0u;
+                // the magnitude the candidate was chosen by (NaN above every
+                // number); a workgroup without a candidate ranks below all
+                const double v = bitsd(payload2(x[i][0]));
+                const int qp = (int)x[i][1].x, qrow = (int)x[i][1].z;
+                const double qa = qrow < 0 ? -1.0 : (v != v ? __builtin_inf() : fabs(v));
+                const bool take = ok && (bw < 0 || better(qa, qp, ba, bp));
+                ba = take ? qa : ba;
+                bp = take ? qp : bp;
+                brow = take ? qrow : brow;
+                bw = take ? lane + 64 * q : bw;
+                bv = take ? v : bv;
+                blm = take ? bitsd(payload2(x[i][2])) : blm;
+                bv1 = take ? bitsd(payload2(x[i][3])) : bv1;
               }
             }
           }
-          if (__all(seen == need)) break;
+          if (__all(done == 0xFu)) break;
           if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
             stop = true;
             break;
           }
         }
         if (!stop) {
-          double ba = -1.0; int bp = INT_MAX, brow = -1;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const bool take = (need >> q & 1u) && (bw < 0 || better(qa[q], qp[q], ba, bp));
-            ba = take ? qa[q] : ba;
-            bp = take ? qp[q] : bp;
-            brow = take ? qrow[q] : brow;
-            bw = take ? lane + 64 * q : bw;
-          }
           const int src = wave_best_lane(ba, bp);
           ba = lane_bcast(ba, src);
           bp = __builtin_amdgcn_readlane(bp, src);
@@ -475,35 +500,17 @@ __device__ __forceinline__ void panel_body(
             win_row = brow;
             win_pos = bp;
             if (win_row < 0) stop = true;
-            // the winner's header (same words in every lane)
-            const unsigned long long* h =
-                (const unsigned long long*)(recs + (int64_t)bw * rec_stride);
-            unsigned long long x[kHdrWords];
-            WaitLimit wh;
-            while (!stop) {
-              bool ok = true;
-#pragma unroll
-              for (int t = 0; t < kHdrWords; ++t) x[t] = ld_agent(h + t);
-#pragma unroll
-              for (int t = 0; t < kHdrWords; ++t) ok = ok && tagged(x[t], tag);
-              if (__all(ok)) break;
-              if (wh.expired(timeout_ticks) || ld_agent_i(fail) != 0) stop = true;
-            }
             if (!stop) {
-              piv = bitsd(join64(x[0], x[1]));
-              wlm = bitsd(join64(x[2], x[3]));
-              wv1 = bitsd(join64(x[4], x[5]));
-              // start fetching the winner's row (columns j+2 on): the bulk
+              piv = lane_bcast(bv, src);
+              wlm = lane_bcast(blm, src);
+              wv1 = lane_bcast(bv1, src);
+              // start loading the winner's row (columns j+2 on): the bulk
               // waves need it at the next step
-              const unsigned long long* wb =
-                  (const unsigned long long*)(recs + (int64_t)bw * rec_stride) + kHdrWords;
+              const Rsrc wb = rsrc_of(recs + (int64_t)bw * rec_stride, rec_stride);
 #pragma unroll
               for (int t = 0; t < kPF; ++t) {
-                const int c = j + 2 + lane + 64 * t;
-                if (c < ncols) {
-                  bl[t] = ld_agent(wb + 2 * c);
-                  bh[t] = ld_agent(wb + 2 * c + 1);
-                }
+                const int c = min(j + 2 + lane + 64 * t, ncols - 1);
+                brow_w[t] = ld_words2(wb, kHdrWords + 2 * c);
               }
             }
           }
@@ -568,13 +575,16 @@ __device__ __forceinline__ void panel_body(
       const int rc = sh_cr;
       if (rc >= 0) {
         constexpr int kBWp = kThreads / 64 - 1;
-        unsigned long long* body =
-            (unsigned long long*)(recs + (int64_t)w * rec_stride) + kHdrWords;
+        const Rsrc body = rsrc_of(recs + (int64_t)w * rec_stride, rec_stride);
         for (int c = j + 1 + (wave - 1) + kBWp * lane; c < ncols; c += kBWp * 64) {
           if (c < j + 2) continue;
           const double v = Ts[(int64_t)c * R + rc];
-          if (nwg > 1) put64(body + 2 * c, tag, dbits(v));
-          else lbody[sj * ncols + c] = v;
+          if (nwg > 1) {
+            const unsigned long long b = dbits(v);
+            st_words2(body, kHdrWords + 2 * c, tag, (unsigned)b, (unsigned)(b >> 32));
+          } else {
+            lbody[sj * ncols + c] = v;
+          }
         }
       }
     }
@@ -584,7 +594,6 @@ __device__ __forceinline__ void panel_body(
       // c = j + w + (waves - 1) t: it completes U(j-1, c) from the
       // winner's row, one update behind, with the same fused multiply-add
       // the winner's own workgroup applies, then updates those columns.
-      constexpr int kBW = kThreads / 64 - 1;
       {
         // the winner's row is in LDS (landed by wave 0 before B1, or
         // written by this workgroup itself when it is alone)
@@ -696,7 +705,8 @@ panel_lu_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int n
                 int64_t rec_stride, long long timeout_ticks, int step0, int total_cols,
                 const int* __restrict__ pos_in, const int* __restrict__ rstep_in) {
   extern __shared__ double smem[];
-  panel_body<RPL>(X, rs, cs, nrows, ncols, R, nwg, pos_out, rstep_out, piv_row_out, ipiv_out,
+  panel_body<RPL, threads_for<RPL>()>(X, rs, cs, nrows, ncols, R, nwg, pos_out, rstep_out,
+                                      piv_row_out, ipiv_out,
                   info_out, fail, xch, rec_stride, timeout_ticks, (int)blockIdx.x, smem,
                   step0, total_cols, pos_in, rstep_in);
 }
@@ -715,9 +725,10 @@ panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __res
     const int e = sched[(int64_t)r * nslots + blockIdx.x];
     if (e < 0) continue;
     const PanelTaskDev t = tasks[e >> 8];
-    panel_body<RPL>(t.X, t.rs, t.cs, t.nrows, t.ncols, t.R, t.nwg, t.pos, t.rstep, t.piv_row,
-                    t.ipiv, t.info, t.fail, t.xch, t.rec_stride, timeout_ticks, e & 255, smem,
-                    0, t.ncols, nullptr, nullptr);
+    panel_body<RPL, threads_for<RPL>()>(t.X, t.rs, t.cs, t.nrows, t.ncols, t.R, t.nwg,
+                                                t.pos, t.rstep, t.piv_row, t.ipiv, t.info,
+                                                t.fail, t.xch, t.rec_stride, timeout_ticks,
+                                                e & 255, smem, 0, t.ncols, nullptr, nullptr);
     __syncthreads();
   }
 }
@@ -734,20 +745,39 @@ int64_t rec_stride_for(int ncols) {
 
 }  // namespace
 
+// Workgroups a panel aims at (rows per workgroup permitting): 128, or the
+// tuning override RLU_PANEL_WG_CAP (16 .. 256) read once per process.
+int panel_wg_cap() {
+  static const int cap = [] {
+    const char* e = std::getenv("RLU_PANEL_WG_CAP");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 16 && v <= 256 ? v : 128;
+  }();
+  return cap;
+}
+
 PanelPlan panel_plan(int nrows, int ncols, int device_cus, int /*max_wg_per_cu_hint*/) {
   PanelPlan p{};
   p.ok = false;
   if (nrows <= 0 || ncols <= 0 || ncols > nrows) return p;
-  // largest row block that fits the LDS (leaving room for static shared data)
+  // the LDS holds R rows of the panel (leaving room for static shared data)
   const size_t budget = kLdsLimit - 1024;
-  if ((size_t)5 * ncols * 8 >= budget) return p;
-  int R = (int)((budget - (size_t)5 * ncols * 8) / ((size_t)ncols * 8 + 8));
-  if (R > 512) R = 512;  // at most 8 rows per lane
-  if (R < 1) return p;
-  int nwg = (nrows + R - 1) / R;
-  // spread the rows evenly over that many workgroups
-  R = (nrows + nwg - 1) / nwg;
-  nwg = (nrows + R - 1) / R;
+  auto fits = [&](int rows) { return lds_for(rows, ncols) <= budget; };
+  int R, nwg;
+  if (nrows <= 512 && fits(nrows)) {
+    // one workgroup: the exchange stays in LDS
+    R = nrows;
+    nwg = 1;
+  } else {
+    // a multiple of 64 rows per workgroup (every lane holds real rows) and
+    // at most 128 workgroups while 512 rows allow it: each step every
+    // workgroup reads every key, so fewer workgroups make a cheaper
+    // exchange, and a lane then watches at most two of them
+    const int per = (nrows + panel_wg_cap() - 1) / panel_wg_cap();
+    R = std::min(512, (per + 63) / 64 * 64);
+    if (!fits(R)) return p;  // narrower column blocks
+    nwg = (nrows + R - 1) / R;
+  }
   // one workgroup per CU is what the LDS footprint guarantees; four records
   // per lane bound the exchange width
   if (nwg > device_cus || nwg > 256) return p;
@@ -817,7 +847,8 @@ int panel_batched_slots(int max_R, size_t lds_bytes, int cus) {
       hipSuccess)
     return 0;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_for_rows(max_R), lds_bytes) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads_for_rows(max_R),
+                                                   lds_bytes) !=
       hipSuccess)
     return 0;
   return per_cu * cus;
@@ -835,7 +866,8 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
                                      (int)lds_bytes);
   if (e != hipSuccess) return e;
   void* args[] = {&tasks, &sched, &rounds, &nslots, &timeout_ticks};
-  return hipLaunchKernel(fn, dim3(nslots), dim3(threads_for_rows(max_R)), args, lds_bytes, s);
+  return hipLaunchKernel(fn, dim3(nslots), dim3(threads_for_rows(max_R)), args, lds_bytes,
+                         s);
 }
 
 // ---------------------------------------------------------------------------
