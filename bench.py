@@ -341,9 +341,11 @@ KERNEL_NAMES = {
              "project_gemm": "gemm_kernel, C = Lv^T A (Step 5), FP32 MFMA 16x16x4"},
     "bf16": {"panel_lu_kernel": "panel_lu_kernel (partial-pivot LU of Y, Step 3, and of B^T, "
                                 "Step 6; one persistent launch per column block)",
-             "sketch_gemm": "gemm_lp2_kernel, Y = A G (Step 2), BF16 MFMA 16x16x32, FP32 A",
-             "project_gemm": "gemm_lp2_kernel, C = Lv^T A (Step 5), BF16 MFMA 16x16x32, "
-                             "FP64 Lv as a hi + lo pair"},
+             "sketch_gemm": "sketch_stream_kernel, Y = A G (Step 2), BF16 MFMA 16x16x32, FP32 A "
+                            "read once (64 rows x all of l per workgroup)",
+             "project_gemm": "project_stream_kernel, C = Lv^T A (Step 5), BF16 MFMA 16x16x32, "
+                             "FP64 Lv as a hi + lo pair, FP32 A read once (64 columns x all "
+                             "of k per workgroup)"},
 }
 SRC = os.path.join(ROOT, "paper_1310_7202_amd", "csrc")
 
@@ -353,7 +355,7 @@ def measured_traffic(workload, prod):
     workload (None where none was taken on the current kernel source)."""
     out = {"panel_lu_kernel": traffic_from_profiles(f"traffic_panel_lu_{workload}.md",
                                                     os.path.join(SRC, "panel_lu.hip"))}
-    gsrc = os.path.join(SRC, "gemm_lp.hip" if prod in ("bf16", "fp16") else "gemm.hip")
+    gsrc = os.path.join(SRC, "gemm_lp_stream.hip" if prod in ("bf16", "fp16") else "gemm.hip")
     out["sketch_gemm"] = traffic_from_profiles(f"traffic_sketch_gemm_{workload}.md", gsrc)
     out["project_gemm"] = traffic_from_profiles(f"traffic_project_gemm_{workload}.md", gsrc)
     return out
@@ -624,7 +626,36 @@ def run_batch(rlu, torch, np, steps, warmup):
         "sequential_rlu_factor": {"factorizations_per_s": count / seq, "ms_total": seq * 1e3},
         "exchange_failures": int((infos[:, 2] != 0).sum()),
         "graph": "one captured HIP graph per batch, replayed",
+        "bf16_low_rank": bf16_low_rank_excess(rlu, torch, items[:16], stream),
     }
+
+
+def bf16_low_rank_excess(rlu, torch, items, stream):
+    """The BF16 form on problems of this low-rank recipe (k = r): its
+    relative residual against the FP32 form's on the same problems.  With
+    partial pivoting in Step 3 the factors are the orthogonal projection of
+    A onto range(A G(:, 1:k)), a range finder without oversampling, and
+    rounding A to 8 significant bits leaves a flat tail (sigma_{k+1} about
+    6e-4 sigma_1) that it amplifies tens to hundreds of times, so the BF16
+    form misses the 1e-3 residual rule here; reported, not hidden."""
+    outs, hs = {}, []
+    for prec in (rlu.PREC_FP32, rlu.PREC_MIXED_BF16):
+        hs.append(rlu.Handle(0))
+        outs[prec] = rlu.Batch(items, precision=prec).run(hs[-1], stream)
+    torch.cuda.synchronize()
+    for h in hs:
+        h.close()
+    ex = []
+    for (A, k, l, sd), f32, b16 in zip(items, outs[rlu.PREC_FP32], outs[rlu.PREC_MIXED_BF16]):
+        r32 = power_residual(A, f32.L, f32.U, f32.p, f32.q)
+        r16 = power_residual(A, b16.L, b16.U, b16.p, b16.q)
+        ex.append((r16 - r32, r16, r32))
+    worst = max(ex)
+    log(f"batch bf16 low-rank: worst residual excess over FP32 {worst[0]:.3e} "
+        f"(bf16 {worst[1]:.3e}, fp32 {worst[2]:.3e})")
+    return {"problems": len(items), "worst_excess_vs_fp32": worst[0],
+            "bf16_residual": worst[1], "fp32_residual": worst[2],
+            "meets_1e-3_rule": bool(worst[0] <= 1e-3)}
 
 
 def make_mixed_input(torch, kind="spectral"):

@@ -875,53 +875,66 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
 // the U rows of the block's pivots for the columns to its right,
 //   L11 U12 = X(pr, c1:),   L11(j, i) = X(pr_j, c0 + i) for i < j (unit lower),
 // with pr_j = piv_row[j] the row chosen at step c0 + j.  Workgroup b solves
-// 64 right-hand-side columns with U12 in LDS, 16 rows at a time: the
-// product with the rows already solved by all 256 threads, then the 16 x 16
-// triangle by one wave.  Output U (w x nrhs, leading dimension w).
+// 32 right-hand-side columns with U12 in LDS, 16 rows at a time: the 16 rows
+// of L11 the step needs are first gathered into LDS by all threads (the
+// solve's dependency chain then only touches LDS), then the product with
+// the rows already solved by all 256 threads, then the 16 x 16 triangle by
+// one wave.  Output U (w x nrhs, leading dimension w).
 // ---------------------------------------------------------------------------
 constexpr int kTrsmMaxW = 288;
+constexpr int kTrsmCols = 32;
 
 __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restrict__ X, int64_t ldx,
                                                          const int* __restrict__ piv_row, int c0,
                                                          int w, int64_t c1, int nrhs,
                                                          double* __restrict__ U) {
-  extern __shared__ double Us[];  // w x 64, row-major
+  extern __shared__ double sm[];
+  double* Us = sm;                     // w x kTrsmCols, row-major
+  double* Ls = sm + w * kTrsmCols;     // 16 x w: rows J0 .. J0+15 of L11, row-major
+  __shared__ int prow_s[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int cc0 = 64 * blockIdx.x;
-  const int jj = tid >> 4, cg = tid & 15;
+  const int cc0 = kTrsmCols * blockIdx.x;
+  const int jj = tid >> 4, cg = tid & 15;  // a row of the block, two columns (cg, cg + 16)
   for (int J0 = 0; J0 < w; J0 += 16) {
-    const int h = min(16, w - J0);
+    const int h = min(16, w - J0), len = J0 + h;
+    if (tid < h) prow_s[tid] = piv_row[J0 + tid];
+    __syncthreads();
+    for (int e = tid; e < h * len; e += 256) {
+      const int r = e / len, i = e % len;
+      Ls[r * w + i] = X[(int64_t)prow_s[r] + (int64_t)(c0 + i) * ldx];
+    }
+    __syncthreads();
     if (jj < h) {
-      const int64_t prow = piv_row[J0 + jj];
-      double acc[4];
+      const int64_t prow = prow_s[jj];
+      double acc[2];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const int c = cc0 + cg + 16 * q;
         acc[q] = c < nrhs ? X[prow + (c1 + c) * ldx] : 0.0;
       }
+      const double* lr = Ls + jj * w;
       for (int i = 0; i < J0; ++i) {
-        const double l = X[prow + (int64_t)(c0 + i) * ldx];
+        const double l = lr[i];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = __fma_rn(-l, Us[i * 64 + cg + 16 * q], acc[q]);
+        for (int q = 0; q < 2; ++q) acc[q] = __fma_rn(-l, Us[i * kTrsmCols + cg + 16 * q], acc[q]);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) Us[(J0 + jj) * 64 + cg + 16 * q] = acc[q];
+      for (int q = 0; q < 2; ++q) Us[(J0 + jj) * kTrsmCols + cg + 16 * q] = acc[q];
     }
     __syncthreads();
-    if (wave == 0) {
+    if (wave == 0 && lane < kTrsmCols) {
       for (int r = 1; r < h; ++r) {
-        const int64_t prow = piv_row[J0 + r];
-        double u = Us[(J0 + r) * 64 + lane];
+        double u = Us[(J0 + r) * kTrsmCols + lane];
         for (int i = 0; i < r; ++i)
-          u = __fma_rn(-X[prow + (int64_t)(c0 + J0 + i) * ldx], Us[(J0 + i) * 64 + lane], u);
-        Us[(J0 + r) * 64 + lane] = u;
+          u = __fma_rn(-Ls[r * w + J0 + i], Us[(J0 + i) * kTrsmCols + lane], u);
+        Us[(J0 + r) * kTrsmCols + lane] = u;
       }
     }
     __syncthreads();
   }
-  for (int e = tid; e < w * 64; e += 256) {
-    const int j = e / 64, c = e % 64;
-    if (cc0 + c < nrhs) U[j + (int64_t)(cc0 + c) * w] = Us[j * 64 + c];
+  for (int e = tid; e < w * kTrsmCols; e += 256) {
+    const int j = e / kTrsmCols, c = e % kTrsmCols;
+    if (cc0 + c < nrhs) U[j + (int64_t)(cc0 + c) * w] = Us[j * kTrsmCols + c];
   }
 }
 
@@ -929,12 +942,12 @@ hipError_t launch_block_trsm(const double* X, int64_t ldx, const int* piv_row, i
                              int64_t c1, int nrhs, double* U, hipStream_t s) {
   if (w <= 0 || nrhs <= 0) return hipSuccess;
   if (w > kTrsmMaxW) return hipErrorInvalidValue;
-  const size_t lds = (size_t)w * 64 * sizeof(double);
+  const size_t lds = (size_t)w * (kTrsmCols + 16) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)block_trsm_kernel,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(block_trsm_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(256), lds, s, X,
-                     ldx, piv_row, c0, w, c1, nrhs, U);
+  hipLaunchKernelGGL(block_trsm_kernel, dim3((unsigned)((nrhs + kTrsmCols - 1) / kTrsmCols)),
+                     dim3(256), lds, s, X, ldx, piv_row, c0, w, c1, nrhs, U);
   return hipGetLastError();
 }
 
