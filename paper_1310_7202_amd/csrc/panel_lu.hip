@@ -196,13 +196,20 @@ __device__ __forceinline__ double lane_bcast(double v, int src) {
 // gives up once more than `tmo` ticks have passed since then.
 struct WaitLimit {
   long long t0 = -1;
-  __device__ __forceinline__ bool expired(long long tmo) {
+  // True when the wait should end: its own limit has passed, or another
+  // workgroup has raised the failure word.  The word is read only once the
+  // wait has lasted kFailCheckTicks (20 us): a normal wait ends well before
+  // and pays no extra device round trip per poll for it.
+  static constexpr long long kFailCheckTicks = 2000;
+  __device__ __forceinline__ bool give_up(long long tmo, const int* fail) {
     const long long now = now_ticks();
     if (t0 < 0) {
       t0 = now;
       return false;
     }
-    return now - t0 > tmo;
+    const long long waited = now - t0;
+    if (waited > tmo) return true;
+    return waited > kFailCheckTicks && ld_agent_i(fail) != 0;
   }
 };
 
@@ -380,7 +387,8 @@ __device__ __forceinline__ void panel_body(
         // ---- (1b) the step j-1 winner's row, columns j+1 on, into LDS for
         // the bulk waves (loaded after that step's exchange; one poll per
         // column normally finds it there)
-        const Rsrc pb = rsrc_of(precs + (int64_t)sh_bw[sp] * rec_stride, rec_stride);
+        const int bwp = __builtin_amdgcn_readfirstlane(sh_bw[sp]);
+        const Rsrc pb = rsrc_of(precs + (int64_t)bwp * rec_stride, rec_stride);
         bool stop = false;
 #pragma unroll
         for (int t = 0; t < kPF; ++t) {
@@ -389,7 +397,7 @@ __device__ __forceinline__ void panel_body(
             u32x4 v = brow_w[t];
             WaitLimit wl;
             while (!tagged2(v, (unsigned)j)) {
-              if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
+              if (wl.give_up(timeout_ticks, fail)) {
                 stop = true;
                 break;
               }
@@ -403,7 +411,7 @@ __device__ __forceinline__ void panel_body(
           u32x4 v = ld_words2(pb, kHdrWords + 2 * c);
           WaitLimit wl;
           while (!tagged2(v, (unsigned)j)) {
-            if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
+            if (wl.give_up(timeout_ticks, fail)) {
               stop = true;
               break;
             }
@@ -483,7 +491,7 @@ __device__ __forceinline__ void panel_body(
             }
           }
           if (__all(done == 0xFu)) break;
-          if (wl.expired(timeout_ticks) || ld_agent_i(fail) != 0) {
+          if (wl.give_up(timeout_ticks, fail)) {
             stop = true;
             break;
           }
