@@ -20,6 +20,7 @@
 // number of rows per workgroup, so a request's factors are the same alone
 // and in any mix.
 #include "rlu_internal.h"
+#include "serve_policy.h"
 
 #include <algorithm>
 #include <atomic>
@@ -124,11 +125,9 @@ struct rlu_server_s {
 
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Req*> queue;
+  rlu_serve::Policy policy{0, 0, 0};  // queue, budget and in-flight accounting
   std::unordered_map<uint64_t, Req*> reqs;
   std::vector<Flight> flights;
-  size_t used = 0;          // footprint of admitted, unreleased requests
-  int inflight = 0;         // admitted requests not yet done
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread thr;
@@ -164,9 +163,8 @@ bool rlu_server_s::reap(std::unique_lock<std::mutex>&) {
         rq->state = Q_DONE;
         rq->status = rlu_check_info(rq->info);
       }
-      used -= rq->ws_bytes;
+      policy.complete(rq->ws_bytes);
       rq->ws_bytes = 0;
-      --inflight;
     }
     if (f.ws) hipFreeAsync(f.ws, streams[f.stream]);
     busy[f.stream] = false;
@@ -183,27 +181,17 @@ bool rlu_server_s::launch_one(std::unique_lock<std::mutex>& lk) {
   int sidx = -1;
   for (int i = 0; i < (int)streams.size(); ++i)
     if (!busy[i]) { sidx = i; break; }
-  if (sidx < 0 || queue.empty()) return false;
+  if (sidx < 0 || policy.queued() == 0) return false;
+  // strict FIFO from the head (serve_policy.h)
   std::vector<Req*> batch;
-  const rlu_problem_t& head = queue.front()->pb;
-  const size_t budget = cfg.hbm_budget_bytes;
-  // strict FIFO: stop at the first request that does not fit or differs in
-  // precision from the head
-  const bool solo = queue.front()->solo;
-  while (!queue.empty() && (int)batch.size() < (solo ? 1 : kMaxBatch)) {
-    Req* r = queue.front();
-    if (r->solo != solo) break;
-    if (r->pb.dtype != head.dtype || r->pb.precision != head.precision) break;
-    if (cfg.max_inflight > 0 && inflight >= cfg.max_inflight) break;
-    const size_t fp = r->ws_bytes + r->out_bytes;
-    if (used + fp > budget) break;
-    used += fp;
-    ++inflight;
-    r->state = Q_RUNNING;
-    queue.pop_front();
-    batch.push_back(r);
+  for (const rlu_serve::Entry& e : policy.admit(kMaxBatch)) {
+    auto it = reqs.find(e.ticket);  // a queued request cannot be released
+    if (it == reqs.end()) continue;
+    it->second->state = Q_RUNNING;
+    batch.push_back(it->second);
   }
   if (batch.empty()) return false;
+  const bool solo = batch.front()->solo;
   busy[sidx] = true;
   const double t = now_us(t0);
   for (Req* r : batch) r->t_start = t;
@@ -268,7 +256,7 @@ void rlu_server_s::loop() {
   while (true) {
     bool progress = reap(lk);
     while (launch_one(lk)) progress = true;
-    if (stop && queue.empty() && flights.empty()) break;
+    if (stop && policy.queued() == 0 && flights.empty()) break;
     if (!progress) {
       if (flights.empty())
         cv.wait_for(lk, std::chrono::milliseconds(5));
@@ -317,6 +305,8 @@ rlu_status_t rlu_serve_create(const rlu_server_config_t* cfg, rlu_server_t* out)
     if (hipMemGetInfo(&fr, &tot) != hipSuccess) return fail(RLU_ERR_DEVICE);
     srv->cfg.hbm_budget_bytes = fr / 10 * 9;
   }
+  srv->policy = rlu_serve::Policy(srv->cfg.hbm_budget_bytes, srv->cfg.max_inflight,
+                                  srv->cfg.max_queue);
   for (int i = 0; i < kStreams; ++i) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(RLU_ERR_DEVICE);
@@ -356,17 +346,23 @@ rlu_status_t rlu_serve_submit(rlu_server_t srv, const rlu_problem_t* pb, const v
   st = request_ws_bytes(*pb, srv->h->cus, &r->ws_bytes, &r->solo);
   if (st != RLU_OK) { delete r; return st; }
   r->out_bytes = output_layout(*pb, &r->offU, &r->offp, &r->offq, &r->offinfo);
-  if (r->ws_bytes + r->out_bytes > srv->cfg.hbm_budget_bytes) { delete r; return RLU_ERR_TOO_LARGE; }
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) { delete r; return RLU_ERR_INVALID_ARG; }
-    if (srv->cfg.max_queue > 0 && (int)srv->queue.size() >= srv->cfg.max_queue) {
+    const rlu_serve::Verdict v = srv->policy.offer(r->ws_bytes, r->out_bytes);
+    if (v != rlu_serve::Verdict::Accept) {
       delete r;
-      return RLU_ERR_QUEUE_FULL;
+      return v == rlu_serve::Verdict::TooLarge ? RLU_ERR_TOO_LARGE : RLU_ERR_QUEUE_FULL;
     }
     r->ticket = srv->next_ticket++;
     r->t_submit = now_us(srv->t0);
-    srv->queue.push_back(r);
+    rlu_serve::Entry e;
+    e.ticket = r->ticket;
+    e.ws = r->ws_bytes;
+    e.out = r->out_bytes;
+    e.key = (int)r->pb.dtype * 16 + (int)r->pb.precision;
+    e.solo = r->solo;
+    srv->policy.push(e);
     srv->reqs[r->ticket] = r;
     *ticket = r->ticket;
   }
@@ -445,7 +441,7 @@ rlu_status_t rlu_serve_release(rlu_server_t srv, uint64_t ticket) {
     r = it->second;
     if (r->state == Q_QUEUED || r->state == Q_RUNNING) return RLU_PENDING;
     srv->reqs.erase(it);
-    srv->used -= r->out_bytes;
+    srv->policy.release(r->out_bytes);
   }
   if (r->out) {
     DeviceScope dev(srv->cfg.device);
@@ -460,9 +456,9 @@ rlu_status_t rlu_serve_stats(rlu_server_t srv, size_t* used_bytes, int32_t* queu
                              int32_t* inflight) {
   if (!srv) return RLU_ERR_INVALID_ARG;
   std::lock_guard<std::mutex> lk(srv->mu);
-  if (used_bytes) *used_bytes = srv->used;
-  if (queued) *queued = (int32_t)srv->queue.size();
-  if (inflight) *inflight = srv->inflight;
+  if (used_bytes) *used_bytes = srv->policy.used();
+  if (queued) *queued = (int32_t)srv->policy.queued();
+  if (inflight) *inflight = srv->policy.inflight();
   return RLU_OK;
 }
 
