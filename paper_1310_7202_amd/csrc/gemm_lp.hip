@@ -57,7 +57,12 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
                                              const int* __restrict__ astep,
                                              const TB* __restrict__ B, int64_t ldb,
                                              TO* __restrict__ C, int64_t ldc, int ksplit,
-                                             TO* __restrict__ partial, int bx, int by, int bz) {
+                                             TO* __restrict__ partial, int bx, int by, int bz,
+                                             const unsigned* __restrict__ amax) {
+  // A's range scale (FP16): the FP32 matrix is operand A of Y = A G and
+  // operand B of C = Lv^T A; undone on the output
+  const float asc = lp_scale(amax);
+  const float sa = OA == OpA::Plain ? asc : 1.f, sb = OA == OpA::Plain ? 1.f : asc;
   constexpr int NT = 64 * WM * WN;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
   constexpr int AE = BM * LBK / NT, BE = BN * LBK / NT;
@@ -116,7 +121,7 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
       a_pos(q, i, kk);
       double xd;
       if (OA == OpA::Plain) {
-        xd = (double)ra[q];
+        xd = (double)((float)ra[q] * sa);
       } else {
         const int64_t gi = m0 + i, gk = k0 + kk;
         xd = (gi < M && gk < kend) ? (double)lv_value<TA>(ra[q], (int)gi, sa1) : 0.0;
@@ -130,7 +135,7 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
     for (int q = 0; q < BE; ++q) {
       const int e = tid + q * NT;
       const int kk = e % LBK, j = e / LBK;
-      Bs[buf][j * LLD + kk] = (LP)(float)rb[q];
+      Bs[buf][j * LLD + kk] = (LP)((float)rb[q] * sb);
     }
   };
 
@@ -183,7 +188,7 @@ __device__ __forceinline__ void gemm_lp_tile(int64_t M, int64_t N, int64_t K,
         const int64_t gi = m0 + wm * WTM + a * 16 + 4 * (lane >> 4) + v;
         const int64_t gj = n0 + wn * WTN + b * 16 + (lane & 15);
         if (gi < M && gj < N) {
-          const TO val = (TO)acc[a][b][v];
+          const TO val = (TO)((double)acc[a][b][v] / (double)asc);
           if (ksplit > 1) partial[(int64_t)bz * M * N + gi + gj * M] = val;
           else C[gi + gj * ldc] = val;
         }
@@ -204,7 +209,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
 gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
                const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
                TO* __restrict__ C, int64_t ldc, int ksplit, TO* __restrict__ partial, int tm,
-               int tn, int nfast) {
+               int tn, int nfast, const unsigned* __restrict__ amax) {
   const int t = xcd_chunked_lp((int)blockIdx.x, (int)gridDim.x);
   int bx, by, bz;
   if (nfast) {
@@ -213,7 +218,7 @@ gemm_lp_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_
     bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
   }
   gemm_lp_tile<LP, TA, TB, TO, OA, SPLIT, BM, BN, WM, WN>(M, N, K, A, lda, astep, B, ldb, C, ldc,
-                                                          ksplit, partial, bx, by, bz);
+                                                          ksplit, partial, bx, by, bz, amax);
 }
 
 // Grouped form: workgroup b computes the tile map[b] = (task, bx + tiles_m by)
@@ -228,7 +233,7 @@ gemm_lp_grouped_kernel(const GemmTaskDev* __restrict__ tasks, const int2* __rest
   const int bx = e.y % t.tiles_m, by = e.y / t.tiles_m;
   gemm_lp_tile<LP, TA, TB, TO, OA, SPLIT, BM, BN, WM, WN>(
       t.M, t.N, t.K, (const TA*)t.A, t.lda, t.astep, (const TB*)t.B, t.ldb, (TO*)t.C, t.ldc, 1,
-      nullptr, bx, by, 0);
+      nullptr, bx, by, 0, t.amax);
 }
 
 // ---------------------------------------------------------------------------
@@ -251,8 +256,11 @@ __global__ void __launch_bounds__(64 * WM * WN)
 gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t lda,
                 const int* __restrict__ astep, const float* __restrict__ B, int64_t ldb,
                 double* __restrict__ C, int64_t ldc, int ksplit, double* __restrict__ partial,
-                int tm, int tn, int nfast) {
+                int tm, int tn, int nfast, const unsigned* __restrict__ amax) {
   constexpr int NT = 64 * WM * WN;
+  // A's range scale (FP16), as in the small-tile form
+  const float asc = lp_scale(amax);
+  const float sa = OA == OpA::Plain ? asc : 1.f, sb = OA == OpA::Plain ? 1.f : asc;
   constexpr int WTM = BM / WM, WTN = BN / WN, TM = WTM / 16, TN = WTN / 16;
   constexpr int NS = SPLIT ? 2 : 1;
   // loads per thread per K slice
@@ -351,7 +359,8 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           lp4 h;
-          h.x = (LP)ra[q][r]; h.y = (LP)ra[q][4 + r]; h.z = (LP)ra[q][8 + r]; h.w = (LP)ra[q][12 + r];
+          h.x = (LP)(ra[q][r] * sa); h.y = (LP)(ra[q][4 + r] * sa);
+          h.z = (LP)(ra[q][8 + r] * sa); h.w = (LP)(ra[q][12 + r] * sa);
           *(lp4*)&As[buf][0][(i4 + r) * LLD + k4] = h;
         }
       } else {
@@ -375,7 +384,8 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
       const int e = tid + q * NT;
       const int kk4 = 4 * (e % (LBK / 4)), j = e / (LBK / 4);
       lp4 h;
-      h.x = (LP)rb[q][0]; h.y = (LP)rb[q][1]; h.z = (LP)rb[q][2]; h.w = (LP)rb[q][3];
+      h.x = (LP)(rb[q][0] * sb); h.y = (LP)(rb[q][1] * sb);
+      h.z = (LP)(rb[q][2] * sb); h.w = (LP)(rb[q][3] * sb);
       *(lp4*)&Bs[buf][j * LLD + kk4] = h;
     }
   };
@@ -429,7 +439,7 @@ gemm_lp2_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64
         const int64_t gi = m0 + wm * WTM + a * 16 + 4 * (lane >> 4) + v;
         const int64_t gj = n0 + wn * WTN + b * 16 + (lane & 15);
         if (gi < M && gj < N) {
-          const double val = (double)acc[a][b][v];
+          const double val = (double)acc[a][b][v] / (double)asc;
           if (ksplit > 1) partial[(int64_t)bz * M * N + gi + gj * M] = val;
           else C[gi + gj * ldc] = val;
         }
@@ -448,7 +458,7 @@ hipError_t launch_lp2(const GemmDesc& d, hipStream_t s) {
   hipLaunchKernelGGL((gemm_lp2_kernel<LP, TA, OA, SPLIT, BM, BN, WM, WN>),
                      dim3((unsigned)(tiles * ks)), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K,
                      (const TA*)d.A, d.lda, d.astep, (const float*)d.B, d.ldb, (double*)d.C,
-                     d.ldc, ks, (double*)d.partial, tm, tn, nfast);
+                     d.ldc, ks, (double*)d.partial, tm, tn, nfast, d.amax);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;
   return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
@@ -469,7 +479,7 @@ hipError_t launch_lp(const GemmDesc& d, hipStream_t s) {
   hipLaunchKernelGGL((gemm_lp_kernel<LP, TA, TB, double, OA, SPLIT, BM, BN, WM, WN>),
                      dim3((unsigned)((int64_t)tm * tn * ks)), dim3(64 * WM * WN), 0, s, d.M, d.N,
                      d.K, (const TA*)d.A, d.lda, d.astep, (const TB*)d.B, d.ldb, (double*)d.C,
-                     d.ldc, ks, (double*)d.partial, tm, tn, nfast);
+                     d.ldc, ks, (double*)d.partial, tm, tn, nfast, d.amax);
   if (d.ksplit_out) *d.ksplit_out = ks;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;

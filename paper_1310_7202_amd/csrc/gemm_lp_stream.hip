@@ -64,8 +64,10 @@ template <typename LP, int TN>
 __global__ void __launch_bounds__(256, 1)
 sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_t lda,
                      const LP* __restrict__ Gs, double* __restrict__ C, int64_t ldc, int ksplit,
-                     double* __restrict__ partial, int tiles_m) {
+                     double* __restrict__ partial, int tiles_m, const unsigned* __restrict__ amax) {
   typedef typename Mma16<LP>::vec vec;
+  const float asc = lp_scale(amax);  // A's range scale (FP16), undone on the output
+  const double ainv = 1.0 / (double)asc;
   constexpr int NP = 64 * TN;  // padded columns of Y
   __shared__ __attribute__((aligned(16))) LP As[2][64 * kLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -103,7 +105,7 @@ sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ 
       const int64_t k0 = kbeg + (int64_t)step * kBK + 8 * ag;
       vec v;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (LP)(k0 + e < kend_t ? r[e] : 0.f);
+      for (int e = 0; e < 8; ++e) v[e] = (LP)((k0 + e < kend_t ? r[e] : 0.f) * asc);
       *(vec*)&As[buf][ar * kLd + 8 * ag] = v;
     };
     // this wave's G fragments: column n0w + 16 t + (lane & 15), k 8 (lane >> 4);
@@ -169,7 +171,7 @@ sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ 
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + 16 * a + 4 * (lane >> 4) + v;
-        if (row < M && col < N) out[row + col * ldo] = (double)acc[a][t][v];
+        if (row < M && col < N) out[row + col * ldo] = (double)acc[a][t][v] * ainv;
       }
     }
 }
@@ -210,7 +212,7 @@ hipError_t launch_sketch_stream(const GemmDesc& d, hipStream_t s) {
 #define RLU_SKS(TN)                                                                          \
   hipLaunchKernelGGL((sketch_stream_kernel<LP, TN>), grid, dim3(256), 0, s, d.M, d.N, d.K,    \
                      (const float*)d.A, d.lda, (const LP*)Gs, (double*)d.C, d.ldc, ks,       \
-                     (double*)d.partial, tiles_m)
+                     (double*)d.partial, tiles_m, d.amax)
   switch (tn) {
     case 1: RLU_SKS(1); break;
     case 2: RLU_SKS(2); break;
@@ -240,8 +242,11 @@ template <typename LP, int TR, bool VEC>
 __global__ void __launch_bounds__(256, 1)
 project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls,
                       const float* __restrict__ A, int64_t lda, double* __restrict__ C,
-                      int64_t ldc, int ksplit, double* __restrict__ partial, int tiles_n) {
+                      int64_t ldc, int ksplit, double* __restrict__ partial, int tiles_n,
+                      const unsigned* __restrict__ amax) {
   typedef typename Mma16<LP>::vec vec;
+  const float asc = lp_scale(amax);  // A's range scale (FP16), undone on the output
+  const double ainv = 1.0 / (double)asc;
   constexpr int RP = 64 * TR;  // padded rows of C
   typedef LP lp4 __attribute__((ext_vector_type(4)));
   __shared__ __attribute__((aligned(16))) LP Bs[2][64 * kLd];
@@ -300,7 +305,7 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
         const float x[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
         lp4 v;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (LP)(kk + e < kend_t[j] ? x[e] : 0.f);
+        for (int e = 0; e < 4; ++e) v[e] = (LP)((kk + e < kend_t[j] ? x[e] : 0.f) * asc);
         *(lp4*)&Bs[buf][bcol[j] * kLd + bk[j]] = v;
       }
     };
@@ -369,7 +374,7 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = r0w + 16 * a + 4 * (lane >> 4) + v;
-        if (row < M && col < N) out[row + col * ldo] = (double)acc[a][c][v];
+        if (row < M && col < N) out[row + col * ldo] = (double)acc[a][c][v] * ainv;
       }
     }
 }
@@ -421,11 +426,11 @@ hipError_t launch_project_stream(const GemmDesc& d, hipStream_t s) {
   if (vec)                                                                                     \
     hipLaunchKernelGGL((project_stream_kernel<LP, TR, true>), grid, dim3(256), 0, s, d.M, d.N, \
                        d.K, (const LP*)Ls, (const float*)d.B, d.ldb, (double*)d.C, d.ldc, ks,  \
-                       (double*)d.partial, tiles_n);                                           \
+                       (double*)d.partial, tiles_n, d.amax);                                   \
   else                                                                                         \
     hipLaunchKernelGGL((project_stream_kernel<LP, TR, false>), grid, dim3(256), 0, s, d.M,     \
                        d.N, d.K, (const LP*)Ls, (const float*)d.B, d.ldb, (double*)d.C, d.ldc, \
-                       ks, (double*)d.partial, tiles_n)
+                       ks, (double*)d.partial, tiles_n, d.amax)
   switch (tr) {
     case 1: RLU_PJS(1); break;
     case 2: RLU_PJS(2); break;
@@ -502,6 +507,61 @@ bool stream_sketch_applies(const GemmDesc& d) {
 hipError_t launch_sketch_stream_lp(const GemmDesc& d, bool fp16, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   return fp16 ? launch_sketch_stream<_Float16>(d, s) : launch_sketch_stream<__bf16>(d, s);
+}
+
+// ---------------------------------------------------------------------------
+// max|A| of FP32 matrices, as FP32 bits by atomic maximum (non-negative
+// floats order like their bits; a NaN ranks above every number and makes the
+// scale 1, see lp_scale).
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ void absmax_block(const float* __restrict__ A, int64_t lda, int64_t m,
+                                             int64_t n, unsigned* word, int64_t b0, int64_t bstep) {
+  __shared__ unsigned red[4];
+  unsigned best = 0;
+  for (int64_t j = b0; j < n; j += bstep)  // a column per workgroup, rows over its threads
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+      const unsigned b = __float_as_uint(A[i + j * lda]) & 0x7fffffffu;
+      best = b > best ? b : best;
+    }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned x = (unsigned)__shfl_xor((int)best, o);
+    best = x > best ? x : best;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = red[w] > t ? red[w] : t;
+    if (t) atomicMax(word, t);
+  }
+}
+
+__global__ void __launch_bounds__(256) absmax_kernel(const float* __restrict__ A, int64_t lda,
+                                                     int64_t m, int64_t n, unsigned* word) {
+  absmax_block(A, lda, m, n, word, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) absmax_batched_kernel(const AbsmaxTaskDev* __restrict__ tasks) {
+  const AbsmaxTaskDev t = tasks[blockIdx.y];
+  absmax_block(t.A, t.lda, t.m, t.n, t.word, blockIdx.x, gridDim.x);
+}
+
+}  // namespace
+
+hipError_t launch_absmax(const float* A, int64_t lda, int64_t m, int64_t n, unsigned* word,
+                         hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t blocks = n < 4096 ? n : 4096;
+  hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s, A, lda, m, n, word);
+  return hipGetLastError();
+}
+
+hipError_t launch_absmax_batched(const AbsmaxTaskDev* tasks, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(absmax_batched_kernel, dim3(64u, (unsigned)count), dim3(256), 0, s, tasks);
+  return hipGetLastError();
 }
 
 }  // namespace rlu

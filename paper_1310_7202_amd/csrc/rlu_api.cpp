@@ -339,7 +339,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   int* rstep_b = at<int>(ws, Ly.rstep_b);
   int* piv_b = at<int>(ws, Ly.piv_b);
   int* ipiv_b = at<int>(ws, Ly.ipiv_b);
-  int* flags = at<int>(ws, Ly.flags);  // [0] info_y, [1] info_b, [2] exchange failure
+  int* flags = at<int>(ws, Ly.flags);  // [0] info_y, [1] info_b, [2] exchange failure; [8] max|A| (FP16)
   void* xch = at<void>(ws, Ly.xch);
   const bool diag = (pb.flags & RLU_FLAG_DIAGNOSTICS) != 0;
 
@@ -348,6 +348,13 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   // already given up
   if (h->xch_preset_fail) HIP_TRY(launch_fill_u32((uint32_t*)flags + 2, 1, 1u, s));
   const long long tmo = h->xch_timeout;
+  // FP16 products: the range of A (max|A|, flags[8]), from which they scale A
+  // by a power of two before rounding it (lp_scale); BF16 keeps FP32's range
+  const unsigned* amax = nullptr;
+  if (lp && fp16) {
+    HIP_TRY(launch_absmax((const float*)io.A, io.lda, m, n, (unsigned*)(flags + 8), s));
+    amax = (const unsigned*)(flags + 8);
+  }
 
   // Step 1 (Algorithm 4.4: the SRFT R = D F S in the place of G)
   const bool fast = (pb.flags & RLU_FLAG_FAST) != 0;
@@ -376,6 +383,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = Y; d.ldc = m;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     if (lp) d.lp_ws = at<void>(ws, Ly.lpw);
+    d.amax = amax;
     int ks = 1;
     d.no_sum = true; d.ksplit_out = &ks;
     {
@@ -399,6 +407,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.C = Out; d.ldc = rows;
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     if (lp) d.lp_ws = at<void>(ws, Ly.lpw);
+    d.amax = amax;
     int ks = 1;
     d.no_sum = true; d.ksplit_out = &ks;
     {

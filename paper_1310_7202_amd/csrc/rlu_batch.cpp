@@ -76,6 +76,7 @@ struct Plan {
   std::vector<char> tab;  // host image of the tables
   // launches
   size_t gauss = 0; int n_gauss = 0; int64_t gauss_max = 0;
+  size_t absmax = 0;  // FP16: max|A| of each problem into int 8 of its flags
   size_t fin = 0; int n_fin = 0; int64_t fin_max = 0;  // non-finite checks of the sketches
   std::vector<GemmLaunch> sketch, gram, project, solve, forml;
   size_t gram_all = 0; int gram_count = 0; int64_t gram_max = 0; bool gram_split = false;
@@ -430,6 +431,17 @@ rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
   }
   P.n_gauss = (int)gauss.size();
   P.gauss = tw.put(gauss);
+  // FP16 products scale A by a power of two chosen from max|A|
+  auto amax_of = [&](const Item& it) -> const unsigned* {
+    return P.fp16 ? (const unsigned*)(base + it.flags) + 8 : nullptr;
+  };
+  if (P.fp16) {
+    std::vector<AbsmaxTaskDev> am;
+    for (const Item& it : P.items)
+      am.push_back(AbsmaxTaskDev{(const float*)it.io.A, it.io.lda, it.pb.m, it.pb.n,
+                                 (unsigned*)(base + it.flags) + 8});
+    P.absmax = tw.put(am);
+  }
   // Step 2: Y = A G
   {
     std::vector<GemmTaskDev> t;
@@ -442,6 +454,7 @@ rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
       g.ldb = it.pb.G ? it.pb.ldg : it.pb.n;
       g.C = base + it.Y; g.ldc = it.pb.m;
       g.ksplit = 1;
+      g.amax = amax_of(it);
       t.push_back(g);
       cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Sketch, g.N));
     }
@@ -475,6 +488,7 @@ rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
       g.B = it.io.A; g.ldb = it.io.lda;
       g.C = base + it.zt; g.ldc = it.pb.l;
       g.ksplit = 1;
+      g.amax = amax_of(it);
       t.push_back(g);
       cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Project, g.N));
       LvDenseTaskDev x{};  // Lv(Z), n x l, in the storage type
@@ -489,6 +503,7 @@ rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
       y.B = base + it.gz; y.ldb = it.pb.n;
       y.C = base + it.Y; y.ldc = it.pb.m;
       y.ksplit = 1;
+      y.amax = amax_of(it);
       r.push_back(y);
       rcfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Sketch, y.N));
     }
@@ -547,6 +562,7 @@ rlu_status_t build_tables(Plan& P, WsBase base, int cus) {
       g.B = it.io.A; g.ldb = it.io.lda;
       g.C = base + it.C; g.ldc = it.pb.k;
       g.ksplit = 1;
+      g.amax = amax_of(it);
       t.push_back(g);
       cfg.push_back(P.lp ? GEMM_CFG_64x64 : pick_cfg(P, GemmRole::Project, g.N));
     }
@@ -645,6 +661,8 @@ rlu_status_t enqueue(rlu_handle_s* h, const Plan& P, char* base, hipEvent_t gate
   char* tab = base + P.tab_off;
   const int count = (int)P.items.size();
   HIP_TRY(launch_fill_u32((uint32_t*)base, P.zero_bytes / 4, 0u, s));
+  if (P.fp16)
+    HIP_TRY(launch_absmax_batched((const AbsmaxTaskDev*)(tab + P.absmax), count, s));
   if (P.n_gauss > 0) {
     PhaseScope ph(h, PH_GAUSSIAN, s);
     HIP_TRY(launch_gaussian_batched<T>((const GaussTaskDev*)(tab + P.gauss), P.n_gauss,

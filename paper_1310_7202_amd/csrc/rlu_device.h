@@ -57,6 +57,22 @@ __device__ __forceinline__ T lv_value(T stored, int r, int s) {
   return r < s ? stored : (r == s ? T(1) : T(0));
 }
 
+// FP16 range of the mixed form: the products round s A to 16 bits with s a
+// power of two that puts max|A| s in [2^13, 2^14) (FP16 then keeps 11
+// significant bits from the largest entry down to 2^-24 of it, far from
+// 65504), and their FP64 results are multiplied by 1/s: both exact.  s = 1
+// without a maximum (BF16 has FP32's exponent range), or when it is zero or
+// not finite.  amax holds max|A| as FP32 bits.
+__device__ __forceinline__ float lp_scale(const unsigned* amax) {
+  if (!amax) return 1.f;
+  const float m = __uint_as_float(*amax);
+  if (!(m > 0.f) || m > 3.0e38f) return 1.f;
+  int e;
+  (void)frexpf(m, &e);  // m = f 2^e, f in [1/2, 1)
+  const int sh = min(max(14 - e, -100), 100);
+  return ldexpf(1.f, sh);
+}
+
 // ---------------------------------------------------------------------------
 // Wall clock (100 MHz constant clock on gfx9) for bounded waits.
 // ---------------------------------------------------------------------------

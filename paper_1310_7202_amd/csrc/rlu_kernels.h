@@ -53,6 +53,8 @@ struct GemmDesc {
   bool csub;           // C -= op(A) op(B) instead of C = ... (requires ksplit 1)
   void* lp_ws;         // low-precision products: room for the pre-converted small
                        // operand (stream_sketch_ws_bytes / stream_project_ws_bytes)
+  const unsigned* amax;  // FP16 products: max|A| (FP32 bits) for the range scale of A
+                         // (lp_scale); null: unscaled
 };
 template <typename T>
 hipError_t launch_gemm(const GemmDesc& d, hipStream_t s);
@@ -100,6 +102,7 @@ struct GemmTaskDev {
   const void* B; int64_t ldb; const int* bstep;
   void* C; int64_t ldc; const int* rowmap;
   void* partial; int ksplit; int tiles_m, tiles_n;
+  const unsigned* amax;  // as GemmDesc::amax (low-precision products)
 };
 // Compiled tile shapes (index = cfg; gemm_cfg_name gives "BMxBNxBK").
 enum { GEMM_CFG_64x64 = 0, GEMM_CFG_64x112 = 1, GEMM_CFG_112x64 = 2, GEMM_CFG_64x112x32 = 3,
@@ -118,6 +121,12 @@ hipError_t launch_splitk_sum_grouped(const GemmTaskDev* tasks, int count, int64_
 // (FP32 A and G) or LvT (FP64 Lv as a hi + lo pair, FP32 A), FP64 output.
 hipError_t launch_gemm_lp_grouped(OpA opa, bool fp16, const GemmTaskDev* tasks, const int2* map,
                                   int nwg, hipStream_t s);
+// max|A| of an FP32 matrix (m x n, column-major) into *word as FP32 bits, by
+// atomic maximum (the word must start at zero): the FP16 products' range.
+hipError_t launch_absmax(const float* A, int64_t lda, int64_t m, int64_t n, unsigned* word,
+                         hipStream_t s);
+struct AbsmaxTaskDev { const float* A; int64_t lda, m, n; unsigned* word; };
+hipError_t launch_absmax_batched(const AbsmaxTaskDev* tasks, int count, hipStream_t s);
 
 // ----- Pivoted LU of a tall matrix, rows spread over workgroups (panel_lu.hip)
 struct PanelDesc {

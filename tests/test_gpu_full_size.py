@@ -123,7 +123,8 @@ def test_exp_spectrum_8192_fp32(rlu, exp8192):
                    "8192^2 FP32")
 
 
-def test_inverse_square_spectrum_16384_bf16(rlu):
+@pytest.mark.parametrize("fp16", [False, True])
+def test_inverse_square_spectrum_16384_mixed(rlu, fp16):
     n, k, l = 16384, 500, 520
     A_dev = workloads.spectral_matrix_torch(n, n, workloads.inv_square(n), 103,
                                             device="cuda", dtype=torch.float32)
@@ -131,4 +132,5 @@ def test_inverse_square_spectrum_16384_bf16(rlu):
     del A_dev
     torch.cuda.empty_cache()
     G32 = philox.gaussian_matrix(n, l, 7203).astype(np.float32)
-    _residual_rule(rlu, A32, k, l, G32, rlu.PREC_MIXED_BF16, "16384^2 i^-2 BF16")
+    prec = rlu.PREC_MIXED_FP16 if fp16 else rlu.PREC_MIXED_BF16
+    _residual_rule(rlu, A32, k, l, G32, prec, f"16384^2 i^-2 {'FP16' if fp16 else 'BF16'}")

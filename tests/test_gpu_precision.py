@@ -172,3 +172,47 @@ def test_power_iterations_reduced_precision(rlu, precision, q):
     r_gpu, r_ora = check(rlu, A64, k, l, 1710 + q, precision, "power", q=q)
     r0_gpu, _ = check(rlu, A64, k, l, 1710 + q, precision, "power q=0")
     assert r_gpu < r0_gpu
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("e", [24, -24])
+def test_mixed_power_of_two_scale_equivariance(rlu, fp16, e):
+    """A times 2^e gives the same pivots and L, and U times 2^e, bit for bit.
+    Every step of Algorithm 4.1 commutes with a power-of-two scale of A as
+    long as nothing leaves the range of its format; FP16 has a range of only
+    about 2^-24 .. 2^16, so for it this holds only because the products scale
+    A by a power of two chosen from max|A| before rounding it (entries near
+    2^24 would round to infinity, entries near 2^-30 to zero)."""
+    m, n, k, l = 1500, 1100, 30, 38
+    A32 = workloads.spectral_matrix(m, n, workloads.exp_decay(n, 10.0), 820).astype(np.float32)
+    G = workloads.gaussian((n, l), 821).astype(np.float32)
+    G = G.astype(np.float16).astype(np.float32) if fp16 else _round_bf16(G)
+    prec = rlu.PREC_MIXED_FP16 if fp16 else rlu.PREC_MIXED_BF16
+    Gd = to_dev_colmajor(G, dtype=torch.float32)
+    print(f"[precision] scale 2^{e} fp16={fp16} m={m} n={n} k={k} l={l}", flush=True)
+    outs = []
+    for scale in (1.0, 2.0 ** e):
+        As = (A32 * np.float32(scale)).astype(np.float32)
+        assert np.array_equal(As / np.float32(scale), A32)   # the scaling is exact
+        out = rlu.factor(to_dev_colmajor(As, dtype=torch.float32), k, l, G=Gd, precision=prec,
+                         diagnostics=True)
+        torch.cuda.synchronize()
+        assert tuple(to_host(out.info)) == (0, 0, 0)
+        outs.append({x: to_host(getattr(out, x)) for x in ("L", "U", "p", "q", "ipiv", "Y")})
+    a, b = outs
+    for x in ("p", "q", "ipiv"):
+        np.testing.assert_array_equal(a[x], b[x])
+    np.testing.assert_array_equal(a["L"], b["L"])
+    for x in ("U", "Y"):
+        np.testing.assert_array_equal(a[x].astype(np.float64) * 2.0 ** e, b[x].astype(np.float64))
+
+
+@pytest.mark.parametrize("scale", [1e7, 1e-6])
+def test_fp16_far_from_unit_scale(rlu, scale):
+    """FP16 products on entries far above and far below unit scale (max|A|
+    about 1.2e5 after a 1e7 scale, past FP16's largest finite value, and
+    about 1.2e-8 after a 1e-6 scale, under its smallest subnormal): the
+    residual rule against the oracle and the sketch within 4 u of |A||G|,
+    as at unit scale."""
+    A = workloads.spectral_matrix(1600, 1200, workloads.exp_decay(1200, 12.0), 830) * scale
+    check_mixed(rlu, A, 40, 48, 831, True, f"fp16 scale {scale:g}")
