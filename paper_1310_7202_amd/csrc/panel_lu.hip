@@ -741,6 +741,224 @@ panel_lu_batched_kernel(const PanelTaskDev* __restrict__ tasks, const int* __res
   }
 }
 
+// ---------------------------------------------------------------------------
+// Panels of one workgroup with at most 32 columns: the rows live in
+// registers (thread t holds rows t, t + 512, ...), a row's registers holding
+// its columns from the current step on (they shift by one after each step,
+// so that column j is always the first register and no step selects among
+// registers by a run-time index), and one barrier per step suffices.
+// Step j:
+//   before the barrier: each thread applies the rank-one update of step j-1
+//     to its live rows (the step j-1 pivot row read from LDS) and finds its
+//     best row in column j; the wave's best lane posts that candidate (rank
+//     key, value, the value's reciprocal, position, row) and its row in the
+//     wave's slot of the step's parity;
+//   after it: every wave reads the eight slots and selects the same winner;
+//     each thread stores column j of its live rows (the multipliers, or
+//     the values themselves for the winner and for a zero pivot), the
+//     first threads store the winner's U row from its slot, and the position
+//     bookkeeping follows; every finished entry goes to memory as it is
+//     produced, so nothing is left to write back at the end.
+// The slots of step j are written again at step j + 2, after the barrier of
+// step j + 1, which a thread reaches only after its update of step j has
+// read the winner's row.  The arithmetic is the multi-workgroup kernel's:
+// the same multipliers, the same fused multiply-add for each update, the
+// same ranking and tie break, so the factors agree bitwise.
+// ---------------------------------------------------------------------------
+constexpr int kSmallThreads = 512;
+constexpr int kSmallWaves = kSmallThreads / 64;
+
+template <int CMAX, int RPT>
+__global__ void __launch_bounds__(kSmallThreads)
+panel_small_kernel(double* __restrict__ X, int64_t rs, int64_t cs, int nrows, int ncols,
+                   int* __restrict__ pos_out, int* __restrict__ rstep_out,
+                   int* __restrict__ piv_row_out, int* __restrict__ ipiv_out,
+                   int* __restrict__ info_out, int* __restrict__ fail, int step0, int total_cols,
+                   const int* __restrict__ pos_in, const int* __restrict__ rstep_in) {
+  // a wave's slot: its candidate's rank key, value in column j, the
+  // reciprocal of that value (taken here, off the path that follows the
+  // barrier), position and row (packed); then the candidate's row from
+  // column j+1 on, aligned with the registers of the next step
+  __shared__ double s_hdr[2][kSmallWaves][4];
+  __shared__ double s_row[2][kSmallWaves][CMAX];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  double x[RPT][CMAX];  // x[q][c]: column j + c of row tid + 512 q at step j
+  double mlt[RPT];
+  int pos[RPT], st[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + kSmallThreads * q;
+    const bool in = r < nrows;
+    const double* xr = X + (int64_t)(in ? r : 0) * rs;
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) {
+      x[q][c] = in && c < ncols ? *xr : 0.0;
+      xr += cs;
+    }
+    pos[q] = in ? (pos_in ? pos_in[r] : r) : INT_MAX;
+    st[q] = -1;  // no such row
+    if (in) {
+      st[q] = kNone;
+      if (rstep_in) {
+        const int s0 = rstep_in[r];
+        if (s0 < step0) st[q] = s0;  // chosen by an earlier block of columns
+      }
+    }
+    mlt[q] = 0.0;
+  }
+
+  int info = 0;
+  bool upd = false;  // the previous step had a nonzero pivot
+  int wprev = 0;     // slot holding the previous step's pivot row
+  int j = 0;
+  for (; j < ncols; ++j) {
+    const int sj = j & 1, sp = sj ^ 1;
+    // ---- (A) update of step j-1 on the live rows ----------------------------
+    if (upd) {
+      double u[CMAX];
+#pragma unroll
+      for (int c = 0; c < CMAX; ++c) u[c] = s_row[sp][wprev][c];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (st[q] == kNone) {
+#pragma unroll
+          for (int c = 0; c < CMAX; ++c) x[q][c] = __fma_rn(-mlt[q], u[c], x[q][c]);
+        }
+    }
+    // ---- (B) the thread's and the wave's best live row in column j ---------
+    double a = -1.0, bv = 0.0;
+    int p = INT_MAX, bq = -1;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const double v = x[q][0];
+      // NaN ranks above every number (see panel_body)
+      const double key = v != v ? __builtin_inf() : fabs(v);
+      const bool take = st[q] == kNone && better(key, pos[q], a, p);
+      a = take ? key : a;
+      p = take ? pos[q] : p;
+      bq = take ? q : bq;
+      bv = take ? v : bv;
+    }
+    const int src = wave_best_lane(a, p);
+    if (lane == src) {
+      const int r = bq < 0 ? -1 : tid + kSmallThreads * bq;
+      s_hdr[sj][wave][0] = a;
+      s_hdr[sj][wave][1] = bv;
+      s_hdr[sj][wave][2] = 1.0 / bv;
+      s_hdr[sj][wave][3] = __hiloint2double(r, p);
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        if (q != bq) continue;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c) s_row[sj][wave][c] = c + 1 < CMAX ? x[q][c + 1] : 0.0;
+      }
+    }
+    lds_barrier();
+    // ---- (C) the winner: lane w holds slot w; every wave selects alike ------
+    double hk = -2.0, hv = 0.0, hi = 0.0;
+    int hp = INT_MAX, hr = -1;
+    if (lane < kSmallWaves) {
+      hk = s_hdr[sj][lane][0];
+      hv = s_hdr[sj][lane][1];
+      hi = s_hdr[sj][lane][2];
+      const double pk = s_hdr[sj][lane][3];
+      hp = __double2loint(pk);
+      hr = __double2hiint(pk);
+    }
+    const int ws = wave_best_lane(hk, hp);
+    const int win_r = __builtin_amdgcn_readlane(hr, ws);
+    if (win_r < 0) {  // no live row anywhere: cannot happen for ncols <= nrows
+      if (tid == 0) st_agent_i(fail, 1);
+      break;
+    }
+    const int win_pos = __builtin_amdgcn_readlane(hp, ws);
+    const double piv = lane_bcast(hv, ws);
+    // ---- (D) multipliers, stores and bookkeeping of step j -------------------
+    const int how = __builtin_amdgcn_readfirstlane(
+        piv == 0.0 ? 0 : (fabs(piv) >= 2.2250738585072014e-308 ? 1 : 2));  // smallest normal
+    double mq[RPT];
+    if (how == 1) {
+      const double rpiv = lane_bcast(hi, ws);  // 1 / piv
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) mq[q] = x[q][0] * rpiv;
+    } else if (how == 2) {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) mq[q] = x[q][0] / piv;
+    } else {
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) mq[q] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int r = tid + kSmallThreads * q;
+      const bool live = st[q] == kNone, isw = r == win_r;
+      if (live) X[(int64_t)r * rs + (int64_t)j * cs] = isw || piv == 0.0 ? x[q][0] : mq[q];
+      mlt[q] = live && !isw ? mq[q] : 0.0;
+      pos[q] = isw ? step0 + j : (pos[q] == step0 + j ? win_pos : pos[q]);
+      st[q] = isw ? step0 + j : st[q];
+    }
+    // the winner's U row, columns j+1 .. ncols-1, from its slot
+    if (tid < ncols - 1 - j)
+      X[(int64_t)win_r * rs + (int64_t)(j + 1 + tid) * cs] = s_row[sj][ws][tid];
+    // the registers move on to column j+1
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+      for (int c = 0; c < CMAX; ++c) x[q][c] = c + 1 < CMAX ? x[q][c + 1] : 0.0;
+    if (tid == 0) {
+      piv_row_out[j] = win_r;
+      ipiv_out[j] = win_pos;
+    }
+    if (piv == 0.0 && info == 0) info = step0 + j + 1;
+    upd = piv != 0.0;
+    wprev = ws;
+  }
+  // a factorization that stopped early still hands its consumers in-range
+  // rows and positions (see panel_body)
+  if (tid == 0)
+    for (int c = j; c < ncols; ++c) {
+      piv_row_out[c] = c;
+      ipiv_out[c] = step0 + c;
+    }
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = tid + kSmallThreads * q;
+    if (r < nrows) {
+      pos_out[r] = pos[q];
+      rstep_out[r] = st[q] == kNone ? total_cols : st[q];
+    }
+  }
+  if (tid == 0 && info != 0 && *info_out == 0) *info_out = info;
+}
+
+// The register-resident kernel for a panel of one workgroup, if one fits:
+// CMAX the smaller of 16 and 32 that holds the columns, RPT rows per thread
+// with RPT CMAX <= 64 (128 registers of panel per thread; 64 columns in one
+// row per thread would leave too few registers for the rest).
+int small_cmax(int ncols) { return ncols <= 16 ? 16 : ncols <= 32 ? 32 : 0; }
+int small_rows_cap(int ncols) {
+  const int cm = small_cmax(ncols);
+  return cm ? kSmallThreads * (64 / cm) : 0;
+}
+bool panel_regs_enabled() {
+  const char* e = std::getenv("RLU_PANEL_REGS");
+  return !(e && e[0] == '0');
+}
+const void* small_fn(int nrows, int ncols) {
+  const int cm = small_cmax(ncols);
+  const int rpt = (nrows + kSmallThreads - 1) / kSmallThreads;
+  if (cm == 16) {
+    return rpt <= 1 ? (const void*)panel_small_kernel<16, 1>
+         : rpt <= 2 ? (const void*)panel_small_kernel<16, 2>
+         : rpt <= 4 ? (const void*)panel_small_kernel<16, 4> : nullptr;
+  }
+  if (cm == 32)
+    return rpt <= 1 ? (const void*)panel_small_kernel<32, 1>
+         : rpt <= 2 ? (const void*)panel_small_kernel<32, 2> : nullptr;
+  return nullptr;
+}
+
 constexpr size_t kLdsLimit = 160 * 1024;
 
 size_t lds_for(int R, int ncols) {
@@ -771,7 +989,18 @@ PanelPlan panel_plan(int nrows, int ncols, int device_cus, int /*max_wg_per_cu_h
   // the LDS holds R rows of the panel (leaving room for static shared data)
   const size_t budget = kLdsLimit - 1024;
   auto fits = [&](int rows) { return lds_for(rows, ncols) <= budget; };
+  p.regs = false;
   int R, nwg;
+  if (nrows <= small_rows_cap(ncols) && panel_regs_enabled()) {
+    // one workgroup, the panel in registers (panel_small_kernel)
+    p.rows_per_wg = nrows;
+    p.nwg = 1;
+    p.lds_bytes = 0;
+    p.xch_bytes = 0;
+    p.ok = true;
+    p.regs = true;
+    return p;
+  }
   if (nrows <= 512 && fits(nrows)) {
     // one workgroup: the exchange stays in LDS
     R = nrows;
@@ -800,6 +1029,21 @@ PanelPlan panel_plan(int nrows, int ncols, int device_cus, int /*max_wg_per_cu_h
 hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s) {
   if (!plan.ok) return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
+  if (plan.regs) {
+    const void* fn = small_fn(d.nrows, d.ncols);
+    if (!fn) return hipErrorInvalidValue;
+    double* X = (double*)d.X;
+    int64_t rs = d.rs, cs = d.cs;
+    int nrows = d.nrows, ncols = d.ncols;
+    int* pos = d.pos; int* rstep = d.rstep; int* piv_row = d.piv_row; int* ipiv = d.ipiv;
+    int* info = d.info; int* fail = d.fail;
+    int step0 = d.step0, total = d.total_cols > 0 ? d.total_cols : d.ncols;
+    const int* pos_in = d.pos_in;
+    const int* rstep_in = d.rstep_in;
+    void* args[] = {&X, &rs, &cs, &nrows, &ncols, &pos, &rstep, &piv_row, &ipiv,
+                    &info, &fail, &step0, &total, &pos_in, &rstep_in};
+    return hipLaunchKernel(fn, dim3(1), dim3(kSmallThreads), args, 0, s);
+  }
   // clear the exchange tags of both parities
   if (plan.nwg > 1) {
     e = launch_fill_u32((uint32_t*)d.xch, plan.xch_bytes / 4, 0u, s);

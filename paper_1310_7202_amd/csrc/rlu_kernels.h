@@ -147,7 +147,11 @@ struct PanelDesc {
   const int* pos_in;         // positions after the earlier columns (nullable)
   const int* rstep_in;       // choosing steps so far (nullable: none chosen)
 };
-struct PanelPlan { int rows_per_wg; int nwg; size_t lds_bytes; size_t xch_bytes; bool ok; };
+// regs: one workgroup holding the panel in registers (at most 32 columns and
+// 1024 or 2048 rows for up to 32 or 16 columns); RLU_PANEL_REGS=0
+// in the environment, read at each plan, turns it off (the LDS-resident
+// kernels then take these panels, as they take all others).
+struct PanelPlan { int rows_per_wg; int nwg; size_t lds_bytes; size_t xch_bytes; bool ok; bool regs; };
 PanelPlan panel_plan(int nrows, int ncols, int device_cus, int max_wg_per_cu_hint);
 hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_t s);
 // Between column blocks of a blocked factorization of a column-major X:

@@ -256,7 +256,7 @@ def test_blocked_panels(rlu, m, n, k, l):
     run_and_compare(rlu, A, k, l, G, f"blocked {m}x{n}")
 
 
-@pytest.mark.parametrize("m,seed", [(6000, 77), (20000, 78)])
+@pytest.mark.parametrize("m,seed", [(6000, 77), (20000, 78), (1500, 79), (500, 80)])
 def test_exact_pivot_ties_go_to_lowest_position(rlu, m, seed):
     """Pivot searches with many equal magnitudes, in exact arithmetic.
 
@@ -314,3 +314,53 @@ def test_power_iterations_blocked_normalization(rlu):
     G = workloads.gaussian((n, l), 661)
     run_and_compare(rlu, A, k, l, G, "power blocked", power=1)
 
+
+
+def _register_panel_cases():
+    rng = np.random.default_rng(4100)
+    ties = rng.choice([-1.0, 1.0], size=(60, 50))
+    few = np.zeros((300, 200))
+    few[rng.choice(300, 5, replace=False)] = rng.standard_normal((5, 200))
+    return [
+        ("512^2 rank-10", *workloads.config_small(101)),
+        ("97x131", workloads.spectral_matrix(97, 131, workloads.exp_decay(97, 3.0), 4101), 5, 9),
+        ("400x300 l=28", workloads.spectral_matrix(400, 300, workloads.exp_decay(300, 9.0),
+                                                   4102), 20, 28),
+        ("480x350 l=32", workloads.spectral_matrix(480, 350, workloads.exp_decay(350, 12.0),
+                                                   4103), 24, 32),
+        ("1000x700 l=30", workloads.spectral_matrix(1000, 700, workloads.exp_decay(700, 9.0),
+                                                    4104), 20, 30),
+        ("1800x900 l=14", workloads.spectral_matrix(1800, 900, workloads.exp_decay(900, 5.0),
+                                                    4105), 8, 14),
+        ("+-1 ties", np.vstack([ties, ties, ties]), 12, 16),
+        ("5 nonzero rows", few, 6, 12),
+    ]
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_register_panel_bitwise_equal_to_lds_panel(rlu, monkeypatch, case):
+    """Panels of one workgroup with at most 32 columns (up to 1024 or 2048
+    rows for 32 or 16 columns) run in registers; with
+    RLU_PANEL_REGS=0 the same panels go to the LDS-resident kernels (one
+    workgroup up to 512 rows, several beyond).  Both take the same
+    multipliers, updates, ranking and ties, so every output agrees bit for
+    bit: on spectral inputs, on exact +-1 ties between identical rows, and
+    on a sketch whose later pivots are exactly zero."""
+    label, A, k, l = _register_panel_cases()[case]
+    m, n = A.shape
+    G = workloads.gaussian((n, l), 4200 + case)
+    Ad, Gd = to_dev_colmajor(A), to_dev_colmajor(G)
+    print(f"[parity] register panel vs LDS panel: {label} m={m} n={n} k={k} l={l}", flush=True)
+    outs = []
+    for regs in ("1", "0"):
+        monkeypatch.setenv("RLU_PANEL_REGS", regs)
+        out = rlu.factor(Ad, k, l, G=Gd, diagnostics=True)
+        torch.cuda.synchronize()
+        outs.append({x: to_host(getattr(out, x)) for x in ("L", "U", "p", "q", "ipiv", "Y", "info")})
+    monkeypatch.delenv("RLU_PANEL_REGS")
+    a, b = outs
+    assert a["info"][2] == 0
+    for x in a:
+        np.testing.assert_array_equal(a[x], b[x], err_msg=x)
+    if label == "5 nonzero rows":
+        assert tuple(a["info"][:2]) == (6, 6)   # zero pivots from step 6 on
