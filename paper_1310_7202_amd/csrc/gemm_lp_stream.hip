@@ -44,31 +44,50 @@ template <> struct Mma16<_Float16> {
 
 constexpr int kBK = 32;           // K per step (one MFMA deep)
 constexpr int kLd = kBK + 8;      // LDS row stride in 16-bit elements (80 bytes)
-constexpr int kDepthA = 4;        // steps of A loads in flight (also the unroll)
-// The small operand is loaded two steps ahead into two register sets (the set
-// a step consumes is refilled right after its MFMAs).  Every load in the loop
-// is unconditional (addresses clamped into the matrix, out-of-range values
+// Loads in flight: kDepth* steps of A, kPre* steps of the small operand (one
+// register set per step, refilled right after the step's MFMAs).  The
+// vector-memory counter retires loads in issue order, so a wait for the
+// small operand of a step also waits for every A load issued before it: the
+// small operand's distance bounds how far ahead A effectively runs, and the
+// two distances are raised together.  Every load in the loop is
+// unconditional (addresses clamped into the matrix, out-of-range values
 // zeroed when they are rounded into LDS), so the body is one basic block and
-// the memory-counter waits count exactly how many loads may stay in flight.
+// the counter waits count exactly how many loads may stay in flight.  The
+// loop is unrolled kDepth* times (a multiple of kPre* and of 2, the LDS
+// buffers).  The widest tiles keep the shallower distances their registers
+// allow.
+template <int TN> struct SketchDepth {
+  static constexpr int kDepth = TN >= 12 ? 4 : 8, kPre = TN >= 12 ? 2 : 4;
+};
+template <int TR> struct ProjectDepth {  // the Lv pair takes twice the registers
+  static constexpr int kDepth = TR >= 9 ? 4 : 6, kPre = TR >= 9 ? 2 : 3;
+};
 
 // ---------------------------------------------------------------------------
 // Step 2.  Workgroup: 64 rows of A x all N_pad = 64 TN columns; wave w owns
 // columns [16 TN w, 16 TN (w + 1)) for all 64 rows (4 x TN MFMA tiles).
-// Per step the workgroup loads A(64 rows, 32 k) (thread: one row, 8 k, eight
-// dword loads, each coalesced over the wave's 64 rows), rounds it to 16 bits
-// and stores it as [row][k] in LDS (one 16-byte store), and each wave reads
-// its G fragments straight from the pre-converted Gb (row = output column, K
-// contiguous).
+// Per step the workgroup loads A(64 rows, 32 k), rounds it to 16 bits and
+// stores it as [row][k] in LDS, and each wave reads its G fragments straight
+// from the pre-converted Gb (row = output column, K contiguous).  A thread
+// loads either four rows at two consecutive k (VEC: two 16-byte loads, for
+// 16-byte aligned columns) or one row at eight k (eight dword loads): a wave
+// may have only so many loads in flight, so the wide form keeps more of A
+// in flight per load issued.
 // ---------------------------------------------------------------------------
-template <typename LP, int TN>
-__global__ void __launch_bounds__(256, 1)
+template <typename LP, int TN, bool VEC, int NW>
+__global__ void __launch_bounds__(64 * NW, 1)
 sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ A, int64_t lda,
                      const LP* __restrict__ Gs, double* __restrict__ C, int64_t ldc, int ksplit,
                      double* __restrict__ partial, int tiles_m, const unsigned* __restrict__ amax) {
   typedef typename Mma16<LP>::vec vec;
+  constexpr int kDepthS = SketchDepth<TN>::kDepth, kPreS = SketchDepth<TN>::kPre;
   const float asc = lp_scale(amax);  // A's range scale (FP16), undone on the output
   const double ainv = 1.0 / (double)asc;
-  constexpr int NP = 64 * TN;  // padded columns of Y
+  constexpr int NP = 64 * TN;       // padded columns of Y
+  constexpr int TNW = 4 * TN / NW;  // 16-column tiles of Y per wave
+  constexpr int NT = 64 * NW;       // threads
+  constexpr int RA = 2048 / NT;     // A values per thread and step (8 or 4)
+  constexpr int VK = RA / 4;        // VEC: consecutive k per thread (2 or 1)
   __shared__ __attribute__((aligned(16))) LP As[2][64 * kLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int bx = (int)(blockIdx.x % tiles_m), bz = (int)(blockIdx.x / tiles_m);
@@ -79,63 +98,92 @@ sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ 
   const int nsteps = kbeg < kend ? (int)((kend - kbeg + kBK - 1) / kBK) : 0;
   const int64_t kstep0 = kbeg / kBK;
 
-  f4 acc[4][TN];
+  f4 acc[4][TNW];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int t = 0; t < TN; ++t) acc[a][t] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < TNW; ++t) acc[a][t] = f4{0.f, 0.f, 0.f, 0.f};
 
   if (nsteps > 0) {
-    // this thread's A row (clamped); its k group (8 consecutive k) is the
+    // this thread's A row (clamped); its k group (RA consecutive k) is the
     // wave's, so the k offsets and their clamps are wave-uniform
     const int ar = tid & 63, ag = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool row_ok = m0 + ar < M;
     const int arow = (int)(row_ok ? m0 + ar : M - 1);
     const int64_t kend_t = row_ok ? kend : kbeg;  // no valid k on a row past M
-    float ring[kDepthA][8];
+    // VEC: rows 4 vi .. 4 vi + 3 (the group clamped into the matrix; rows
+    // past M are zeroed when stored) at k VK vp .. VK vp + VK - 1
+    const int vi = tid & 15, vp = tid >> 4;
+    const int64_t vrow = m0 + 4 * vi < M ? m0 + 4 * vi : M - 4;
+    float ring[kDepthS][RA];
     auto load_a = [&](int step, float* r) {
-      const int64_t k0 = kbeg + (int64_t)step * kBK + 8 * ag;
+      if (VEC) {
+        const int64_t k0 = kbeg + (int64_t)step * kBK + VK * vp;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t kk = k0 + e < K ? k0 + e : K - 1;
-        r[e] = (A + kk * lda)[arow];
+        for (int e = 0; e < VK; ++e) {
+          const int64_t kk = k0 + e < K ? k0 + e : K - 1;
+          const float4 x = *(const float4*)(A + kk * lda + vrow);
+          r[4 * e] = x.x; r[4 * e + 1] = x.y; r[4 * e + 2] = x.z; r[4 * e + 3] = x.w;
+        }
+      } else {
+        const int64_t k0 = kbeg + (int64_t)step * kBK + RA * ag;
+#pragma unroll
+        for (int e = 0; e < RA; ++e) {
+          const int64_t kk = k0 + e < K ? k0 + e : K - 1;
+          r[e] = (A + kk * lda)[arow];
+        }
       }
     };
     auto store_a = [&](int buf, int step, const float* r) {
-      const int64_t k0 = kbeg + (int64_t)step * kBK + 8 * ag;
-      vec v;
+      if (VEC) {
+        typedef LP lpv __attribute__((ext_vector_type(VK)));
+        const int64_t k0 = kbeg + (int64_t)step * kBK + VK * vp;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) v[e] = (LP)((k0 + e < kend_t ? r[e] : 0.f) * asc);
-      *(vec*)&As[buf][ar * kLd + 8 * ag] = v;
+        for (int q = 0; q < 4; ++q) {
+          const bool ok = m0 + 4 * vi + q < M;
+          lpv v;
+#pragma unroll
+          for (int e = 0; e < VK; ++e) v[e] = (LP)((ok && k0 + e < kend ? r[4 * e + q] : 0.f) * asc);
+          *(lpv*)&As[buf][(4 * vi + q) * kLd + VK * vp] = v;
+        }
+      } else {
+        typedef LP lpv __attribute__((ext_vector_type(RA)));
+        const int64_t k0 = kbeg + (int64_t)step * kBK + RA * ag;
+        lpv v;
+#pragma unroll
+        for (int e = 0; e < RA; ++e) v[e] = (LP)((k0 + e < kend_t ? r[e] : 0.f) * asc);
+        *(lpv*)&As[buf][ar * kLd + RA * ag] = v;
+      }
     };
     // this wave's G fragments: column n0w + 16 t + (lane & 15), k 8 (lane >> 4);
     // steps past the end re-read the last step (their A is zero)
     // (16-byte units: a step block is NP rows x 4; a 16-row tile is 64)
-    const int gv = (wave * 16 * TN + (lane & 15)) * 4 + (lane >> 4);
+    const int gv = (wave * 16 * TNW + (lane & 15)) * 4 + (lane >> 4);
     auto load_g = [&](int step, vec* g) {
       const int st = step < nsteps ? step : nsteps - 1;
       const vec* blk = (const vec*)Gs + (kstep0 + st) * (int64_t)(NP * 4);
 #pragma unroll
-      for (int t = 0; t < TN; ++t) g[t] = blk[gv + 64 * t];
+      for (int t = 0; t < TNW; ++t) g[t] = blk[gv + 64 * t];
     };
 
-    vec gset[2][TN];
+    vec gset[kPreS][TNW];
 #pragma unroll
-    for (int d = 0; d < kDepthA; ++d) load_a(d, ring[d]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_g(0, gset[0]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_g(1, gset[1]);
+    for (int d = 0; d < kDepthS; ++d) load_a(d, ring[d]);
+#pragma unroll
+    for (int d = 0; d < kPreS; ++d) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_g(d, gset[d]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     store_a(0, 0, ring[0]);
-    load_a(kDepthA, ring[0]);
+    load_a(kDepthS, ring[0]);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     const int kof = 8 * (lane >> 4);
-    const int nloop = (nsteps + kDepthA - 1) / kDepthA * kDepthA;
-    for (int s0 = 0; s0 < nloop; s0 += kDepthA) {
+    const int nloop = (nsteps + kDepthS - 1) / kDepthS * kDepthS;
+    for (int s0 = 0; s0 < nloop; s0 += kDepthS) {
 #pragma unroll
-      for (int u = 0; u < kDepthA; ++u) {
+      for (int u = 0; u < kDepthS; ++u) {
         const int s = s0 + u, buf = u & 1;
         vec af[4];
 #pragma unroll
@@ -144,16 +192,16 @@ sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ 
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int t = 0; t < TN; ++t) acc[a][t] = Mma16<LP>::mma(af[a], gset[u & 1][t], acc[a][t]);
+          for (int t = 0; t < TNW; ++t) acc[a][t] = Mma16<LP>::mma(af[a], gset[u % kPreS][t], acc[a][t]);
         // program order is kept (the fences stop the scheduler from moving
         // the refills, and with them the counter waits, across the MFMAs)
         __builtin_amdgcn_sched_barrier(0);
-        load_g(s + 2, gset[u & 1]);
+        load_g(s + kPreS, gset[u % kPreS]);
         __builtin_amdgcn_sched_barrier(0);
-        // step s+1's A (loaded kDepthA - 1 steps ago) into the other buffer,
-        // then that ring slot takes step s+1+kDepthA
-        store_a(buf ^ 1, s + 1, ring[(u + 1) % kDepthA]);
-        load_a(s + 1 + kDepthA, ring[(u + 1) % kDepthA]);
+        // step s+1's A (loaded kDepthS - 1 steps ago) into the other buffer,
+        // then that ring slot takes step s+1+kDepthS
+        store_a(buf ^ 1, s + 1, ring[(u + 1) % kDepthS]);
+        load_a(s + 1 + kDepthS, ring[(u + 1) % kDepthS]);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
       }
@@ -162,11 +210,11 @@ sketch_stream_kernel(int64_t M, int64_t N, int64_t K, const float* __restrict__ 
 
   double* out = ksplit > 1 ? partial + (int64_t)bz * M * N : C;
   const int64_t ldo = ksplit > 1 ? M : ldc;
-  const int64_t n0w = (int64_t)wave * 16 * TN;
+  const int64_t n0w = (int64_t)wave * 16 * TNW;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int t = 0; t < TN; ++t) {
+    for (int t = 0; t < TNW; ++t) {
       const int64_t col = n0w + 16 * t + (lane & 15);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -209,20 +257,29 @@ hipError_t launch_sketch_stream(const GemmDesc& d, hipStream_t s) {
   if (d.ksplit_out) *d.ksplit_out = ks;
   const int tn = (int)(npad / 64);
   const dim3 grid((unsigned)(tiles_m * ks));
-#define RLU_SKS(TN)                                                                          \
-  hipLaunchKernelGGL((sketch_stream_kernel<LP, TN>), grid, dim3(256), 0, s, d.M, d.N, d.K,    \
-                     (const float*)d.A, d.lda, (const LP*)Gs, (double*)d.C, d.ldc, ks,       \
-                     (double*)d.partial, tiles_m, d.amax)
+  const bool vec = d.M % 4 == 0 && d.lda % 4 == 0 && ((uintptr_t)d.A & 15) == 0;
+#define RLU_SKS1(TN, V, NW)                                                                   \
+  hipLaunchKernelGGL((sketch_stream_kernel<LP, TN, V, NW>), grid, dim3(64 * NW), 0, s, d.M,    \
+                     d.N, d.K, (const float*)d.A, d.lda, (const LP*)Gs, (double*)d.C, d.ldc,  \
+                     ks, (double*)d.partial, tiles_m, d.amax)
+  // eight waves (two per SIMD) where the columns split evenly over them
+#define RLU_SKS(TN)                              \
+  if (vec)                                       \
+    RLU_SKS1(TN, true, (TN % 2 == 0 ? 8 : 4));   \
+  else                                           \
+    RLU_SKS1(TN, false, (TN % 2 == 0 ? 8 : 4))
   switch (tn) {
     case 1: RLU_SKS(1); break;
     case 2: RLU_SKS(2); break;
     case 4: RLU_SKS(4); break;
     case 6: RLU_SKS(6); break;
+    case 8: RLU_SKS(8); break;
     case 9: RLU_SKS(9); break;
     case 12: RLU_SKS(12); break;
     default: return hipErrorInvalidValue;
   }
 #undef RLU_SKS
+#undef RLU_SKS1
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;
   return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
@@ -238,16 +295,20 @@ hipError_t launch_sketch_stream(const GemmDesc& d, hipStream_t s) {
 // [column][k] (the B-fragment layout), and each wave reads its Lv fragments
 // straight from the pre-converted pair (row i of Lv^T, K contiguous).
 // ---------------------------------------------------------------------------
-template <typename LP, int TR, bool VEC>
-__global__ void __launch_bounds__(256, 1)
+template <typename LP, int TR, bool VEC, int NW>
+__global__ void __launch_bounds__(64 * NW, 1)
 project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls,
                       const float* __restrict__ A, int64_t lda, double* __restrict__ C,
                       int64_t ldc, int ksplit, double* __restrict__ partial, int tiles_n,
                       const unsigned* __restrict__ amax) {
   typedef typename Mma16<LP>::vec vec;
+  constexpr int kDepthP = ProjectDepth<TR>::kDepth, kPreP = ProjectDepth<TR>::kPre;
   const float asc = lp_scale(amax);  // A's range scale (FP16), undone on the output
   const double ainv = 1.0 / (double)asc;
-  constexpr int RP = 64 * TR;  // padded rows of C
+  constexpr int RP = 64 * TR;      // padded rows of C
+  constexpr int TRW = 4 * TR / NW;  // 16-row tiles of C per wave
+  constexpr int NT = 64 * NW;       // threads
+  constexpr int AJ = 512 / NT;      // float4 of A per thread and step
   typedef LP lp4 __attribute__((ext_vector_type(4)));
   __shared__ __attribute__((aligned(16))) LP Bs[2][64 * kLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -258,22 +319,22 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
   const int64_t kend = kbeg + kchunk < K ? kbeg + kchunk : K;
   const int nsteps = kbeg < kend ? (int)((kend - kbeg + kBK - 1) / kBK) : 0;
   const int64_t kstep0 = kbeg / kBK;
-  const int64_t r0w = (int64_t)wave * 16 * TR;
+  const int64_t r0w = (int64_t)wave * 16 * TRW;
 
-  f4 acc[TR][4];
+  f4 acc[TRW][4];
 #pragma unroll
-  for (int a = 0; a < TR; ++a)
+  for (int a = 0; a < TRW; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = f4{0.f, 0.f, 0.f, 0.f};
 
   if (nsteps > 0) {
     // this thread's two float4 of A per step: column f >> 3 (clamped), k 4 (f & 7)
-    int bcol[2], bk[2];
-    int64_t kend_t[2];  // kbeg on a column past N: no valid k there
-    const float* Acol[2];
+    int bcol[AJ], bk[AJ];
+    int64_t kend_t[AJ];  // kbeg on a column past N: no valid k there
+    const float* Acol[AJ];
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int f = tid + 256 * j;
+    for (int j = 0; j < AJ; ++j) {
+      const int f = tid + NT * j;
       bcol[j] = f >> 3;
       bk[j] = 4 * (f & 7);
       const bool col_ok = n0 + bcol[j] < N;
@@ -281,11 +342,11 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
       Acol[j] = A + (col_ok ? n0 + bcol[j] : N - 1) * lda;
     }
     const int64_t kmax4 = (K - 4) & ~(int64_t)3;  // last aligned float4 inside a column
-    float4 ring[kDepthA][2];
+    float4 ring[kDepthP][AJ];
     auto load_a = [&](int step, float4* r) {
       const int64_t k0 = kbeg + (int64_t)step * kBK;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < AJ; ++j) {
         const int64_t kk = k0 + bk[j];
         if (VEC) {
           r[j] = *(const float4*)(Acol[j] + (kk < kmax4 ? kk : kmax4));
@@ -300,7 +361,7 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
     auto store_a = [&](int buf, int step, const float4* r) {
       const int64_t k0 = kbeg + (int64_t)step * kBK;
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < AJ; ++j) {
         const int64_t kk = k0 + bk[j];
         const float x[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
         lp4 v;
@@ -313,51 +374,52 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
     // steps past the end re-read the last step (their A is zero)
     // (16-byte units: a step block is 2 x RP rows x 4, hi then lo; a
     // 16-row tile is 64)
-    const int lv = (wave * 16 * TR + (lane & 15)) * 4 + (lane >> 4);
+    const int lv = (wave * 16 * TRW + (lane & 15)) * 4 + (lane >> 4);
     auto load_l = [&](int step, vec* h, vec* lo) {
       const int st = step < nsteps ? step : nsteps - 1;
       const vec* blk = (const vec*)Ls + (kstep0 + st) * (int64_t)(2 * RP * 4);
 #pragma unroll
-      for (int a = 0; a < TR; ++a) {
+      for (int a = 0; a < TRW; ++a) {
         h[a] = blk[lv + 64 * a];
         lo[a] = blk[RP * 4 + lv + 64 * a];
       }
     };
 
-    vec hset[2][TR], lset[2][TR];
+    vec hset[kPreP][TRW], lset[kPreP][TRW];
 #pragma unroll
-    for (int d = 0; d < kDepthA; ++d) load_a(d, ring[d]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_l(0, hset[0], lset[0]);
-    __builtin_amdgcn_sched_barrier(0);
-    load_l(1, hset[1], lset[1]);
+    for (int d = 0; d < kDepthP; ++d) load_a(d, ring[d]);
+#pragma unroll
+    for (int d = 0; d < kPreP; ++d) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_l(d, hset[d], lset[d]);
+    }
     __builtin_amdgcn_sched_barrier(0);
     store_a(0, 0, ring[0]);
-    load_a(kDepthA, ring[0]);
+    load_a(kDepthP, ring[0]);
     __builtin_amdgcn_sched_barrier(0);
     __syncthreads();
     const int kof = 8 * (lane >> 4);
-    const int nloop = (nsteps + kDepthA - 1) / kDepthA * kDepthA;
-    for (int s0 = 0; s0 < nloop; s0 += kDepthA) {
+    const int nloop = (nsteps + kDepthP - 1) / kDepthP * kDepthP;
+    for (int s0 = 0; s0 < nloop; s0 += kDepthP) {
 #pragma unroll
-      for (int u = 0; u < kDepthA; ++u) {
+      for (int u = 0; u < kDepthP; ++u) {
         const int s = s0 + u, buf = u & 1;
         vec bf[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c)
           bf[c] = *(const vec*)&Bs[buf][(16 * c + (lane & 15)) * kLd + kof];
 #pragma unroll
-        for (int a = 0; a < TR; ++a)
+        for (int a = 0; a < TRW; ++a)
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            acc[a][c] = Mma16<LP>::mma(hset[u & 1][a], bf[c], acc[a][c]);
-            acc[a][c] = Mma16<LP>::mma(lset[u & 1][a], bf[c], acc[a][c]);
+            acc[a][c] = Mma16<LP>::mma(hset[u % kPreP][a], bf[c], acc[a][c]);
+            acc[a][c] = Mma16<LP>::mma(lset[u % kPreP][a], bf[c], acc[a][c]);
           }
         __builtin_amdgcn_sched_barrier(0);
-        load_l(s + 2, hset[u & 1], lset[u & 1]);
+        load_l(s + kPreP, hset[u % kPreP], lset[u % kPreP]);
         __builtin_amdgcn_sched_barrier(0);
-        store_a(buf ^ 1, s + 1, ring[(u + 1) % kDepthA]);
-        load_a(s + 1 + kDepthA, ring[(u + 1) % kDepthA]);
+        store_a(buf ^ 1, s + 1, ring[(u + 1) % kDepthP]);
+        load_a(s + 1 + kDepthP, ring[(u + 1) % kDepthP]);
         __builtin_amdgcn_sched_barrier(0);
         __syncthreads();
       }
@@ -367,7 +429,7 @@ project_stream_kernel(int64_t M, int64_t N, int64_t K, const LP* __restrict__ Ls
   double* out = ksplit > 1 ? partial + (int64_t)bz * M * N : C;
   const int64_t ldo = ksplit > 1 ? M : ldc;
 #pragma unroll
-  for (int a = 0; a < TR; ++a)
+  for (int a = 0; a < TRW; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t col = n0 + 16 * c + (lane & 15);
@@ -422,15 +484,16 @@ hipError_t launch_project_stream(const GemmDesc& d, hipStream_t s) {
   const int tr = (int)(rpad / 64);
   const dim3 grid((unsigned)(tiles_n * ks));
   const bool vec = d.ldb % 4 == 0 && ((uintptr_t)d.B & 15) == 0;
-#define RLU_PJS(TR)                                                                            \
-  if (vec)                                                                                     \
-    hipLaunchKernelGGL((project_stream_kernel<LP, TR, true>), grid, dim3(256), 0, s, d.M, d.N, \
-                       d.K, (const LP*)Ls, (const float*)d.B, d.ldb, (double*)d.C, d.ldc, ks,  \
-                       (double*)d.partial, tiles_n, d.amax);                                   \
-  else                                                                                         \
-    hipLaunchKernelGGL((project_stream_kernel<LP, TR, false>), grid, dim3(256), 0, s, d.M,     \
-                       d.N, d.K, (const LP*)Ls, (const float*)d.B, d.ldb, (double*)d.C, d.ldc, \
-                       ks, (double*)d.partial, tiles_n, d.amax)
+#define RLU_PJS1(TR, V, NW)                                                                   \
+  hipLaunchKernelGGL((project_stream_kernel<LP, TR, V, NW>), grid, dim3(64 * NW), 0, s, d.M,  \
+                     d.N, d.K, (const LP*)Ls, (const float*)d.B, d.ldb, (double*)d.C, d.ldc,  \
+                     ks, (double*)d.partial, tiles_n, d.amax)
+  // eight waves (two per SIMD) where the rows of C split evenly over them
+#define RLU_PJS(TR)                                 \
+  if (vec)                                          \
+    RLU_PJS1(TR, true, (TR % 2 == 0 ? 8 : 4));      \
+  else                                              \
+    RLU_PJS1(TR, false, (TR % 2 == 0 ? 8 : 4))
   switch (tr) {
     case 1: RLU_PJS(1); break;
     case 2: RLU_PJS(2); break;
@@ -441,6 +504,7 @@ hipError_t launch_project_stream(const GemmDesc& d, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
 #undef RLU_PJS
+#undef RLU_PJS1
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || ks == 1 || d.no_sum) return e;
   return launch_splitk_sum_f64(d.M, d.N, ks, (const double*)d.partial, (double*)d.C, d.ldc,
@@ -450,7 +514,7 @@ hipError_t launch_project_stream(const GemmDesc& d, hipStream_t s) {
 }  // namespace
 
 int64_t stream_sketch_npad(int64_t N) {
-  static const int kTn[] = {1, 2, 4, 6, 9, 12};
+  static const int kTn[] = {1, 2, 4, 6, 8, 9, 12};
   for (int t : kTn)
     if (N <= 64 * t) return 64 * t;
   return -1;
