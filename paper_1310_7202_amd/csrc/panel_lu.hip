@@ -1151,36 +1151,64 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restric
     const int h = min(16, w - J0), len = J0 + h;
     if (tid < h) prow_s[tid] = piv_row[J0 + tid];
     __syncthreads();
+    // this chunk's right-hand sides, loaded beside the L11 rows
+    double acc[2] = {0.0, 0.0};
+    if (jj < h) {
+      const int64_t prow = prow_s[jj];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int c = cc0 + cg + 16 * q;
+        acc[q] = c < nrhs ? X[prow + (c1 + c) * ldx] : 0.0;
+      }
+    }
     for (int e = tid; e < h * len; e += 256) {
       const int r = e / len, i = e % len;
       Ls[r * w + i] = X[(int64_t)prow_s[r] + (int64_t)(c0 + i) * ldx];
     }
     __syncthreads();
     if (jj < h) {
-      const int64_t prow = prow_s[jj];
-      double acc[2];
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int c = cc0 + cg + 16 * q;
-        acc[q] = c < nrhs ? X[prow + (c1 + c) * ldx] : 0.0;
-      }
+      // the rows already solved (J0 is a multiple of 16): four partial sums
+      // per output over i mod 4, so that four multiply-add chains run side by
+      // side, added in a fixed order
       const double* lr = Ls + jj * w;
-      for (int i = 0; i < J0; ++i) {
-        const double l = lr[i];
+      double part[4][2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) acc[q] = __fma_rn(-l, Us[i * kTrsmCols + cg + 16 * q], acc[q]);
+      for (int t = 0; t < 4; ++t) part[t][0] = part[t][1] = 0.0;
+      for (int i = 0; i < J0; i += 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const double l = lr[i + t];
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            part[t][q] = __fma_rn(-l, Us[(i + t) * kTrsmCols + cg + 16 * q], part[t][q]);
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q) Us[(J0 + jj) * kTrsmCols + cg + 16 * q] = acc[q];
+      for (int q = 0; q < 2; ++q)
+        Us[(J0 + jj) * kTrsmCols + cg + 16 * q] =
+            acc[q] + ((part[0][q] + part[1][q]) + (part[2][q] + part[3][q]));
     }
     __syncthreads();
     if (wave == 0 && lane < kTrsmCols) {
-      for (int r = 1; r < h; ++r) {
-        double u = Us[(J0 + r) * kTrsmCols + lane];
-        for (int i = 0; i < r; ++i)
-          u = __fma_rn(-Ls[r * w + J0 + i], Us[(J0 + i) * kTrsmCols + lane], u);
-        Us[(J0 + r) * kTrsmCols + lane] = u;
-      }
+      // the 16 x 16 triangle in registers, a lane per column: once u_i is
+      // final it updates every later row, so each u_r still takes its
+      // terms in increasing i (the order of the dot-product form) while
+      // the updates of one i run side by side
+      // (straight-line, so that every LDS read is issued up front: rows
+      // past the last, h <= r < 16, repeat row h-1 and are never stored;
+      // they feed only rows after themselves)
+      const int hm = h - 1;
+      double u[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) u[r] = Us[(J0 + min(r, hm)) * kTrsmCols + lane];
+#pragma unroll
+      for (int i = 0; i < 15; ++i)
+#pragma unroll
+        for (int r = i + 1; r < 16; ++r)
+          u[r] = __fma_rn(-Ls[min(r, hm) * w + J0 + min(i, hm)], u[i], u[r]);
+#pragma unroll
+      for (int r = 1; r < 16; ++r)
+        if (r < h) Us[(J0 + r) * kTrsmCols + lane] = u[r];
     }
     __syncthreads();
   }
