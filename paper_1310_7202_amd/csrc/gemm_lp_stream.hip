@@ -64,15 +64,16 @@ template <int TR> struct ProjectDepth {  // the Lv pair takes twice the register
 };
 
 // ---------------------------------------------------------------------------
-// Step 2.  Workgroup: 64 rows of A x all N_pad = 64 TN columns; wave w owns
-// columns [16 TN w, 16 TN (w + 1)) for all 64 rows (4 x TN MFMA tiles).
-// Per step the workgroup loads A(64 rows, 32 k), rounds it to 16 bits and
-// stores it as [row][k] in LDS, and each wave reads its G fragments straight
-// from the pre-converted Gb (row = output column, K contiguous).  A thread
-// loads either four rows at two consecutive k (VEC: two 16-byte loads, for
-// 16-byte aligned columns) or one row at eight k (eight dword loads): a wave
-// may have only so many loads in flight, so the wide form keeps more of A
-// in flight per load issued.
+// Step 2.  Workgroup of NW waves (4, or 8 = two per SIMD when the columns
+// split evenly): 64 rows of A x all N_pad = 64 TN columns; wave w owns
+// columns [16 TNW w, 16 TNW (w + 1)), TNW = 4 TN / NW, for all 64 rows
+// (4 x TNW MFMA tiles).  Per step the workgroup loads A(64 rows, 32 k),
+// rounds it to 16 bits and stores it as [row][k] in LDS, and each wave
+// reads its G fragments straight from the pre-converted Gb (row = output
+// column, K contiguous).  A thread loads either four rows at consecutive k
+// (VEC: 16-byte loads, for 16-byte aligned columns) or one row at several
+// k (dword loads): a wave may have only so many loads in flight, so the
+// wide form keeps more of A in flight per load issued.
 // ---------------------------------------------------------------------------
 template <typename LP, int TN, bool VEC, int NW>
 __global__ void __launch_bounds__(64 * NW, 1)
@@ -287,13 +288,15 @@ hipError_t launch_sketch_stream(const GemmDesc& d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Step 5.  C (R x N) = Lv^T A.  Workgroup: 64 columns of A x all R_pad = 64 TR
-// rows of C; wave w owns rows [16 TR w, 16 TR (w + 1)) for all 64 columns
-// (TR x 4 MFMA tiles, two MFMAs each for the hi and lo parts of Lv).  Per
-// step the workgroup loads A(32 k, 64 columns) (a wave: 8 columns x 128
-// contiguous bytes per float4 load), rounds it to 16 bits into LDS as
-// [column][k] (the B-fragment layout), and each wave reads its Lv fragments
-// straight from the pre-converted pair (row i of Lv^T, K contiguous).
+// Step 5.  C (R x N) = Lv^T A.  Workgroup of NW waves (4, or 8 = two per
+// SIMD when the rows split evenly): 64 columns of A x all R_pad = 64 TR rows
+// of C; wave w owns rows [16 TRW w, 16 TRW (w + 1)), TRW = 4 TR / NW, for
+// all 64 columns (TRW x 4 MFMA tiles, two MFMAs each for the hi and lo parts
+// of Lv).  Per step the workgroup loads A(32 k, 64 columns) (a wave: 8
+// columns x 128 contiguous bytes per float4 load), rounds it to 16 bits into
+// LDS as [column][k] (the B-fragment layout), and each wave reads its Lv
+// fragments straight from the pre-converted pair (row i of Lv^T, K
+// contiguous).
 // ---------------------------------------------------------------------------
 template <typename LP, int TR, bool VEC, int NW>
 __global__ void __launch_bounds__(64 * NW, 1)

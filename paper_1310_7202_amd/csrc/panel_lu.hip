@@ -7,7 +7,13 @@
 //           B and produces the same pivot sequence.
 // The Remark after Algorithm 4.1 allows partial pivoting in Step 3.
 //
-// Design (one persistent cooperative launch, no host round trip):
+// Two kernels: panel_lu_kernel below for panels spread over workgroups, and
+// panel_small_kernel (further down) for panels of at most 32 columns whose
+// rows fit one workgroup's registers; both make the same choices and give
+// the same bits.
+//
+// Design of the spread kernel (one persistent cooperative launch, no host
+// round trip):
 //   * workgroup w keeps rows [w R, (w+1) R) of X resident in LDS for the whole
 //     factorization; rows never move ("virtual" pivoting): each row records
 //     its current position (to reproduce LAPACK's swap bookkeeping and its
@@ -1128,10 +1134,12 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
 //   L11 U12 = X(pr, c1:),   L11(j, i) = X(pr_j, c0 + i) for i < j (unit lower),
 // with pr_j = piv_row[j] the row chosen at step c0 + j.  Workgroup b solves
 // 32 right-hand-side columns with U12 in LDS, 16 rows at a time: the 16 rows
-// of L11 the step needs are first gathered into LDS by all threads (the
-// solve's dependency chain then only touches LDS), then the product with
-// the rows already solved by all 256 threads, then the 16 x 16 triangle by
-// one wave.  Output U (w x nrhs, leading dimension w).
+// of L11 the step needs are first gathered into LDS by all threads, beside
+// their right-hand sides (the solve's dependency chain then only touches
+// LDS and registers), then the product with the rows already solved by all
+// 256 threads (four multiply-add chains per output), then the 16 x 16
+// triangle by one wave, in registers.  Output U (w x nrhs, leading
+// dimension w).
 // ---------------------------------------------------------------------------
 constexpr int kTrsmMaxW = 288;
 constexpr int kTrsmCols = 32;
