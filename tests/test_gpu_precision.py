@@ -216,3 +216,16 @@ def test_fp16_far_from_unit_scale(rlu, scale):
     as at unit scale."""
     A = workloads.spectral_matrix(1600, 1200, workloads.exp_decay(1200, 12.0), 830) * scale
     check_mixed(rlu, A, 40, 48, 831, True, f"fp16 scale {scale:g}")
+
+
+@pytest.mark.parametrize("fp16", [False, True])
+@pytest.mark.parametrize("m,n,k,l", [
+    (2048, 1536, 280, 300),   # sketch 384 padded columns, projection 384 rows (eight waves)
+    (2048, 1200, 430, 450),   # 512 columns, 512 rows (eight waves)
+    (3000, 1100, 560, 700),   # 768 columns (eight waves), 576 rows (four waves)
+])
+def test_mixed_wide_streaming_tiles(rlu, m, n, k, l, fp16):
+    """The streaming products at the wider compiled widths (K >= 1024 on
+    both passes), by the same rule as every mixed case."""
+    A = workloads.spectral_matrix(m, n, workloads.exp_decay(min(m, n), l / 4.0), 900 + l)
+    check_mixed(rlu, A, k, l, 910 + l, fp16, "mixed wide tiles")
