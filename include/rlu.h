@@ -54,6 +54,12 @@
  * exchange area, the split-K partials) is reused by every call, and nothing
  * orders calls on different streams, so a caller that switches streams
  * must order the calls itself (or use one handle per stream).
+ *
+ * Environment (tuning and tests; results are the same bits either way):
+ *   RLU_PANEL_WG_CAP  16..256, read once per process: the most workgroups
+ *                     a pivoted LU spread over workgroups aims at (128).
+ *   RLU_PANEL_REGS=0  read at each call: pivoted LUs that fit one
+ *                     workgroup's registers use the LDS-resident kernels.
  */
 #ifndef RLU_H
 #define RLU_H
