@@ -343,7 +343,11 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   void* xch = at<void>(ws, Ly.xch);
   const bool diag = (pb.flags & RLU_FLAG_DIAGNOSTICS) != 0;
 
-  HIP_TRY(launch_fill_u32((uint32_t*)flags, 16, 0u, s));
+  // the flags start at zero: cleared by Step 1's Gaussian launch when this
+  // call draws G (one launch less on small problems), else by a fill here
+  const bool clear_in_step1 = !(pb.flags & RLU_FLAG_FAST) && !pb.G && !(lp && fp16) &&
+                              !h->xch_preset_fail;
+  if (!clear_in_step1) HIP_TRY(launch_fill_u32((uint32_t*)flags, 16, 0u, s));
   // a test of the failure path: the exchange starts as if a partner had
   // already given up
   if (h->xch_preset_fail) HIP_TRY(launch_fill_u32((uint32_t*)flags + 2, 1, 1u, s));
@@ -369,7 +373,8 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
   } else if (!G) {
     T* Gw = at<T>(ws, Ly.G);
     PhaseScope ph(h, PH_GAUSSIAN, s);
-    HIP_TRY(launch_gaussian<T>(Gw, n, n, l, pb.seed, s));
+    HIP_TRY(launch_gaussian<T>(Gw, n, n, l, pb.seed, s,
+                               clear_in_step1 ? (uint32_t*)flags : nullptr));
     G = Gw;
     ldg = n;
   }

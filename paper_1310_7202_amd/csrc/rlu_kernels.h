@@ -8,9 +8,11 @@
 namespace rlu {
 
 // ----- Step 1: Gaussian test matrix (rng.hip) ------------------------------
+// clear (optional): 16 words the launch also sets to zero (a call's flags,
+// saving it a launch of its own).
 template <typename T>
 hipError_t launch_gaussian(T* G, int64_t ldg, int64_t n, int64_t l, uint64_t seed,
-                           hipStream_t s);
+                           hipStream_t s, uint32_t* clear = nullptr);
 struct GaussTaskDev { void* G; int64_t ldg, n, l; uint64_t seed; };
 // One launch for a batch of test matrices (max_elems = largest n l).
 template <typename T>

@@ -59,7 +59,9 @@ __device__ __forceinline__ void gaussian_body(T* __restrict__ G, int64_t ldg, in
 
 template <typename T>
 __global__ void __launch_bounds__(256) gaussian_kernel(T* __restrict__ G, int64_t ldg, int64_t n,
-                                                       int64_t l, uint32_t k0, uint32_t k1) {
+                                                       int64_t l, uint32_t k0, uint32_t k1,
+                                                       uint32_t* __restrict__ clear) {
+  if (clear && blockIdx.x == 0 && threadIdx.x < 16) clear[threadIdx.x] = 0u;
   gaussian_body<T>(G, ldg, n, l, k0, k1);
 }
 
@@ -164,20 +166,20 @@ template hipError_t launch_srft<float>(float*, int64_t, int64_t, int, uint64_t, 
 
 template <typename T>
 hipError_t launch_gaussian(T* G, int64_t ldg, int64_t n, int64_t l, uint64_t seed,
-                           hipStream_t s) {
+                           hipStream_t s, uint32_t* clear) {
   const int64_t npairs = (n * l + 1) / 2;
   int64_t blocks = (npairs + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(gaussian_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, s, G, ldg, n, l,
-                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32));
+                     (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), clear);
   return hipGetLastError();
 }
 
 template hipError_t launch_gaussian<double>(double*, int64_t, int64_t, int64_t, uint64_t,
-                                            hipStream_t);
+                                            hipStream_t, uint32_t*);
 template hipError_t launch_gaussian<float>(float*, int64_t, int64_t, int64_t, uint64_t,
-                                           hipStream_t);
+                                           hipStream_t, uint32_t*);
 
 template <typename T>
 hipError_t launch_gaussian_batched(const GaussTaskDev* tasks, int count, int64_t max_elems,
