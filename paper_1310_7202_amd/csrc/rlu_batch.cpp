@@ -92,13 +92,18 @@ struct Plan {
   size_t asmb = 0; int64_t asm_max = 0;
 };
 
-// Rows per workgroup of a panel: the largest multiple of 64 (at most 512)
-// whose LDS image fits for a panel of that width.
+// Rows per workgroup of a panel: the most (at most 512) whose LDS image fits
+// for a panel of that width, together with the margin plan_panels adds for a
+// launch compiled for 512 rows.  The panel kernel takes any row count up to
+// its compiled one, so the count need not be a power of two: fewer
+// workgroups per panel means fewer rounds of the batched launch.
 constexpr size_t kPanelLdsBudget = 159 * 1024;
 
 int panel_rows_for(int ncols) {
-  for (int rpl = 8; rpl >= 1; rpl >>= 1)
-    if (panel_lds_bytes(64 * rpl, ncols) <= kPanelLdsBudget) return 64 * rpl;
+  for (int r = 512; r >= 1; --r)
+    if (panel_lds_bytes(r, ncols) <= kPanelLdsBudget &&
+        (size_t)8 * ((size_t)(ncols - 1) * r + 512) <= kPanelLdsBudget)
+      return r;
   return 0;
 }
 

@@ -209,11 +209,13 @@ def test_serve_mixed_precision_stream(rlu):
 
 
 def test_oversize_request_runs_alone_in_the_mix(rlu):
-    """A request whose panel does not fit the batched kernels (20000 rows,
-    l = 210) runs through the single-problem path, interleaved with batched
-    requests; its factors equal a direct rlu_factor call."""
+    """A request whose panel does not fit the batched kernels (30000 rows,
+    l = 210: at most 91 rows of that width fit one workgroup's LDS, so the
+    panel would need 330 workgroups, more than a gang may have) runs through
+    the single-problem path, interleaved with batched requests; its factors
+    equal a direct rlu_factor call."""
     srv = rlu.Server(0)
-    m, n, k, l = 20000, 1500, 200, 210
+    m, n, k, l = 30000, 1500, 200, 210
     A = workloads.low_rank_plus_noise_torch(m, n, k, 1e-6, 31, dtype=torch.float64)
     ref = rlu.factor(A, k, l, seed=9)
     small = _inputs(1600)
