@@ -201,7 +201,8 @@ def phase_work(m, n, k, l, s_a, s_out, prod="fp64"):
         "project_gemm": (2.0 * m * n * k, s_a * m * n + 8.0 * m * k + 8.0 * k * n, pk),
         "solve_gemm": (2.0 * k * k * n, 16.0 * k * n + 8.0 * k * k, "f64"),
         "panel_lu_bt": (n * k * k - k ** 3 / 3.0, 16.0 * k * n, "f64"),
-        "form_l_gemm": (2.0 * m * k * k, 8.0 * m * k + s_out * m * k, "f64"),
+        # L_b is unit lower triangular: row i of L takes k(k-1)/2 products
+        "form_l_gemm": (m * k * (k - 1.0), 8.0 * m * k + s_out * m * k, "f64"),
     }
 
 

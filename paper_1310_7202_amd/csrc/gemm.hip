@@ -52,7 +52,7 @@ __device__ __forceinline__ void gemm_tile(
     const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
     const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
     const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int bx, int by,
-    int bz, int acol0 = 0, int csub = 0) {
+    int bz, int acol0 = 0, int csub = 0, int blower = 0) {
   constexpr bool AK = (OA == OpA::LvT);  // A operand contiguous along K
   constexpr bool BKC = true;             // B operands are contiguous along K
   typedef Tile<BM, BN, BK, WM, WN, AK, BKC, NBUF> Tl;
@@ -67,8 +67,14 @@ __device__ __forceinline__ void gemm_tile(
   const int64_t n0 = (int64_t)by * BN;
   // K range of this split (multiples of BK)
   const int64_t kchunk = ((K + ksplit - 1) / ksplit + BK - 1) / BK * BK;
-  const int64_t kbeg = (int64_t)bz * kchunk;
+  int64_t kbeg = (int64_t)bz * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
+  // B lower triangular (B(t, j) = 0 for t < j): the tile's columns start at
+  // n0, so the K slices wholly above row n0 add only exact zeros; skip them
+  if (blower) {
+    const int64_t kb = n0 / BK * BK;
+    if (kb > kbeg) kbeg = kb;
+  }
 
   // Prefetch registers hold the operands in their storage type: the
   // conversion, and the Lv mapping of the K-contiguous operands (one step
@@ -228,7 +234,7 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
             const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
             const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
             const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int tm, int tn,
-            int nfast, int acol0, int csub) {
+            int nfast, int acol0, int csub, int blower) {
   const int t = xcd_chunked((int)blockIdx.x, (int)gridDim.x);
   int bx, by, bz;
   if (nfast) {
@@ -238,7 +244,7 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
   }
   gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
       M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, bx, by, bz, acol0,
-      csub);
+      csub, blower);
 }
 
 // Many independent products in one launch: workgroup b computes the tile
@@ -375,7 +381,8 @@ hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>),
                      dim3((unsigned)nb), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A,
                      d.lda, d.astep, (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap,
-                     ksplit, (TO*)d.partial, tm, tn, nfast, d.acol0, d.csub ? 1 : 0);
+                     ksplit, (TO*)d.partial, tm, tn, nfast, d.acol0, d.csub ? 1 : 0,
+                     d.b_lower ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -619,6 +619,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.M = m; d.N = k; d.K = k;
     d.A = Y; d.lda = m; d.opa = OpA::Lv; d.astep = rstep_y;
     d.B = Lb; d.ldb = k; d.opb = OpB::Plain;
+    d.b_lower = true;  // L_b is unit lower triangular
     d.C = io.L; d.ldc = io.ldl;
     d.rowmap = pos_y;
     d.ksplit = 1;

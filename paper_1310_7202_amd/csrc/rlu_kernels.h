@@ -53,6 +53,8 @@ struct GemmDesc {
   int* ksplit_out;     // optional: receives the split used (1 = none)
   int acol0;           // LvStrict: global index of the first column of A
   bool csub;           // C -= op(A) op(B) instead of C = ... (requires ksplit 1)
+  bool b_lower;        // op(B) is lower triangular (B(t, j) = 0 for t < j): a tile
+                       // skips the K slices above its first column
   void* lp_ws;         // low-precision products: room for the pre-converted small
                        // operand (stream_sketch_ws_bytes / stream_project_ws_bytes)
   const unsigned* amax;  // FP16 products: max|A| (FP32 bits) for the range scale of A
