@@ -92,15 +92,17 @@ struct Plan {
   size_t asmb = 0; int64_t asm_max = 0;
 };
 
-// Rows per workgroup of a panel: the most (at most 512) whose LDS image fits
-// for a panel of that width, together with the margin plan_panels adds for a
-// launch compiled for 512 rows.  The panel kernel takes any row count up to
-// its compiled one, so the count need not be a power of two: fewer
-// workgroups per panel means fewer rounds of the batched launch.
+// Rows per workgroup of a panel: the most (at most 512, at least 64) whose
+// LDS image fits for a panel of that width, together with the margin
+// plan_panels adds for a launch compiled for 512 rows.  The panel kernel
+// takes any row count up to its compiled one, so the count need not be a
+// power of two: fewer workgroups per panel means fewer rounds of the batched
+// launch.  A panel too wide for 64 rows (more than 294 columns) makes the
+// batch unsupported (the server runs such a request alone).
 constexpr size_t kPanelLdsBudget = 159 * 1024;
 
 int panel_rows_for(int ncols) {
-  for (int r = 512; r >= 1; --r)
+  for (int r = 512; r >= 64; --r)
     if (panel_lds_bytes(r, ncols) <= kPanelLdsBudget &&
         (size_t)8 * ((size_t)(ncols - 1) * r + 512) <= kPanelLdsBudget)
       return r;
