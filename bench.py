@@ -196,7 +196,8 @@ def phase_work(m, n, k, l, s_a, s_out, prod="fp64"):
     return {
         "sketch_gemm": (2.0 * m * n * l, s_a * m * n + s_a * n * l + 8.0 * m * l, pk),
         "panel_lu_y": (m * l * l - l ** 3 / 3.0, 16.0 * m * l, "f64"),
-        "gram_gemm": (2.0 * m * k * k, 8.0 * m * k, "f64"),
+        # S = Lv^T Lv is symmetric: k(k+1)/2 distinct entries of m products each
+        "gram_gemm": (m * k * (k + 1.0), 8.0 * m * k, "f64"),
         "gram_inverse": (2.0 * k ** 3, 16.0 * k * k, "f64"),
         "project_gemm": (2.0 * m * n * k, s_a * m * n + 8.0 * m * k + 8.0 * k * n, pk),
         "solve_gemm": (2.0 * k * k * n, 16.0 * k * n + 8.0 * k * k, "f64"),

@@ -52,7 +52,7 @@ __device__ __forceinline__ void gemm_tile(
     const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
     const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
     const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int bx, int by,
-    int bz, int acol0 = 0, int csub = 0, int blower = 0) {
+    int bz, int acol0 = 0, int csub = 0, int blower = 0, int mirror = 0) {
   constexpr bool AK = (OA == OpA::LvT);  // A operand contiguous along K
   constexpr bool BKC = true;             // B operands are contiguous along K
   typedef Tile<BM, BN, BK, WM, WN, AK, BKC, NBUF> Tl;
@@ -205,6 +205,10 @@ __device__ __forceinline__ void gemm_tile(
           const TO val = (TO)acc[a][b][v];
           if (ksplit > 1) {
             partial[(int64_t)bz * M * N + gi + gj * M] = val;
+            if (mirror) partial[(int64_t)bz * M * N + gj + gi * M] = val;
+          } else if (mirror) {
+            C[gi + gj * ldc] = val;
+            C[gj + gi * ldc] = val;
           } else {
             const int64_t oi = rowmap ? (int64_t)rowmap[gi] : gi;
             if (csub) C[oi + gj * ldc] -= val;
@@ -234,17 +238,30 @@ gemm_kernel(int64_t M, int64_t N, int64_t K, const TA* __restrict__ A, int64_t l
             const int* __restrict__ astep, const TB* __restrict__ B, int64_t ldb,
             const int* __restrict__ bstep, TO* __restrict__ C, int64_t ldc,
             const int* __restrict__ rowmap, int ksplit, TO* __restrict__ partial, int tm, int tn,
-            int nfast, int acol0, int csub, int blower) {
+            int nfast, int acol0, int csub, int blower, int sym) {
   const int t = xcd_chunked((int)blockIdx.x, (int)gridDim.x);
   int bx, by, bz;
-  if (nfast) {
+  if (sym) {
+    // a symmetric product (tm == tn): tile u of a split is the u-th tile on
+    // or below the diagonal, row by row
+    const int ntri = tm * (tm + 1) / 2;
+    bz = t / ntri;
+    const int u = t % ntri;
+    int row = 0, first = 0;  // first: index of tile (row, 0)
+    while (first + row + 1 <= u) {
+      first += row + 1;
+      ++row;
+    }
+    bx = row;
+    by = u - first;
+  } else if (nfast) {
     by = t % tn; const int rest = t / tn; bx = rest % tm; bz = rest / tm;
   } else {
     bx = t % tm; const int rest = t / tm; by = rest % tn; bz = rest / tn;
   }
   gemm_tile<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>(
       M, N, K, A, lda, astep, B, ldb, bstep, C, ldc, rowmap, ksplit, partial, bx, by, bz, acol0,
-      csub, blower);
+      csub, blower, sym && bx != by ? 1 : 0);
 }
 
 // Many independent products in one launch: workgroup b computes the tile
@@ -375,14 +392,16 @@ template <typename TA, typename TB, typename TC, typename TO, int BM, int BN, in
           int WN, int NBUF, OpA OA, OpB OB>
 hipError_t launch_cfg(const GemmDesc& d, int ksplit, hipStream_t s) {
   const int tm = (int)((d.M + BM - 1) / BM), tn = (int)((d.N + BN - 1) / BN);
-  const int64_t nb = (int64_t)tm * tn * ksplit;
+  // a symmetric product computes the tiles on and below the diagonal only
+  const int sym = d.sym && BM == BN && d.M == d.N && !d.rowmap && !d.csub ? 1 : 0;
+  const int64_t nb = sym ? (int64_t)tm * (tm + 1) / 2 * ksplit : (int64_t)tm * tn * ksplit;
   if (nb >= (1LL << 31)) return hipErrorInvalidValue;
   const int nfast = d.M > d.N ? 1 : 0;  // A is the larger operand
   hipLaunchKernelGGL((gemm_kernel<TA, TB, TC, TO, BM, BN, BK, WM, WN, NBUF, OA, OB>),
                      dim3((unsigned)nb), dim3(64 * WM * WN), 0, s, d.M, d.N, d.K, (const TA*)d.A,
                      d.lda, d.astep, (const TB*)d.B, d.ldb, d.bstep, (TO*)d.C, d.ldc, d.rowmap,
                      ksplit, (TO*)d.partial, tm, tn, nfast, d.acol0, d.csub ? 1 : 0,
-                     d.b_lower ? 1 : 0);
+                     d.b_lower ? 1 : 0, sym);
   return hipGetLastError();
 }
 

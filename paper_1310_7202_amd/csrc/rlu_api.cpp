@@ -551,6 +551,7 @@ rlu_status_t factor_path(rlu_handle_s* h, const rlu_problem_t& pb, const rlu_buf
     d.A = Y; d.lda = m; d.opa = OpA::LvT; d.astep = rstep_y;
     d.B = Y; d.ldb = m; d.opb = OpB::Lv; d.bstep = rstep_y;
     d.C = S; d.ldc = k;
+    d.sym = true;  // S = Lv^T Lv
     d.ksplit = 0; d.partial = at<void>(ws, Ly.part);
     PhaseScope ph(h, PH_GRAM, s);
     HIP_TRY(launch_gemm<double>(d, s));

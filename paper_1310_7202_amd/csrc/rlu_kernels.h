@@ -55,6 +55,9 @@ struct GemmDesc {
   bool csub;           // C -= op(A) op(B) instead of C = ... (requires ksplit 1)
   bool b_lower;        // op(B) is lower triangular (B(t, j) = 0 for t < j): a tile
                        // skips the K slices above its first column
+  bool sym;            // C is symmetric (M == N, op(A) = op(B)^T): only the tiles on
+                       // and below the diagonal are computed, each also written to
+                       // its mirror image (square tiles, no rowmap or csub)
   void* lp_ws;         // low-precision products: room for the pre-converted small
                        // operand (stream_sketch_ws_bytes / stream_project_ws_bytes)
   const unsigned* amax;  // FP16 products: max|A| (FP32 bits) for the range scale of A
