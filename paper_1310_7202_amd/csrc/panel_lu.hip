@@ -12,8 +12,7 @@
 // rows fit one workgroup's registers; both make the same choices and give
 // the same bits.
 //
-// Design of the spread kernel (one persistent cooperative launch, no host
-// round trip):
+// Design of the spread kernel (one persistent launch, no host round trip):
 //   * workgroup w keeps rows [w R, (w+1) R) of X resident in LDS for the whole
 //     factorization; rows never move ("virtual" pivoting): each row records
 //     its current position (to reproduce LAPACK's swap bookkeeping and its
@@ -1073,13 +1072,15 @@ hipError_t launch_panel_lu(const PanelDesc& d, const PanelPlan& plan, hipStream_
                             : (const void*)panel_lu_kernel<8>;
   e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds_bytes);
   if (e != hipSuccess) return e;
-  // the pivot exchange needs every workgroup resident at once (cooperative
-  // launch); a single workgroup exchanges through LDS and needs no guarantee
-  if (nwg == 1)
-    return hipLaunchKernel(fn, dim3(1), dim3(threads_for_rows(R)), args, (unsigned)plan.lds_bytes,
-                           s);
-  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(threads_for_rows(R)), args,
-                                    (unsigned)plan.lds_bytes, s);
+  // The pivot exchange needs every workgroup resident at once.  An ordinary
+  // launch gives that here: the grid is at most one workgroup per CU (the
+  // plan's bound, and the LDS footprint allows no more per CU), the stream
+  // runs it alone after the work before it, and every wait is bounded, so
+  // a workgroup that starts late (work of other streams holding CUs) only
+  // delays its partners, and one that cannot start ends the factorization
+  // with the exchange-failure status rather than a hang.
+  return hipLaunchKernel(fn, dim3(nwg), dim3(threads_for_rows(R)), args, (unsigned)plan.lds_bytes,
+                         s);
 }
 
 int64_t panel_rec_stride(int ncols) { return rec_stride_for(ncols); }

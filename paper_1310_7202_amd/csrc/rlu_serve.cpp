@@ -224,8 +224,8 @@ bool rlu_server_s::launch_one(std::unique_lock<std::mutex>& lk) {
   }
   if (solo) {
     // the single-problem path keeps every workgroup busy in its pivoted LUs
-    // and uses cooperative launches: order it after the last panel launch
-    // and make the next one wait for all of it
+    // (persistent launches that need all their workgroups resident): order
+    // it after the last panel launch and make the next one wait for all of it
     if (st == RLU_OK && hipStreamWaitEvent(s, gate, 0) != hipSuccess) st = RLU_ERR_DEVICE;
     if (st == RLU_OK) st = rlu_factor(solo_h[sidx], &pbs[0], &ios[0], s);
     if (st == RLU_OK && hipEventRecord(gate, s) != hipSuccess) st = RLU_ERR_DEVICE;
