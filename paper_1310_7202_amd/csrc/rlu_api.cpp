@@ -250,16 +250,23 @@ rlu_status_t begin_timing(rlu_handle_s* h) {
   h->cur = nullptr;
   if (!h->timing) return RLU_OK;
   TimingSlot& t = h->ring[h->ring_next];
+  // timing-only events: no system-scope fence (cache write-back and
+  // invalidation) when they are recorded, which would idle the device for
+  // several microseconds at every event; they are only read for their
+  // timestamps after the call
+  auto mk = [](hipEvent_t* e) {
+    return hipEventCreateWithFlags(e, hipEventDisableSystemFence) == hipSuccess;
+  };
   for (int p = 0; p < PH_COUNT; ++p) {
     for (int e = 0; e < 2; ++e)
-      if (!t.ev[p][e] && hipEventCreate(&t.ev[p][e]) != hipSuccess) return RLU_ERR_DEVICE;
+      if (!t.ev[p][e] && !mk(&t.ev[p][e])) return RLU_ERR_DEVICE;
     t.used[p] = false;
   }
   t.nk = 0;
   if (h->timing_mode == 3)
     for (int k = 0; k < kMaxKernelTimes; ++k)
       for (int e = 0; e < 2; ++e)
-        if (!t.kev[k][e] && hipEventCreate(&t.kev[k][e]) != hipSuccess) return RLU_ERR_DEVICE;
+        if (!t.kev[k][e] && !mk(&t.kev[k][e])) return RLU_ERR_DEVICE;
   t.valid = true;
   h->cur = &t;
   h->ring_next = (h->ring_next + 1) % RLU_TIMING_RING;
