@@ -53,7 +53,12 @@
  * one stream at a time: its workspace (Y, the Gram matrix, the pivot
  * exchange area, the split-K partials) is reused by every call, and nothing
  * orders calls on different streams, so a caller that switches streams
- * must order the calls itself (or use one handle per stream).
+ * must order the calls itself (or use one handle per stream).  A pivoted
+ * LU spread over workgroups needs all of them resident at once (at most one
+ * per CU, 128 by default); calls on several streams at once share the CUs,
+ * and if their pivoted LUs together leave one without its workgroups, its
+ * waits reach their time limit and the call reports the exchange failure
+ * (info[2] bit 0) instead of hanging.
  *
  * Environment (tuning and tests; results are the same bits either way):
  *   RLU_PANEL_WG_CAP  16..256, read once per process: the most workgroups
