@@ -1134,7 +1134,7 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
 // the U rows of the block's pivots for the columns to its right,
 //   L11 U12 = X(pr, c1:),   L11(j, i) = X(pr_j, c0 + i) for i < j (unit lower),
 // with pr_j = piv_row[j] the row chosen at step c0 + j.  Workgroup b solves
-// 32 right-hand-side columns with U12 in LDS, 16 rows at a time: the 16 rows
+// 16 right-hand-side columns with U12 in LDS, 16 rows at a time: the 16 rows
 // of L11 the step needs are first gathered into LDS by all threads, beside
 // their right-hand sides (the solve's dependency chain then only touches
 // LDS and registers), then the product with the rows already solved by all
@@ -1143,7 +1143,12 @@ hipError_t launch_panel_lu_batched(const PanelTaskDev* tasks, const int* sched, 
 // dimension w).
 // ---------------------------------------------------------------------------
 constexpr int kTrsmMaxW = 288;
-constexpr int kTrsmCols = 32;
+// Right-hand-side columns per workgroup: 16 (one per thread of a row) gives
+// twice the workgroups of 32 on the narrow solves between column blocks
+// and halves each one's product with the rows already solved (its LDS
+// reads dominate a chunk once many rows are solved).
+constexpr int kTrsmCols = 16;
+constexpr int kTrsmQ = kTrsmCols / 16;  // columns per thread
 
 __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restrict__ X, int64_t ldx,
                                                          const int* __restrict__ piv_row, int c0,
@@ -1155,17 +1160,19 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restric
   __shared__ int prow_s[16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int cc0 = kTrsmCols * blockIdx.x;
-  const int jj = tid >> 4, cg = tid & 15;  // a row of the block, two columns (cg, cg + 16)
+  const int jj = tid >> 4, cg = tid & 15;  // a row of the block, columns cg + 16 q
   for (int J0 = 0; J0 < w; J0 += 16) {
     const int h = min(16, w - J0), len = J0 + h;
     if (tid < h) prow_s[tid] = piv_row[J0 + tid];
     __syncthreads();
     // this chunk's right-hand sides, loaded beside the L11 rows
-    double acc[2] = {0.0, 0.0};
+    double acc[kTrsmQ];
+#pragma unroll
+    for (int q = 0; q < kTrsmQ; ++q) acc[q] = 0.0;
     if (jj < h) {
       const int64_t prow = prow_s[jj];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < kTrsmQ; ++q) {
         const int c = cc0 + cg + 16 * q;
         acc[q] = c < nrhs ? X[prow + (c1 + c) * ldx] : 0.0;
       }
@@ -1180,20 +1187,22 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const double* __restric
       // per output over i mod 4, so that four multiply-add chains run side by
       // side, added in a fixed order
       const double* lr = Ls + jj * w;
-      double part[4][2];
+      double part[4][kTrsmQ];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) part[t][0] = part[t][1] = 0.0;
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int q = 0; q < kTrsmQ; ++q) part[t][q] = 0.0;
       for (int i = 0; i < J0; i += 4) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           const double l = lr[i + t];
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
+          for (int q = 0; q < kTrsmQ; ++q)
             part[t][q] = __fma_rn(-l, Us[(i + t) * kTrsmCols + cg + 16 * q], part[t][q]);
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < kTrsmQ; ++q)
         Us[(J0 + jj) * kTrsmCols + cg + 16 * q] =
             acc[q] + ((part[0][q] + part[1][q]) + (part[2][q] + part[3][q]));
     }
