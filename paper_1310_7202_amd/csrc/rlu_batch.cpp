@@ -102,11 +102,17 @@ struct Plan {
 constexpr size_t kPanelLdsBudget = 159 * 1024;
 
 int panel_rows_for(int ncols) {
-  for (int r = 512; r >= 64; --r)
-    if (panel_lds_bytes(r, ncols) <= kPanelLdsBudget &&
-        (size_t)8 * ((size_t)(ncols - 1) * r + 512) <= kPanelLdsBudget)
-      return r;
-  return 0;
+  if (ncols < 1) return 0;
+  // the largest r with panel_lds_bytes(r, c) = 8 (r c + 5 c + r) and the
+  // margin 8 ((c - 1) r + 512) both within the budget
+  const int64_t b8 = (int64_t)(kPanelLdsBudget / 8), c = ncols;
+  int64_t r = 512;
+  r = std::min(r, b8 >= 5 * c ? (b8 - 5 * c) / (c + 1) : 0);
+  if (c > 1) r = std::min(r, (b8 - 512) / (c - 1));
+  if (r < 64) return 0;
+  // the closed form restates panel_lds_bytes; keep the two in step
+  if (panel_lds_bytes((int)r, ncols) > kPanelLdsBudget) return 0;
+  return (int)r;
 }
 
 // Tile shape of a grouped product: a handle override, else the tuned table,
